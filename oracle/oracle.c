@@ -1,0 +1,768 @@
+/*
+ * CPU ORACLE for the traffic microsimulation step -- test infrastructure only.
+ *
+ * Plain, slow, obviously-correct C.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it; the product library never
+ * does.  It shares no code, header, table or constant generator with the HIP
+ * path.  The same source is compiled twice: -DORACLE_F64 gives the FP64
+ * oracle, without it the FP32 oracle.  Build flags: -O2 -ffp-contract=off
+ * -fno-fast-math (no FMA contraction, IEEE round-to-nearest-even).
+ *
+ * What it computes (one synchronous step t -> t+1; every decision reads
+ * state t only):
+ *   - car following: the Intelligent Driver Model of Sec. 6.3.2
+ *     (the car-following equation, exponent 4, v0 = desired speed of the
+ *     link, s = gap to the vehicle ahead);
+ *   - lane changes, mandatory or discretionary, each subject to gap
+ *     acceptance (Sec. 6.3.2, lane-changing and gap-acceptance items);
+ *   - route traversal: every vehicle follows its precomputed edge list from
+ *     origin to destination (Sec. 6.2.1, Sec. 6.3.1) with time step dt
+ *     (Sec. 6.3.2, dt = 0.5 s);
+ *   - departures from per-trip departure steps (Sec. 6.2.2);
+ *   - per-link traversal statistics (Sec. 6.4).
+ * Where the paper is silent the readings are the documented ones: ballistic
+ * integration, MOBIL incentive for discretionary changes, a distance
+ * threshold for the mandatory state, one-metre claim cells with the
+ * lowest-vehicle-id-wins rule for merges, lane changes and insertions.
+ *
+ * Parity: pinned by closed forms (free-road acceleration from rest, ring-road
+ * equilibrium), invariants (conservation, no overlap within a lane) and an
+ * independent brute-force implementation on tiny networks.  The lane-choice
+ * and intersection behaviour beyond those invariants is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_F64
+typedef double real;
+#define RFLOOR floor
+#define RRINT rint
+#else
+typedef float real;
+#define RFLOOR floorf
+#define RRINT rintf
+#endif
+
+#define RMAX(a, b) ((a) > (b) ? (a) : (b))
+#define RMIN(a, b) ((a) < (b) ? (a) : (b))
+#define LC_NONE (-(1 << 30))
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_EROUTE = -2, OR_ENOMEM = -3, OR_ESTATE = -5 };
+enum { K_STAY = 0, K_ARRIVE = 1, K_CROSS = 2, K_CHANGE = 3 };
+
+typedef struct {
+    int32_t vid, edge, lane, rcur, next, lc, kin;
+    real x, v, phin;
+} veh_t;
+
+typedef struct {
+    /* network */
+    int32_t nn, ne, nlanes;
+    int32_t *row_ptr, *col_idx, *lanes, *cls, *lane_base, *ncell;
+    real *len, *inv_v0;
+    /* parameters */
+    int32_t ncls, lc_cool;
+    real dt, h, lveh, s0, claim_len, s_eps, b_max, p, athr, bsafe, dmand, dt_us_f;
+    int64_t dt_us;
+    real *T, *A, *kab;
+    /* demand, indexed by vehicle id */
+    int32_t ntrips, loaded;
+    int32_t *dep, *rbeg, *rend, *route_edges;
+    int64_t nroute_edges;
+    int32_t *depart_actual, *arrive_step;
+    /* state */
+    int32_t t, nact, npend, relc;
+    veh_t* act;
+    int32_t* pend;
+    int64_t *st_cnt, *st_steps, *st_us;
+    int64_t departed, arrived, updates, claims_lost, clamps;
+} osim;
+
+/* ------------------------------------------------------------------------ */
+/* creation: derived constants are computed once in double from the inputs
+ * and rounded once to `real`. */
+osim* or_create(int32_t nn, int32_t ne, const int32_t* row_ptr, const int32_t* col_idx,
+                const int32_t* lanes, const float* length, const float* speed,
+                const int32_t* link_class, int32_t ncls, const float* idm,
+                const float* fp, int32_t lc_cool, int32_t* err) {
+    *err = OR_EINVAL;
+    if (nn <= 0 || ne <= 0 || ncls <= 0) return NULL;
+    if (row_ptr[0] != 0 || row_ptr[nn] != ne) return NULL;
+    osim* S = (osim*)calloc(1, sizeof(osim));
+    S->nn = nn; S->ne = ne; S->ncls = ncls; S->lc_cool = lc_cool;
+    S->row_ptr = (int32_t*)malloc(sizeof(int32_t) * (nn + 1));
+    memcpy(S->row_ptr, row_ptr, sizeof(int32_t) * (nn + 1));
+    S->col_idx = (int32_t*)malloc(sizeof(int32_t) * ne);
+    S->lanes = (int32_t*)malloc(sizeof(int32_t) * ne);
+    S->cls = (int32_t*)malloc(sizeof(int32_t) * ne);
+    S->lane_base = (int32_t*)malloc(sizeof(int32_t) * (ne + 1));
+    S->ncell = (int32_t*)malloc(sizeof(int32_t) * ne);
+    S->len = (real*)malloc(sizeof(real) * ne);
+    S->inv_v0 = (real*)malloc(sizeof(real) * ne);
+    S->T = (real*)malloc(sizeof(real) * ncls);
+    S->A = (real*)malloc(sizeof(real) * ncls);
+    S->kab = (real*)malloc(sizeof(real) * ncls);
+    S->dt = (real)fp[0];
+    S->lveh = (real)fp[1];
+    S->s0 = (real)fp[2];
+    S->s_eps = (real)fp[3];
+    S->b_max = (real)fp[4];
+    S->p = (real)fp[5];
+    S->athr = (real)fp[6];
+    S->bsafe = (real)fp[7];
+    S->dmand = (real)fp[8];
+    S->h = (real)(0.5 * (double)fp[0] * (double)fp[0]);
+    S->claim_len = (real)((double)fp[1] + (double)fp[2]);
+    S->dt_us = llround((double)fp[0] * 1e6);
+    S->dt_us_f = (real)((double)fp[0] * 1e6);
+    for (int c = 0; c < ncls; ++c) {
+        double a = idm[4 * c + 2], b = idm[4 * c + 3];
+        if (!(a > 0) || !(b > 0) || !(idm[4 * c + 0] > 0) || !(idm[4 * c + 1] >= 0)) goto bad;
+        S->T[c] = (real)idm[4 * c + 1];
+        S->A[c] = (real)a;
+        S->kab[c] = (real)(1.0 / (2.0 * sqrt(a * b)));
+    }
+    S->lane_base[0] = 0;
+    for (int32_t e = 0; e < ne; ++e) {
+        int32_t c = link_class ? link_class[e] : 0;
+        if (c < 0 || c >= ncls || lanes[e] < 1 || lanes[e] > 8 || !(speed[e] > 0) ||
+            !(length[e] >= fp[1] + fp[2]) || col_idx[e] < 0 || col_idx[e] >= nn)
+            goto bad;
+        S->col_idx[e] = col_idx[e];
+        S->lanes[e] = lanes[e];
+        S->cls[e] = c;
+        S->len[e] = (real)length[e];
+        S->inv_v0[e] = (real)(1.0 / ((double)idm[4 * c + 0] * (double)speed[e]));
+        S->ncell[e] = (int32_t)floor((double)length[e]) + 1;
+        S->lane_base[e + 1] = S->lane_base[e] + lanes[e];
+    }
+    S->nlanes = S->lane_base[ne];
+    *err = OR_OK;
+    return S;
+bad:
+    *err = OR_EINVAL;
+    free(S->row_ptr); free(S->col_idx); free(S->lanes); free(S->cls); free(S->lane_base);
+    free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab); free(S);
+    return NULL;
+}
+
+void or_destroy(osim* S) {
+    if (!S) return;
+    free(S->row_ptr); free(S->col_idx); free(S->lanes); free(S->cls); free(S->lane_base);
+    free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab);
+    free(S->dep); free(S->rbeg); free(S->rend); free(S->route_edges);
+    free(S->depart_actual); free(S->arrive_step); free(S->act); free(S->pend);
+    free(S->st_cnt); free(S->st_steps); free(S->st_us);
+    free(S);
+}
+
+/* ------------------------------------------------------------------------ */
+/* demand: vehicle id = rank of the trip by (departure step, trip index).   */
+static const int32_t* g_sort_dep;
+static int cmp_trip(const void* a, const void* b) {
+    int32_t i = *(const int32_t*)a, j = *(const int32_t*)b;
+    if (g_sort_dep[i] != g_sort_dep[j]) return g_sort_dep[i] < g_sort_dep[j] ? -1 : 1;
+    return (i > j) - (i < j);
+}
+
+static int32_t tail_of(const osim* S, int32_t e) {
+    int32_t lo = 0, hi = S->nn; /* largest node u with row_ptr[u] <= e */
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) / 2;
+        if (S->row_ptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+static int32_t lane_key(const osim* S, int32_t e, int32_t l) { return S->lane_base[e] + l; }
+
+/* order used for lanes: (lane key, x, vehicle id) */
+static const osim* g_S;
+static const veh_t* g_act;
+static int cmp_order(const void* a, const void* b) {
+    const veh_t* u = &g_act[*(const int32_t*)a];
+    const veh_t* w = &g_act[*(const int32_t*)b];
+    int32_t ku = lane_key(g_S, u->edge, u->lane), kw = lane_key(g_S, w->edge, w->lane);
+    if (ku != kw) return ku < kw ? -1 : 1;
+    if (u->x != w->x) return u->x < w->x ? -1 : 1;
+    return (u->vid > w->vid) - (u->vid < w->vid);
+}
+
+int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const int32_t* trip_route,
+                   int32_t nroutes, const int64_t* route_ptr, const int32_t* route_edges,
+                   const float* init_x, const float* init_v, const int32_t* init_lane) {
+    if (S->loaded) return OR_ESTATE;
+    if (ntrips < 0 || nroutes < 0 || (ntrips > 0 && nroutes == 0)) return OR_EINVAL;
+    if (route_ptr[0] != 0) return OR_EROUTE;
+    int64_t nre = route_ptr[nroutes];
+    if (nre < 0 || nre > INT32_MAX - 2) return OR_EROUTE;
+    for (int32_t r = 0; r < nroutes; ++r) {
+        if (route_ptr[r + 1] <= route_ptr[r]) return OR_EROUTE;
+        for (int64_t k = route_ptr[r]; k < route_ptr[r + 1]; ++k) {
+            int32_t e = route_edges[k];
+            if (e < 0 || e >= S->ne) return OR_EROUTE;
+            if (k + 1 < route_ptr[r + 1] && S->col_idx[e] != tail_of(S, route_edges[k + 1])) return OR_EROUTE;
+        }
+    }
+    for (int32_t i = 0; i < ntrips; ++i) {
+        if (trip_route[i] < 0 || trip_route[i] >= nroutes) return OR_EINVAL;
+        if (depart_step[i] < S->t) return OR_ESTATE;
+        if (init_x && depart_step[i] != S->t) return OR_EINVAL;
+    }
+    int32_t* ord = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    for (int32_t i = 0; i < ntrips; ++i) ord[i] = i;
+    g_sort_dep = depart_step;
+    qsort(ord, ntrips, sizeof(int32_t), cmp_trip);
+    S->ntrips = ntrips;
+    S->dep = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->rbeg = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->rend = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->depart_actual = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->arrive_step = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->nroute_edges = nre;
+    S->route_edges = (int32_t*)malloc(sizeof(int32_t) * (nre + 1));
+    memcpy(S->route_edges, route_edges, sizeof(int32_t) * nre);
+    for (int32_t v = 0; v < ntrips; ++v) {
+        int32_t i = ord[v];
+        S->dep[v] = depart_step[i];
+        S->rbeg[v] = (int32_t)route_ptr[trip_route[i]];
+        S->rend[v] = (int32_t)route_ptr[trip_route[i] + 1];
+        S->depart_actual[v] = -1;
+        S->arrive_step[v] = -1;
+    }
+    S->act = (veh_t*)malloc(sizeof(veh_t) * (ntrips + 1));
+    S->pend = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->st_cnt = (int64_t*)calloc(S->ne, sizeof(int64_t));
+    S->st_steps = (int64_t*)calloc(S->ne, sizeof(int64_t));
+    S->st_us = (int64_t*)calloc(S->ne, sizeof(int64_t));
+    S->nact = 0;
+    S->npend = 0;
+    if (init_x) {
+        /* placed vehicles enter state t directly, without a claim */
+        for (int32_t v = 0; v < ntrips; ++v) {
+            int32_t i = ord[v];
+            veh_t* q = &S->act[v];
+            q->vid = v;
+            q->rcur = S->rbeg[v];
+            q->edge = S->route_edges[q->rcur];
+            q->next = (q->rcur + 1 < S->rend[v]) ? S->route_edges[q->rcur + 1] : -1;
+            q->lane = init_lane ? init_lane[i] : 0;
+            q->x = (real)init_x[i];
+            q->v = init_v ? (real)init_v[i] : (real)0;
+            q->lc = LC_NONE;
+            q->kin = S->t;
+            q->phin = (real)1;
+            if (q->lane < 0 || q->lane >= S->lanes[q->edge] || !(init_x[i] >= 0) ||
+                !(init_x[i] <= (float)S->len[q->edge]) || (init_v && !(init_v[i] >= 0))) {
+                free(ord);
+                return OR_EINVAL;
+            }
+        }
+        S->nact = ntrips;
+        /* no overlap within a lane */
+        int32_t* o = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+        for (int32_t k = 0; k < ntrips; ++k) o[k] = k;
+        g_S = S; g_act = S->act;
+        qsort(o, ntrips, sizeof(int32_t), cmp_order);
+        for (int32_t k = 0; k + 1 < ntrips; ++k) {
+            const veh_t *a = &S->act[o[k]], *b = &S->act[o[k + 1]];
+            if (a->edge == b->edge && a->lane == b->lane && ((b->x - S->lveh) - a->x) < 0) {
+                free(o); free(ord);
+                S->nact = 0;
+                return OR_EINVAL;
+            }
+        }
+        free(o);
+        for (int32_t v = 0; v < ntrips; ++v) S->depart_actual[v] = S->t;
+        S->departed = ntrips;
+    }
+    free(ord);
+    S->loaded = 1;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the car-following law and the kinematic update                             */
+typedef struct {
+    int kind;   /* 0 free road, 1 same link, 2 first vehicle of the next link */
+    real s;     /* bumper-to-bumper gap (m) */
+    real vl;    /* speed of the vehicle ahead */
+    real xl;    /* its front position on its own link */
+} lead_t;
+
+/* IDM acceleration (Sec. 6.3.2, car-following equation), with the dynamic
+ * part of the desired gap floored at 0, the gap floored at s_eps and the
+ * result floored at -b_max. */
+static real idm(const osim* S, int32_t c, real inv_v0, real v, lead_t L) {
+    real r = v * inv_v0;
+    real r2 = r * r;
+    real r4 = r2 * r2;
+    real fr = (real)1 - r4;
+    real acc;
+    if (L.kind == 0) {
+        acc = S->A[c] * fr;
+    } else {
+        real dv = v - L.vl;
+        real dyn = v * S->T[c] + (v * dv) * S->kab[c];
+        real ss = S->s0 + RMAX((real)0, dyn);
+        real q = ss / RMAX(L.s, S->s_eps);
+        acc = S->A[c] * (fr - q * q);
+    }
+    return RMAX(acc, -S->b_max);
+}
+
+/* Ballistic update over dt; when the speed would turn negative the vehicle
+ * stops within the step. */
+static void move(const osim* S, real v, real acc, real* dx, real* vn) {
+    real vv = v + acc * S->dt;
+    if (vv < (real)0) {
+        *dx = (v * v) / ((real)(-2) * acc);
+        *vn = (real)0;
+    } else {
+        *dx = v * S->dt + acc * S->h;
+        *vn = vv;
+    }
+    *dx = RMAX(*dx, (real)0);
+}
+
+/* never advance past the rear of the vehicle ahead */
+static int clampmv(lead_t L, real* dx, real* vn) {
+    if (L.kind != 0 && *dx > L.s) {
+        *dx = RMAX(L.s, (real)0);
+        *vn = RMIN(*vn, L.vl);
+        return 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* step                                                                        */
+typedef struct {
+    int kind;
+    real xs, vs;                 /* outcome if the vehicle keeps its place (or loses its claim) */
+    int32_t tkey, tedge, tlane;  /* claim target */
+    real X, vc, f;               /* front on the target, speed, crossing fraction */
+    int32_t lo, hi;              /* claim cells */
+    int clamped;
+} dec_t;
+
+typedef struct {
+    int32_t key, lo, hi, vid, src; /* src: index into the ordered vehicles, or -1-k for insert k */
+    int win;
+} claim_t;
+
+static int cmp_claim(const void* a, const void* b) {
+    const claim_t *u = (const claim_t*)a, *w = (const claim_t*)b;
+    if (u->key != w->key) return u->key < w->key ? -1 : 1;
+    return (u->vid > w->vid) - (u->vid < w->vid);
+}
+
+static void claim_cells(const osim* S, int32_t edge, real X, int32_t* lo, int32_t* hi) {
+    int32_t a = (int32_t)RFLOOR(X - S->claim_len);
+    int32_t b = (int32_t)RFLOOR(X);
+    *lo = a < 0 ? 0 : a;
+    *hi = b > S->ncell[edge] - 1 ? S->ncell[edge] - 1 : b;
+}
+
+typedef struct {
+    const osim* S;
+    const veh_t* act;
+    const int32_t* ord;   /* ordered position -> index in act */
+    const int32_t* first; /* lane key -> ordered position of its rearmost vehicle, or -1 */
+    const int32_t* cnt;   /* lane key -> number of vehicles */
+} view_t;
+
+static const veh_t* at(const view_t* W, int32_t o) { return &W->act[W->ord[o]]; }
+
+/* vehicle ahead on lane key k of link e for a vehicle at x (strictly ahead),
+ * else the rearmost vehicle of lane min(l, lanes-1) of the next link. */
+static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_t next, int32_t l) {
+    const osim* S = W->S;
+    lead_t L = {0, 0, 0, 0};
+    int32_t f = W->first[k], n = W->cnt[k];
+    for (int32_t j = 0; j < n; ++j) {
+        const veh_t* q = at(W, f + j);
+        if (q->x > x) {
+            L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x;
+            return L;
+        }
+    }
+    if (next >= 0) {
+        int32_t l2 = l < S->lanes[next] - 1 ? l : S->lanes[next] - 1;
+        int32_t k2 = lane_key(S, next, l2);
+        if (W->cnt[k2] > 0) {
+            const veh_t* q = at(W, W->first[k2]);
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (S->len[e] - x) + (q->x - S->lveh);
+        }
+    }
+    return L;
+}
+
+/* the same vehicle ahead, seen from another vehicle at xf on the same link */
+static lead_t relead(const osim* S, int32_t e, lead_t L, real xf) {
+    lead_t R = L;
+    if (L.kind == 1) R.s = (L.xl - S->lveh) - xf;
+    else if (L.kind == 2) R.s = (S->len[e] - xf) + (L.xl - S->lveh);
+    return R;
+}
+
+static dec_t decide(const view_t* W, int32_t o) {
+    const osim* S = W->S;
+    const veh_t* me = at(W, o);
+    int32_t e = me->edge, l = me->lane, c = S->cls[e], k = lane_key(S, e, l);
+    real len = S->len[e], iv = S->inv_v0[e], x = me->x, v = me->v;
+    dec_t D;
+    memset(&D, 0, sizeof(D));
+
+    /* own leader: the next vehicle of this lane, else look ahead one link */
+    lead_t L = {0, 0, 0, 0};
+    if (o + 1 < S->nact && lane_key(S, at(W, o + 1)->edge, at(W, o + 1)->lane) == k) {
+        const veh_t* q = at(W, o + 1);
+        L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x;
+    } else if (me->next >= 0) {
+        int32_t n2 = me->next;
+        int32_t l2 = l < S->lanes[n2] - 1 ? l : S->lanes[n2] - 1;
+        int32_t k2 = lane_key(S, n2, l2);
+        if (W->cnt[k2] > 0) {
+            const veh_t* q = at(W, W->first[k2]);
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (len - x) + (q->x - S->lveh);
+        }
+    }
+    real ac = idm(S, c, iv, v, L);
+    real dx, vn;
+    move(S, v, ac, &dx, &vn);
+    D.clamped = clampmv(L, &dx, &vn);
+    real xs = x + dx;
+    if (xs >= len) {
+        D.f = dx > (real)0 ? RMIN((len - x) / dx, (real)1) : (real)0;
+        if (me->next < 0) {
+            D.kind = K_ARRIVE;
+            return D;
+        }
+        int32_t n2 = me->next;
+        D.kind = K_CROSS;
+        D.tedge = n2;
+        D.tlane = l < S->lanes[n2] - 1 ? l : S->lanes[n2] - 1;
+        D.tkey = lane_key(S, n2, D.tlane);
+        D.X = xs - len;
+        D.vc = vn;
+        D.xs = len;
+        D.vs = (real)0;
+        claim_cells(S, n2, D.X, &D.lo, &D.hi);
+        return D;
+    }
+    D.kind = K_STAY;
+    D.xs = xs;
+    D.vs = vn;
+
+    /* lane change (Sec. 6.3.2): eligibility */
+    int32_t n = S->lanes[e];
+    if (n < 2 || (S->t - me->lc) < S->lc_cool || x < S->lveh) return D;
+    int32_t lo = 0, hi = n - 1;
+    if (me->next >= 0) {
+        int32_t hn = S->col_idx[e];
+        int32_t m = S->row_ptr[hn + 1] - S->row_ptr[hn];
+        int32_t j = me->next - S->row_ptr[hn];
+        lo = (j * n) / m;
+        hi = ((j + 1) * n + m - 1) / m - 1;
+        if (hi < lo) hi = lo;
+    }
+    real d = len - x;
+    int inband = lo <= l && l <= hi;
+    int mand = !inband && d <= S->dmand;
+    int32_t cand[2];
+    int nc = 0;
+    if (mand) {
+        cand[nc++] = l < lo ? l + 1 : l - 1;
+    } else {
+        for (int32_t s = l - 1; s <= l + 1; s += 2) {
+            if (s < 0 || s >= n) continue;
+            if (inband && d <= S->dmand && (s < lo || s > hi)) continue;
+            cand[nc++] = s;
+        }
+    }
+    /* follower in the own lane (same link) */
+    const veh_t* F = NULL;
+    if (o > 0 && lane_key(S, at(W, o - 1)->edge, at(W, o - 1)->lane) == k) F = at(W, o - 1);
+
+    int best = -1;
+    real best_inc = 0, best_X = 0, best_v = 0;
+    for (int ci = 0; ci < nc; ++ci) {
+        int32_t lt = cand[ci], kt = lane_key(S, e, lt);
+        lead_t Lt = lead_in_lane(W, e, kt, x, me->next, lt);
+        /* lag: last vehicle of the target lane with position <= x */
+        const veh_t* Ft = NULL;
+        for (int32_t j = 0; j < W->cnt[kt]; ++j) {
+            const veh_t* q = at(W, W->first[kt] + j);
+            if (q->x <= x) Ft = q; else break;
+        }
+        /* gap acceptance */
+        if (Lt.kind != 0 && Lt.s < S->s0) continue;
+        if (Ft && ((x - S->lveh) - Ft->x) < S->s0) continue;
+        real at_ = idm(S, c, iv, v, Lt);
+        if (at_ < -S->bsafe) continue;
+        real dxt, vt;
+        move(S, v, at_, &dxt, &vt);
+        clampmv(Lt, &dxt, &vt);
+        real Xt = x + dxt;
+        if (Xt >= len) continue;
+        real an = 0, ant = 0;
+        if (Ft) {
+            an = idm(S, c, iv, Ft->v, relead(S, e, Lt, Ft->x));
+            lead_t Li = {1, (x - S->lveh) - Ft->x, v, x};
+            ant = idm(S, c, iv, Ft->v, Li);
+            if (ant < -S->bsafe) continue;
+            lead_t none = {0, 0, 0, 0};
+            real afree = idm(S, c, iv, Ft->v, none);
+            real dxF, vF;
+            move(S, Ft->v, afree, &dxF, &vF);
+            if (((Xt - S->lveh) - Ft->x) < dxF) continue;
+        }
+        real inc = 0;
+        if (!mand) {
+            real d1 = at_ - ac;
+            real d2 = Ft ? (ant - an) : (real)0;
+            real d3 = (real)0;
+            if (F) {
+                lead_t Lo = {1, (x - S->lveh) - F->x, v, x};
+                real ao = idm(S, c, iv, F->v, Lo);
+                real aot = idm(S, c, iv, F->v, relead(S, e, L, F->x));
+                d3 = aot - ao;
+            }
+            inc = d1 + S->p * (d2 + d3);
+            if (!(inc > S->athr)) continue;
+        }
+        if (best < 0 || inc > best_inc) {
+            best = lt; best_inc = inc; best_X = Xt; best_v = vt;
+        }
+    }
+    if (best >= 0) {
+        D.kind = K_CHANGE;
+        D.tedge = e;
+        D.tlane = best;
+        D.tkey = lane_key(S, e, best);
+        D.X = best_X;
+        D.vc = best_v;
+        claim_cells(S, e, best_X, &D.lo, &D.hi);
+    }
+    return D;
+}
+
+static void record_exit(osim* S, const veh_t* q, real f, int32_t t) {
+    int64_t ns = (int64_t)(t + 1) - q->kin;
+    real frac = f - q->phin;
+    S->st_cnt[q->edge] += 1;
+    S->st_steps[q->edge] += ns;
+    S->st_us[q->edge] += ns * S->dt_us + (int64_t)RRINT(frac * S->dt_us_f);
+}
+
+static int step_once(osim* S) {
+    int32_t t = S->t, N = S->nact;
+    int32_t *ord = (int32_t*)malloc(sizeof(int32_t) * (N + 1));
+    int32_t *first = (int32_t*)malloc(sizeof(int32_t) * (S->nlanes + 1));
+    int32_t *cnt = (int32_t*)calloc(S->nlanes + 1, sizeof(int32_t));
+    for (int32_t i = 0; i < N; ++i) ord[i] = i;
+    g_S = S; g_act = S->act;
+    qsort(ord, N, sizeof(int32_t), cmp_order);
+    for (int32_t k = 0; k < S->nlanes; ++k) first[k] = -1;
+    for (int32_t o = 0; o < N; ++o) {
+        const veh_t* q = &S->act[ord[o]];
+        int32_t k = lane_key(S, q->edge, q->lane);
+        if (first[k] < 0) first[k] = o;
+        cnt[k] += 1;
+    }
+    view_t W = {S, S->act, ord, first, cnt};
+
+    /* 1. decisions of the vehicles on the road */
+    dec_t* D = (dec_t*)malloc(sizeof(dec_t) * (N + 1));
+    for (int32_t o = 0; o < N; ++o) D[o] = decide(&W, o);
+
+    /* 2. insertion candidates: waiting trips due now, in vehicle-id order */
+    int32_t ncand = S->npend;
+    int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (S->npend + S->ntrips + 1));
+    memcpy(cand, S->pend, sizeof(int32_t) * S->npend);
+    while (S->relc < S->ntrips && S->dep[S->relc] < t) S->relc += 1;
+    for (int32_t v = S->relc; v < S->ntrips && S->dep[v] == t; ++v)
+        if (S->depart_actual[v] < 0) cand[ncand++] = v;
+    int32_t* clane = (int32_t*)malloc(sizeof(int32_t) * (ncand + 1));
+
+    /* 3. claims */
+    claim_t* C = (claim_t*)malloc(sizeof(claim_t) * (N + ncand + 1));
+    int32_t nclaim = 0;
+    for (int32_t o = 0; o < N; ++o) {
+        if (D[o].kind == K_CROSS || D[o].kind == K_CHANGE) {
+            claim_t c = {D[o].tkey, D[o].lo, D[o].hi, at(&W, o)->vid, o, 0};
+            C[nclaim++] = c;
+        }
+    }
+    for (int32_t i = 0; i < ncand; ++i) {
+        int32_t v = cand[i];
+        int32_t e0 = S->route_edges[S->rbeg[v]];
+        int32_t best = -1;
+        real bsp = 0;
+        for (int32_t l = 0; l < S->lanes[e0]; ++l) {
+            int32_t k = lane_key(S, e0, l);
+            real sp = cnt[k] > 0 ? (at(&W, first[k])->x - S->lveh) : S->len[e0];
+            if (best < 0 || sp > bsp) { best = l; bsp = sp; }
+        }
+        clane[i] = -1;
+        if (bsp >= S->claim_len) {
+            clane[i] = best;
+            claim_t c;
+            c.key = lane_key(S, e0, best);
+            claim_cells(S, e0, S->lveh, &c.lo, &c.hi);
+            c.vid = v; c.src = -1 - i; c.win = 0;
+            C[nclaim++] = c;
+        }
+    }
+    /* a claim wins iff no overlapping claim on the same lane has a lower id */
+    qsort(C, nclaim, sizeof(claim_t), cmp_claim);
+    int32_t* cwin_veh = (int32_t*)calloc(N + 1, sizeof(int32_t));
+    int32_t* cwin_ins = (int32_t*)calloc(ncand + 1, sizeof(int32_t));
+    for (int32_t a = 0; a < nclaim;) {
+        int32_t b = a;
+        while (b < nclaim && C[b].key == C[a].key) ++b;
+        for (int32_t i = a; i < b; ++i) {
+            int win = 1;
+            for (int32_t j = a; j < b; ++j) {
+                if (C[j].vid < C[i].vid && C[j].lo <= C[i].hi && C[i].lo <= C[j].hi) { win = 0; break; }
+            }
+            C[i].win = win;
+            if (!win) S->claims_lost += 1;
+            if (C[i].src >= 0) cwin_veh[C[i].src] = win;
+            else cwin_ins[-1 - C[i].src] = win;
+        }
+        a = b;
+    }
+
+    /* 4. apply */
+    veh_t* nact = (veh_t*)malloc(sizeof(veh_t) * (N + ncand + 1));
+    int32_t nn = 0;
+    for (int32_t o = 0; o < N; ++o) {
+        veh_t q = *at(&W, o);
+        const dec_t* d = &D[o];
+        S->clamps += d->clamped;
+        if (d->kind == K_ARRIVE) {
+            record_exit(S, &q, d->f, t);
+            S->arrive_step[q.vid] = t + 1;
+            S->arrived += 1;
+            continue;
+        }
+        if (d->kind == K_CROSS && cwin_veh[o]) {
+            record_exit(S, &q, d->f, t);
+            q.rcur += 1;
+            q.edge = d->tedge;
+            q.lane = d->tlane;
+            q.next = (q.rcur + 1 < S->rend[q.vid]) ? S->route_edges[q.rcur + 1] : -1;
+            q.x = d->X;
+            q.v = d->vc;
+            q.kin = t + 1;
+            q.phin = d->f;
+        } else if (d->kind == K_CHANGE && cwin_veh[o]) {
+            q.lane = d->tlane;
+            q.x = d->X;
+            q.v = d->vc;
+            q.lc = t;
+        } else {
+            q.x = d->xs;
+            q.v = d->vs;
+        }
+        nact[nn++] = q;
+    }
+    int32_t np = 0;
+    for (int32_t i = 0; i < ncand; ++i) {
+        int32_t v = cand[i];
+        if (clane[i] >= 0 && cwin_ins[i]) {
+            veh_t q;
+            q.vid = v;
+            q.rcur = S->rbeg[v];
+            q.edge = S->route_edges[q.rcur];
+            q.lane = clane[i];
+            q.next = (q.rcur + 1 < S->rend[v]) ? S->route_edges[q.rcur + 1] : -1;
+            q.x = S->lveh;
+            q.v = (real)0;
+            q.lc = LC_NONE;
+            q.kin = t + 1;
+            q.phin = (real)1;
+            nact[nn++] = q;
+            S->depart_actual[v] = t + 1;
+            S->departed += 1;
+        } else {
+            S->pend[np++] = v;
+        }
+    }
+    S->npend = np;
+    S->updates += N;
+    free(S->act);
+    S->act = nact;
+    S->nact = nn;
+    S->t = t + 1;
+    free(ord); free(first); free(cnt); free(D); free(cand); free(clane); free(C);
+    free(cwin_veh); free(cwin_ins);
+    return OR_OK;
+}
+
+int or_step(osim* S, int32_t n) {
+    if (!S->loaded) return OR_ESTATE;
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = step_once(S);
+        if (rc) return rc;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* outputs                                                                     */
+/* counters: step, loaded, waiting, en_route, arrived, departed, vehicle_updates,
+ * claims_lost, clamps */
+void or_counters(const osim* S, int64_t* out) {
+    out[0] = S->t;
+    out[1] = S->ntrips;
+    out[2] = (int64_t)S->ntrips - S->departed;
+    out[3] = S->nact;
+    out[4] = S->arrived;
+    out[5] = S->departed;
+    out[6] = S->updates;
+    out[7] = S->claims_lost;
+    out[8] = S->clamps;
+}
+
+static int cmp_vid(const void* a, const void* b) {
+    const veh_t *u = (const veh_t*)a, *w = (const veh_t*)b;
+    return (u->vid > w->vid) - (u->vid < w->vid);
+}
+
+/* active vehicles sorted by vehicle id; ints: vid, edge, lane, cursor (index
+ * in the route), lc, kin; reals (as double): x, v, phin */
+int32_t or_get_vehicles(osim* S, int32_t* iv, double* rv) {
+    qsort(S->act, S->nact, sizeof(veh_t), cmp_vid);
+    for (int32_t i = 0; i < S->nact; ++i) {
+        const veh_t* q = &S->act[i];
+        iv[6 * i + 0] = q->vid;
+        iv[6 * i + 1] = q->edge;
+        iv[6 * i + 2] = q->lane;
+        iv[6 * i + 3] = q->rcur - S->rbeg[q->vid];
+        iv[6 * i + 4] = q->lc;
+        iv[6 * i + 5] = q->kin;
+        rv[3 * i + 0] = (double)q->x;
+        rv[3 * i + 1] = (double)q->v;
+        rv[3 * i + 2] = (double)q->phin;
+    }
+    return S->nact;
+}
+
+void or_get_trips(const osim* S, int32_t* depart_actual, int32_t* arrive_step) {
+    memcpy(depart_actual, S->depart_actual, sizeof(int32_t) * S->ntrips);
+    memcpy(arrive_step, S->arrive_step, sizeof(int32_t) * S->ntrips);
+}
+
+void or_get_edge_stats(const osim* S, int64_t* cnt, int64_t* steps, int64_t* us) {
+    memcpy(cnt, S->st_cnt, sizeof(int64_t) * S->ne);
+    memcpy(steps, S->st_steps, sizeof(int64_t) * S->ne);
+    memcpy(us, S->st_us, sizeof(int64_t) * S->ne);
+}
+
+int32_t or_num_active(const osim* S) { return S->nact; }
+int32_t or_num_pending(const osim* S) { return S->npend; }
