@@ -171,7 +171,7 @@ class Brute:
         dx, vn, clamped = self._clamp(L, dx, vn)
         xs = x + dx
         out = {"clamped": clamped}
-        if xs >= self.len[e]:
+        if xs > self.len[e]:  # the front passes the link end strictly
             f = min((self.len[e] - x) / dx, 1.0) if dx > 0.0 else 0.0
             if nxt < 0:
                 out.update(kind="arrive", f=f)

@@ -435,7 +435,7 @@ static dec_t decide(const view_t* W, int32_t o) {
     move(S, v, ac, &dx, &vn);
     D.clamped = clampmv(L, &dx, &vn);
     real xs = x + dx;
-    if (xs >= len) {
+    if (xs > len) { /* the front passes the link end strictly */
         D.f = dx > (real)0 ? RMIN((len - x) / dx, (real)1) : (real)0;
         if (me->next < 0) {
             D.kind = K_ARRIVE;

@@ -165,7 +165,9 @@ def check_invariants(o, scen, ntrips):
     k, x = key[order], V["x"][order].astype(np.float64)
     same = k[1:] == k[:-1]
     gaps = (x[1:] - lveh) - x[:-1]
-    assert np.all(gaps[same] >= 0), gaps[same].min()
+    # within a lane, consecutive vehicles never overlap (up to float rounding
+    # of the clamped position, far below a millimetre)
+    assert np.all(gaps[same] >= -1e-4), gaps[same].min()
     # every completed link traversal is accounted for
     d = scen["demand"]
     rl = np.diff(d["route_ptr"])[d["trip_route"]][S.sorted_trip_order(d["depart_step"])]
@@ -232,6 +234,7 @@ def test_brute_force_tiny_grids(seed):
         V = o.vehicles()
         common, ia, ib = np.intersect1d(prev["vid"], V["vid"], return_indices=True)
         lane_changes += int(np.sum((prev["edge"][ia] == V["edge"][ib]) & (prev["lane"][ia] != V["lane"][ib])))
+        check_invariants(o, scen, 60)
     for k, v in o.edge_stats().items():
         assert np.array_equal(v, b.edge_stats()[k])
     assert np.array_equal(o.trips()["arrive_step"], np.array(b.arrive_step))
