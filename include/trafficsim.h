@@ -1,0 +1,176 @@
+/*
+ * trafficsim.h -- C ABI of the MI355X traffic microsimulation library
+ * (libtrafficsim.so, HIP kernels for gfx950).
+ *
+ * The library advances a population of vehicles over a lane-level road network
+ * in synchronous time steps, as the GPU traffic microsimulator of Waddell et
+ * al., "Architecture for Modular Microsimulation of Real Estate Markets and
+ * Transportation", Sec. 6: every vehicle follows a precomputed route
+ * (Sec. 6.3.1) and is updated each step by lane changing and car following
+ * (Sec. 6.3.2, car-following equation = Intelligent Driver Model), with
+ * departures from per-trip departure times (Sec. 6.2.2) and per-link travel
+ * time statistics (Sec. 6.4).
+ *
+ * Conventions for every entry point:
+ *   - Return value: SIM_OK (0) or a negative SIM_E* code.  The library never
+ *     aborts; sim_last_error() names the offending item of the last failure.
+ *   - Host pointers are read during the call only (the caller may free them on
+ *     return).  Pointers documented as "device" must be device memory that is
+ *     valid on the handle's stream.
+ *   - All GPU work is enqueued on the handle's HIP stream.  Entry points that
+ *     return host data synchronise that stream first.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef TRAFFICSIM_H
+#define TRAFFICSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1, /* null pointer, size or value out of range, overlapping placement */
+    SIM_EROUTE = -2, /* empty route, edge id out of range, or consecutive edges not joined */
+    SIM_ENOMEM = -3, /* device allocation failed */
+    SIM_EHIP = -4,   /* a HIP runtime call failed; sim_last_error has hipGetErrorString */
+    SIM_ESTATE = -5  /* call not valid now (e.g. demand loaded twice, departure in the past) */
+};
+
+typedef struct sim_t sim_t;
+
+/* Device allocator hooks.  alloc returns device memory of `bytes` bytes (or
+ * NULL); free releases it.  Both NULL: the library uses hipMalloc/hipFree. */
+typedef void* (*sim_alloc_fn)(void* ctx, size_t bytes);
+typedef void (*sim_free_fn)(void* ctx, void* ptr);
+
+/* Road network (Sec. 6.2.1): directed multigraph in CSR form by tail node.
+ * Edge id == CSR position.  All arrays are HOST memory.
+ *   row_ptr   [num_nodes+1]  row_ptr[0] = 0, row_ptr[num_nodes] = num_edges
+ *   col_idx   [num_edges]    head node of each edge (self-loops allowed)
+ *   lanes     [num_edges]    1..8
+ *   length_m  [num_edges]    >= veh_length + s0
+ *   speed_mps [num_edges]    speed limit > 0; desired speed v0 = v0_scale[class]*speed
+ *   link_class[num_edges]    0..num_classes-1, or NULL (all class 0)            */
+typedef struct {
+    int32_t num_nodes, num_edges;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* lanes;
+    const float* length_m;
+    const float* speed_mps;
+    const int32_t* link_class;
+} sim_network;
+
+/* Model parameters.  dt: time step (s; Sec. 6.3.2 uses 0.5).  veh_length and
+ * s0 (minimum gap) in m.  idm: HOST [num_classes][4] = {v0_scale, T, a, b} of
+ * the car-following equation (Sec. 6.3.2), exponent fixed at 4.  s_eps floors
+ * the gap in the IDM interaction term; b_max floors the acceleration.  MOBIL
+ * politeness, threshold and safe braking for discretionary lane changes;
+ * mand_dist: distance to the link end below which a vehicle outside the lanes
+ * of its next turn changes lanes mandatorily (Sec. 6.3.2, lane changing);
+ * lc_cooldown_steps: minimum steps between two changes of one vehicle.      */
+typedef struct {
+    float dt, veh_length, s0, s_eps, b_max;
+    int32_t num_classes;
+    const float* idm;
+    float mobil_p, mobil_athr, mobil_bsafe, mand_dist;
+    int32_t lc_cooldown_steps;
+} sim_params;
+
+/* Counters (Sec. 6.4 outputs).  vehicle_updates = sum over completed steps of
+ * the vehicles on the road at the start of the step. */
+typedef struct {
+    int64_t step, loaded, waiting, en_route, arrived, departed;
+    int64_t vehicle_updates, claims_lost, clamps;
+    int64_t claims; /* claims issued (crossings, lane changes, insertions) */
+} sim_stats_t;
+
+/* Create a simulation of `net` with `params` on `hip_stream` (a hipStream_t,
+ * NULL = default stream).  Validates and copies the network; derived
+ * constants (1/v0 per edge, 1/(2 sqrt(ab)) per class, dt^2/2) are computed in
+ * double on the host and rounded once to float.  *out receives the handle.
+ * Errors: SIM_EINVAL (bad sizes/values, *out untouched), SIM_ENOMEM, SIM_EHIP. */
+int sim_create(const sim_network* net, const sim_params* params, void* hip_stream,
+               sim_alloc_fn alloc, sim_free_fn free_fn, void* alloc_ctx, sim_t** out);
+
+/* Load the trips (Sec. 6.2.2 departure times, Sec. 6.3.1 routes).  Once per
+ * handle.  HOST arrays:
+ *   depart_step [num_trips]   step at which the trip becomes due (>= current step)
+ *   trip_route  [num_trips]   route id per trip (routes may be shared)
+ *   route_ptr   [num_routes+1] offsets into route_edges (int64, total < 2^31)
+ *   route_edges [route_ptr[num_routes]]  consecutive edges must be joined
+ *   init_x/init_v/init_lane   NULL, or [num_trips] each: every trip is then
+ *                             placed on the first edge of its route at that
+ *                             position (front bumper, m), speed and lane, all
+ *                             with depart_step == current step, no overlap.
+ * Vehicle id = rank of the trip by (depart_step, trip index); lower ids win
+ * conflicting claims.  All-or-nothing: on error nothing is loaded.
+ * Errors: SIM_EINVAL, SIM_EROUTE, SIM_ESTATE (second call, departure in the
+ * past), SIM_ENOMEM, SIM_EHIP. */
+int sim_load_demand(sim_t* sim, int32_t num_trips, const int32_t* depart_step,
+                    const int32_t* trip_route, int32_t num_routes, const int64_t* route_ptr,
+                    const int32_t* route_edges, const float* init_x, const float* init_v,
+                    const int32_t* init_lane);
+
+/* Advance num_steps synchronous steps (Sec. 6.3.2: lane change, car following,
+ * position/speed/travel-time update per vehicle per dt).  Asynchronous: only
+ * enqueues kernels.  Errors: SIM_ESTATE (no demand), SIM_EINVAL, SIM_EHIP. */
+int sim_step(sim_t* sim, int32_t num_steps);
+
+/* Read counters into host_out (synchronises), and enqueue device-to-device
+ * copies of the per-edge statistics into the DEVICE arrays edge_count,
+ * edge_tt_steps (sum of whole steps spent on the edge) and edge_tt_us (sum of
+ * crossing-interpolated traversal times, microseconds), each [num_edges].
+ * Every pointer may be NULL. */
+int sim_stats(sim_t* sim, sim_stats_t* host_out, int64_t* edge_count, int64_t* edge_tt_steps,
+              int64_t* edge_tt_us);
+
+/* Copy the vehicles on the road to HOST arrays of capacity `cap` (in the
+ * library's lane order; synchronises).  *n_out = number on the road (if it
+ * exceeds cap nothing is copied and SIM_EINVAL is returned).  Any array may
+ * be NULL.  cursor = index of the current edge within the vehicle's route;
+ * lc = step of the last lane change; kin/phin = entry step / fraction. */
+int sim_read_vehicles(sim_t* sim, int32_t cap, int32_t* n_out, int32_t* vid, int32_t* edge,
+                      int32_t* lane, int32_t* cursor, int32_t* lc, int32_t* kin, float* x,
+                      float* v, float* phin);
+
+/* Copy per-vehicle-id outcomes to HOST arrays [num_trips]: the step at which the
+ * vehicle appeared on the road (-1 if not yet) and the first step after its
+ * arrival (-1 if not arrived).  Synchronises. */
+int sim_read_trips(sim_t* sim, int32_t* depart_actual, int32_t* arrive_step);
+
+/* Replace the IDM parameters (same num_classes) between steps; derived
+ * constants are recomputed as in sim_create.  Errors: SIM_EINVAL. */
+int sim_set_idm(sim_t* sim, const float* idm);
+
+/* Per-kernel timing with HIP events on the handle's stream: when every > 0,
+ * every `every`-th subsequent step records an event before and after each of
+ * its SIM_NUM_KERNELS kernel launches (decide, resolve, scan, scatter, place);
+ * 0 disables.  Timing adds no synchronisation to sim_step. */
+#define SIM_NUM_KERNELS 5
+int sim_set_timing(sim_t* sim, int32_t every);
+
+/* Synchronise, then add the elapsed milliseconds of every sampled launch to
+ * kernel_ms[SIM_NUM_KERNELS] (HOST) and store the number of sampled steps in
+ * *samples; the sampled events are released. */
+int sim_read_timing(sim_t* sim, double* kernel_ms, int64_t* samples);
+
+/* Route subsequent work to another HIP stream. */
+int sim_set_stream(sim_t* sim, void* hip_stream);
+
+/* Free all device memory of the handle (synchronises its stream). */
+void sim_destroy(sim_t* sim);
+
+/* Text of the last error on this handle ("" if none); valid until the next
+ * call on the handle.  sim_strerror: fixed text of a SIM_E* code. */
+const char* sim_last_error(const sim_t* sim);
+const char* sim_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRAFFICSIM_H */

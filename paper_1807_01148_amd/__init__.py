@@ -1,0 +1,254 @@
+"""MI355X traffic microsimulation: Python binding of libtrafficsim.so.
+
+Argument marshalling only.  Every step of the simulation runs in the HIP
+kernels of ``csrc/trafficsim.hip`` behind the C ABI of
+``include/trafficsim.h``; PyTorch supplies device memory (its caching
+allocator, through the library's allocator hooks) and the HIP stream.  If the
+library is not built, importing works but creating a simulation raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrafficsim.so")
+_LIB = None
+
+SIM_OK, SIM_EINVAL, SIM_EROUTE, SIM_ENOMEM, SIM_EHIP, SIM_ESTATE = 0, -1, -2, -3, -4, -5
+
+EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_vehicles",
+            "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_set_stream",
+            "sim_destroy", "sim_last_error", "sim_strerror")
+KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place")
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "error"), code, msg))
+        self.code = code
+
+
+_ERRNAMES = {SIM_EINVAL: "SIM_EINVAL", SIM_EROUTE: "SIM_EROUTE", SIM_ENOMEM: "SIM_ENOMEM",
+             SIM_EHIP: "SIM_EHIP", SIM_ESTATE: "SIM_ESTATE"}
+
+
+class SimNetwork(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_int32), ("num_edges", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("lanes", ctypes.c_void_p),
+                ("length_m", ctypes.c_void_p), ("speed_mps", ctypes.c_void_p), ("link_class", ctypes.c_void_p)]
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("veh_length", ctypes.c_float), ("s0", ctypes.c_float),
+                ("s_eps", ctypes.c_float), ("b_max", ctypes.c_float), ("num_classes", ctypes.c_int32),
+                ("idm", ctypes.c_void_p), ("mobil_p", ctypes.c_float), ("mobil_athr", ctypes.c_float),
+                ("mobil_bsafe", ctypes.c_float), ("mand_dist", ctypes.c_float),
+                ("lc_cooldown_steps", ctypes.c_int32)]
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("step", "loaded", "waiting", "en_route", "arrived", "departed",
+                                              "vehicle_updates", "claims_lost", "clamps", "claims")]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def library(path: str = LIB_PATH):
+    """Load libtrafficsim.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise ImportError("libtrafficsim.so is not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        P, i32 = ctypes.c_void_p, ctypes.c_int32
+        lib.sim_create.argtypes = [ctypes.POINTER(SimNetwork), ctypes.POINTER(SimParams), P, ALLOC_FN, FREE_FN,
+                                   P, ctypes.POINTER(P)]
+        lib.sim_create.restype = ctypes.c_int
+        lib.sim_load_demand.argtypes = [P, i32, P, P, i32, P, P, P, P, P]
+        lib.sim_load_demand.restype = ctypes.c_int
+        lib.sim_step.argtypes = [P, i32]
+        lib.sim_step.restype = ctypes.c_int
+        lib.sim_stats.argtypes = [P, ctypes.POINTER(SimStats), P, P, P]
+        lib.sim_stats.restype = ctypes.c_int
+        lib.sim_read_vehicles.argtypes = [P, i32, ctypes.POINTER(i32), P, P, P, P, P, P, P, P, P]
+        lib.sim_read_vehicles.restype = ctypes.c_int
+        lib.sim_read_trips.argtypes = [P, P, P]
+        lib.sim_read_trips.restype = ctypes.c_int
+        lib.sim_set_idm.argtypes = [P, P]
+        lib.sim_set_idm.restype = ctypes.c_int
+        lib.sim_set_timing.argtypes = [P, i32]
+        lib.sim_set_timing.restype = ctypes.c_int
+        lib.sim_read_timing.argtypes = [P, P, ctypes.POINTER(ctypes.c_int64)]
+        lib.sim_read_timing.restype = ctypes.c_int
+        lib.sim_set_stream.argtypes = [P, P]
+        lib.sim_set_stream.restype = ctypes.c_int
+        lib.sim_destroy.argtypes = [P]
+        lib.sim_destroy.restype = None
+        lib.sim_last_error.argtypes = [P]
+        lib.sim_last_error.restype = ctypes.c_char_p
+        lib.sim_strerror.argtypes = [ctypes.c_int]
+        lib.sim_strerror.restype = ctypes.c_char_p
+        _LIB = lib
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _TorchAllocator:
+    """Allocator hooks backed by torch's caching allocator on one stream."""
+
+    def __init__(self, device, stream):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, ctx, nbytes):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:  # noqa: BLE001 - reported to the library as NULL
+            return None
+
+    def _free(self, ctx, ptr):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Sim:
+    """A simulation of one scenario dict (see ``scenarios``) on one GPU.
+
+    ``stream``: a torch.cuda.Stream (default: the current stream of
+    ``device``).  ``torch_alloc``: route device allocations through torch's
+    caching allocator (otherwise the library calls hipMalloc)."""
+
+    def __init__(self, scen, device: int = 0, stream=None, torch_alloc: bool = True):
+        import torch
+        self.lib = library()
+        self.h = None
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self._alloc = _TorchAllocator(device, stream) if torch_alloc else None
+        net, p = scen["net"], scen["params"]
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dt)
+            keep.append(a)
+            return _p(a)
+
+        self.num_edges = int(net["col_idx"].size)
+        cls = net.get("link_class")
+        self._net = SimNetwork(int(net["row_ptr"].size - 1), self.num_edges, arr(net["row_ptr"], np.int32),
+                               arr(net["col_idx"], np.int32), arr(net["lanes"], np.int32),
+                               arr(net["length"], np.float32), arr(net["speed"], np.float32),
+                               None if cls is None else arr(cls, np.int32))
+        self.num_classes = int(p["num_classes"])
+        idm = np.ascontiguousarray(p["idm"], np.float32).reshape(self.num_classes, 4)
+        self._params = SimParams(p["dt"], p["veh_length"], p["s0"], p["s_eps"], p["b_max"], self.num_classes,
+                                 arr(idm, np.float32), p["mobil_p"], p["mobil_athr"], p["mobil_bsafe"],
+                                 p["mand_dist"], int(p["lc_cooldown"]))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            rc = self.lib.sim_create(ctypes.byref(self._net), ctypes.byref(self._params),
+                                     ctypes.c_void_p(stream.cuda_stream),
+                                     self._alloc.alloc if self._alloc else ALLOC_FN(),
+                                     self._alloc.free if self._alloc else FREE_FN(), None, ctypes.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, self.lib.sim_strerror(rc).decode())
+        self.h = h
+        d = scen["demand"]
+        self.num_trips = int(d["depart_step"].size)
+        ix = d.get("init_x")
+        with torch.cuda.device(device):
+            rc = self.lib.sim_load_demand(
+                self.h, self.num_trips, arr(d["depart_step"], np.int32), arr(d["trip_route"], np.int32),
+                int(d["route_ptr"].size - 1), arr(d["route_ptr"], np.int64), arr(d["route_edges"], np.int32),
+                None if ix is None else arr(ix, np.float32),
+                None if d.get("init_v") is None else arr(d["init_v"], np.float32),
+                None if d.get("init_lane") is None else arr(d["init_lane"], np.int32))
+        self._check(rc)
+
+    def _check(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, self.lib.sim_last_error(self.h).decode())
+
+    def close(self):
+        if self.h is not None:
+            import torch
+            with torch.cuda.device(self.device):
+                self.lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def step(self, n: int = 1):
+        self._check(self.lib.sim_step(self.h, int(n)))
+
+    def counters(self) -> dict:
+        st = SimStats()
+        self._check(self.lib.sim_stats(self.h, ctypes.byref(st), None, None, None))
+        return {n: int(getattr(st, n)) for n, _ in SimStats._fields_}
+
+    def edge_stats_device(self):
+        """Per-edge statistics as int64 torch tensors on the device."""
+        import torch
+        out = [torch.empty(self.num_edges, dtype=torch.int64, device="cuda:%d" % self.device) for _ in range(3)]
+        with torch.cuda.stream(self.stream):
+            self._check(self.lib.sim_stats(self.h, None, ctypes.c_void_p(out[0].data_ptr()),
+                                           ctypes.c_void_p(out[1].data_ptr()), ctypes.c_void_p(out[2].data_ptr())))
+        return {"count": out[0], "tt_steps": out[1], "tt_us": out[2]}
+
+    def edge_stats(self) -> dict:
+        d = self.edge_stats_device()
+        self.stream.synchronize()
+        return {k: v.cpu().numpy() for k, v in d.items()}
+
+    def vehicles(self) -> dict:
+        """Vehicles on the road, sorted by vehicle id (host arrays)."""
+        n = ctypes.c_int32(0)
+        cap = self.num_trips
+        iv = {k: np.zeros(max(cap, 1), np.int32) for k in ("vid", "edge", "lane", "cursor", "lc", "kin")}
+        fv = {k: np.zeros(max(cap, 1), np.float32) for k in ("x", "v", "phin")}
+        self._check(self.lib.sim_read_vehicles(self.h, cap, ctypes.byref(n), _p(iv["vid"]), _p(iv["edge"]),
+                                               _p(iv["lane"]), _p(iv["cursor"]), _p(iv["lc"]), _p(iv["kin"]),
+                                               _p(fv["x"]), _p(fv["v"]), _p(fv["phin"])))
+        m = n.value
+        o = np.argsort(iv["vid"][:m], kind="stable")
+        out = {k: a[:m][o] for k, a in iv.items()}
+        out.update({k: a[:m][o] for k, a in fv.items()})
+        return out
+
+    def trips(self) -> dict:
+        da = np.zeros(self.num_trips, np.int32)
+        ar = np.zeros(self.num_trips, np.int32)
+        self._check(self.lib.sim_read_trips(self.h, _p(da), _p(ar)))
+        return {"depart_actual": da, "arrive_step": ar}
+
+    def set_timing(self, every: int):
+        """Sample per-kernel HIP-event timings on every ``every``-th step."""
+        self._check(self.lib.sim_set_timing(self.h, int(every)))
+
+    def read_timing(self):
+        """(sum of ms per kernel over sampled steps, number of sampled steps)."""
+        ms = np.zeros(len(KERNELS), np.float64)
+        n = ctypes.c_int64(0)
+        self._check(self.lib.sim_read_timing(self.h, _p(ms), ctypes.byref(n)))
+        return dict(zip(KERNELS, ms.tolist())), int(n.value)
+
+    def set_idm(self, idm):
+        idm = np.ascontiguousarray(idm, np.float32).reshape(self.num_classes, 4)
+        self._check(self.lib.sim_set_idm(self.h, _p(idm)))

@@ -406,3 +406,56 @@ def metro_scenario(seed: int = 1810, n_nodes: int = 1_000_000, n_edges: int = 2_
 def sorted_trip_order(depart_step):
     """Vehicle ids: trips ranked by (departure step, trip index)."""
     return np.lexsort((np.arange(depart_step.size), depart_step))
+
+
+def placed_snapshot(net, n_veh: int, *, seed: int = 7, route_len: int = 3, spacing=(8.0, 40.0),
+                    platoon=(1, 6), params=None, name="snapshot"):
+    """A synthetic mid-simulation snapshot on ``net``: about ``n_veh`` vehicles
+    placed in platoons on randomly chosen lanes (weighted by lane length),
+    consecutive vehicles of a platoon ``spacing`` metres apart (front to
+    front), speeds uniform below the speed limit, each with a random
+    ``route_len``-edge route that starts on its edge.  All trips depart at
+    step 0 as placed trips."""
+    rng = np.random.default_rng(seed)
+    E = int(net["col_idx"].size)
+    lanes = net["lanes"].astype(np.int64)
+    length = net["length"].astype(np.float64)
+    lane_edge = np.repeat(np.arange(E), lanes)
+    lane_no = np.arange(lane_edge.size) - np.repeat(np.concatenate([[0], np.cumsum(lanes)[:-1]]), lanes)
+    w = length[lane_edge]
+    mean_pl = 0.5 * (platoon[0] + platoon[1])
+    n_lanes = min(lane_edge.size, max(1, int(n_veh / mean_pl)))
+    chosen = rng.choice(lane_edge.size, size=n_lanes, replace=False, p=w / w.sum())
+    k = rng.integers(platoon[0], platoon[1] + 1, n_lanes)
+    e_of = np.repeat(lane_edge[chosen], k)
+    l_of = np.repeat(lane_no[chosen], k)
+    first = np.repeat(np.concatenate([[0], np.cumsum(k)[:-1]]), k)
+    rank = np.arange(e_of.size) - first
+    gaps = rng.uniform(spacing[0], spacing[1], e_of.size)
+    gaps[rank == 0] = 0.0
+    offs = np.cumsum(gaps)
+    offs -= np.repeat(offs[first[rank == 0]], k)
+    start = np.repeat(rng.uniform(0.0, 1.0, n_lanes), k) * length[e_of]
+    x = start + offs
+    keep = x < length[e_of] - 0.01
+    e_of, l_of, x = e_of[keep], l_of[keep], x[keep]
+    n = e_of.size
+    v = rng.uniform(0.0, 1.0, n) * net["speed"][e_of]
+    # random contiguous routes
+    rp = net["row_ptr"].astype(np.int64)
+    head = net["col_idx"].astype(np.int64)
+    route = np.empty((n, route_len), np.int64)
+    route[:, 0] = e_of
+    for j in range(1, route_len):
+        h = head[route[:, j - 1]]
+        deg = rp[h + 1] - rp[h]
+        route[:, j] = rp[h] + np.floor(rng.uniform(0.0, 1.0, n) * deg).astype(np.int64)
+    p = params if params is not None else default_params(int(net.get("link_class", np.zeros(1)).max()) + 1)
+    demand = {
+        "depart_step": np.zeros(n, np.int32),
+        "trip_route": np.arange(n, dtype=np.int32),
+        "route_ptr": np.arange(0, n * route_len + 1, route_len, dtype=np.int64),
+        "route_edges": route.ravel().astype(np.int32),
+        "init_x": x.astype(np.float32), "init_v": v.astype(np.float32), "init_lane": l_of.astype(np.int32),
+    }
+    return {"name": name, "net": net, "params": p, "demand": demand, "steps": 1}
