@@ -24,17 +24,30 @@ FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-
 
 
 def build(force: bool = False):
-    """Compile liboracle_f32.so and liboracle_f64.so with gcc."""
-    src = os.path.join(_HERE, "oracle.c")
+    """Compile liboracle_f32.so, liboracle_f64.so and libadjoint.so with gcc."""
     outs = []
-    for prec, defs in (("f32", []), ("f64", ["-DORACLE_F64"])):
-        out = os.path.join(_HERE, "liboracle_%s.so" % prec)
+    for prec, defs, name in (("f32", [], "oracle.c"), ("f64", ["-DORACLE_F64"], "oracle.c"),
+                             ("adj", [], "adjoint.c")):
+        src = os.path.join(_HERE, name)
+        out = os.path.join(_HERE, "liboracle_%s.so" % prec if prec != "adj" else "libadjoint.so")
         if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
             tmp = out + ".tmp%d" % os.getpid()
             subprocess.check_call(["gcc"] + FLAGS + defs + ["-o", tmp, src, "-lm"])
             os.replace(tmp, out)
         outs.append(out)
     return outs
+
+
+def _adjlib():
+    if "adj" not in _LIBS:
+        build()
+        lib = ctypes.CDLL(os.path.join(_HERE, "libadjoint.so"))
+        P = ctypes.c_void_p
+        lib.adj_eval.argtypes = [ctypes.c_int64] + [P] * 8 + [ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                                            ctypes.c_int32] + [P] * 9
+        lib.adj_eval.restype = ctypes.c_int
+        _LIBS["adj"] = lib
+    return _LIBS["adj"]
 
 
 def _lib(prec):
@@ -59,6 +72,10 @@ def _lib(prec):
         lib.or_num_active.restype = i32
         lib.or_num_pending.argtypes = [P]
         lib.or_num_pending.restype = i32
+        lib.or_tape_enable.argtypes = [P, i32]
+        lib.or_tape_size.argtypes = [P]
+        lib.or_tape_size.restype = ctypes.c_int64
+        lib.or_tape_get.argtypes = [P] + [P] * 8
         _LIBS[prec] = lib
     return _LIBS[prec]
 
@@ -81,10 +98,44 @@ class OracleError(RuntimeError):
     pass
 
 
+TAPE_INT = ("step", "vid", "mode", "lead", "flags", "edge")
+TAPE_F64 = ("x0", "v0")
+
+
+def replay(tape, scen, theta, target, mask, grad=True):
+    """Frozen-event FP64 replay of ``tape`` at parameters ``theta``
+    [num_classes, 4] = (v0_scale, T, a, b): returns (loss, gradient or None,
+    mean link travel times [E], final x [V], final v [V])."""
+    lib = _adjlib()
+    net, p = scen["net"], scen["params"]
+    ne = int(net["col_idx"].size)
+    nveh = int(scen["demand"]["depart_step"].size)
+    # the network and constants enter as the float32 values the simulators use
+    length = np.asarray(net["length"], np.float32).astype(np.float64)
+    speed = np.asarray(net["speed"], np.float32).astype(np.float64)
+    cls = np.ascontiguousarray(net.get("link_class", np.zeros(ne)), np.int32)
+    th = np.ascontiguousarray(theta, np.float64).reshape(-1, 4)
+    fp = np.array([np.float32(p[k]) for k in ("dt", "veh_length", "s0", "s_eps", "b_max")], np.float64)
+    tgt = np.ascontiguousarray(target, np.float64)
+    msk = np.ascontiguousarray(mask, np.uint8)
+    loss = ctypes.c_double(0.0)
+    g = np.zeros(th.size, np.float64) if grad else None
+    tbar = np.zeros(ne, np.float64)
+    xf = np.zeros(max(nveh, 1), np.float64)
+    vf = np.zeros(max(nveh, 1), np.float64)
+    tp = {k: np.ascontiguousarray(tape[k]) for k in TAPE_INT + TAPE_F64}
+    rc = lib.adj_eval(int(tp["step"].size), *[_p(tp[k]) for k in TAPE_INT + TAPE_F64], nveh, ne,
+                      _p(length), _p(speed), _p(cls), int(th.shape[0]), _p(th), _p(fp), _p(tgt), _p(msk),
+                      ctypes.byref(loss), _p(g), _p(tbar), _p(xf), _p(vf))
+    if rc != 0:
+        raise OracleError("adj_eval failed: %d" % rc)
+    return loss.value, (None if g is None else g.reshape(th.shape)), tbar, xf[:nveh], vf[:nveh]
+
+
 class Oracle:
     """One oracle simulation of a scenario dict (see ``scenarios``)."""
 
-    def __init__(self, scen, precision: str = "f32"):
+    def __init__(self, scen, precision: str = "f32", tape: bool = False):
         self.lib = _lib(precision)
         self.precision = precision
         net, p = scen["net"], scen["params"]
@@ -109,6 +160,8 @@ class Oracle:
         d = scen["demand"]
         self.ntrips = int(d["depart_step"].size)
         ix = d.get("init_x")
+        if tape:
+            self.lib.or_tape_enable(self.h, 1)
         rc = self.lib.or_load_demand(
             self.h, self.ntrips, _p(arr(d["depart_step"], np.int32)), _p(arr(d["trip_route"], np.int32)),
             int(d["route_ptr"].size - 1), _p(arr(d["route_ptr"], np.int64)), _p(arr(d["route_edges"], np.int32)),
@@ -152,6 +205,17 @@ class Oracle:
         ar = np.zeros(self.ntrips, np.int32)
         self.lib.or_get_trips(self.h, _p(da), _p(ar))
         return {"depart_actual": da, "arrive_step": ar}
+
+    def enable_tape(self, on: bool = True):
+        """Record the discrete events of the following steps."""
+        self.lib.or_tape_enable(self.h, 1 if on else 0)
+
+    def tape(self) -> dict:
+        n = int(self.lib.or_tape_size(self.h))
+        t = {k: np.zeros(max(n, 1), np.int32) for k in TAPE_INT}
+        t.update({k: np.zeros(max(n, 1), np.float64) for k in TAPE_F64})
+        self.lib.or_tape_get(self.h, *[_p(t[k]) for k in TAPE_INT + TAPE_F64])
+        return {k: a[:n] for k, a in t.items()}
 
     def edge_stats(self) -> dict:
         c = np.zeros(self.ne, np.int64)

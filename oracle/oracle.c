@@ -51,6 +51,8 @@ typedef float real;
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_EROUTE = -2, OR_ENOMEM = -3, OR_ESTATE = -5 };
 enum { K_STAY = 0, K_ARRIVE = 1, K_CROSS = 2, K_CHANGE = 3 };
+/* modes of the event tape */
+enum { TM_STAY = 0, TM_CHANGE = 1, TM_YIELD = 2, TM_ARRIVE = 3, TM_CROSS = 4, TM_APPEAR = 5 };
 
 typedef struct {
     int32_t vid, edge, lane, rcur, next, lc, kin;
@@ -78,7 +80,32 @@ typedef struct {
     int32_t* pend;
     int64_t *st_cnt, *st_steps, *st_us;
     int64_t departed, arrived, updates, claims_lost, clamps;
+    /* event tape (discrete outcomes of every step, for the frozen-event replay) */
+    int tape_on;
+    int64_t tp_n, tp_cap;
+    int32_t *tp_step, *tp_vid, *tp_mode, *tp_lead, *tp_flags, *tp_edge;
+    double *tp_x0, *tp_v0;
 } osim;
+
+static void tape_push(osim* S, int32_t step, int32_t vid, int32_t mode, int32_t lead, int32_t flags,
+                      int32_t edge, double x0, double v0) {
+    if (!S->tape_on) return;
+    if (S->tp_n == S->tp_cap) {
+        int64_t c = S->tp_cap ? 2 * S->tp_cap : 4096;
+        S->tp_step = (int32_t*)realloc(S->tp_step, sizeof(int32_t) * c);
+        S->tp_vid = (int32_t*)realloc(S->tp_vid, sizeof(int32_t) * c);
+        S->tp_mode = (int32_t*)realloc(S->tp_mode, sizeof(int32_t) * c);
+        S->tp_lead = (int32_t*)realloc(S->tp_lead, sizeof(int32_t) * c);
+        S->tp_flags = (int32_t*)realloc(S->tp_flags, sizeof(int32_t) * c);
+        S->tp_edge = (int32_t*)realloc(S->tp_edge, sizeof(int32_t) * c);
+        S->tp_x0 = (double*)realloc(S->tp_x0, sizeof(double) * c);
+        S->tp_v0 = (double*)realloc(S->tp_v0, sizeof(double) * c);
+        S->tp_cap = c;
+    }
+    int64_t i = S->tp_n++;
+    S->tp_step[i] = step; S->tp_vid[i] = vid; S->tp_mode[i] = mode; S->tp_lead[i] = lead;
+    S->tp_flags[i] = flags; S->tp_edge[i] = edge; S->tp_x0[i] = x0; S->tp_v0[i] = v0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* creation: derived constants are computed once in double from the inputs
@@ -155,6 +182,8 @@ void or_destroy(osim* S) {
     free(S->dep); free(S->rbeg); free(S->rend); free(S->route_edges);
     free(S->depart_actual); free(S->arrive_step); free(S->act); free(S->pend);
     free(S->st_cnt); free(S->st_steps); free(S->st_us);
+    free(S->tp_step); free(S->tp_vid); free(S->tp_mode); free(S->tp_lead); free(S->tp_flags);
+    free(S->tp_edge); free(S->tp_x0); free(S->tp_v0);
     free(S);
 }
 
@@ -275,7 +304,10 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
             }
         }
         free(o);
-        for (int32_t v = 0; v < ntrips; ++v) S->depart_actual[v] = S->t;
+        for (int32_t v = 0; v < ntrips; ++v) {
+            S->depart_actual[v] = S->t;
+            tape_push(S, S->t, v, TM_APPEAR, -1, 0, S->act[v].edge, (double)S->act[v].x, (double)S->act[v].v);
+        }
         S->departed = ntrips;
     }
     free(ord);
@@ -290,52 +322,81 @@ typedef struct {
     real s;     /* bumper-to-bumper gap (m) */
     real vl;    /* speed of the vehicle ahead */
     real xl;    /* its front position on its own link */
+    int32_t vid;
 } lead_t;
+
+/* branch flags of one applied motion (recorded in the event tape) */
+enum {
+    TF_HAS_LEAD = 1, TF_LEAD_CROSS = 2, TF_DYN_FLOOR = 4, TF_S_FLOOR = 8, TF_ACC_FLOOR = 16,
+    TF_STOP = 32, TF_DX_FLOOR = 64, TF_CLAMP = 128, TF_CLAMP_ZERO = 256, TF_CLAMP_V = 512, TF_F_ONE = 1024
+};
+static int lead_flags(lead_t L) { return L.kind == 0 ? 0 : (TF_HAS_LEAD | (L.kind == 2 ? TF_LEAD_CROSS : 0)); }
 
 /* IDM acceleration (Sec. 6.3.2, car-following equation), with the dynamic
  * part of the desired gap floored at 0, the gap floored at s_eps and the
  * result floored at -b_max. */
-static real idm(const osim* S, int32_t c, real inv_v0, real v, lead_t L) {
+static real idm_fl(const osim* S, int32_t c, real inv_v0, real v, lead_t L, int* fl) {
     real r = v * inv_v0;
     real r2 = r * r;
     real r4 = r2 * r2;
     real fr = (real)1 - r4;
     real acc;
+    int f = 0;
     if (L.kind == 0) {
         acc = S->A[c] * fr;
     } else {
         real dv = v - L.vl;
         real dyn = v * S->T[c] + (v * dv) * S->kab[c];
+        if ((real)0 > dyn) f |= TF_DYN_FLOOR;
         real ss = S->s0 + RMAX((real)0, dyn);
+        if (!(L.s > S->s_eps)) f |= TF_S_FLOOR;
         real q = ss / RMAX(L.s, S->s_eps);
         acc = S->A[c] * (fr - q * q);
     }
+    if (!(acc > -S->b_max)) f |= TF_ACC_FLOOR;
+    if (fl) *fl |= f;
     return RMAX(acc, -S->b_max);
+}
+
+static real idm(const osim* S, int32_t c, real inv_v0, real v, lead_t L) {
+    return idm_fl(S, c, inv_v0, v, L, NULL);
 }
 
 /* Ballistic update over dt; when the speed would turn negative the vehicle
  * stops within the step. */
-static void move(const osim* S, real v, real acc, real* dx, real* vn) {
+static void move_fl(const osim* S, real v, real acc, real* dx, real* vn, int* fl) {
     real vv = v + acc * S->dt;
+    int f = 0;
     if (vv < (real)0) {
         *dx = (v * v) / ((real)(-2) * acc);
         *vn = (real)0;
+        f |= TF_STOP;
     } else {
         *dx = v * S->dt + acc * S->h;
         *vn = vv;
     }
+    if (!(*dx > (real)0)) f |= TF_DX_FLOOR;
     *dx = RMAX(*dx, (real)0);
+    if (fl) *fl |= f;
 }
 
+static void move(const osim* S, real v, real acc, real* dx, real* vn) { move_fl(S, v, acc, dx, vn, NULL); }
+
 /* never advance past the rear of the vehicle ahead */
-static int clampmv(lead_t L, real* dx, real* vn) {
+static int clampmv_fl(lead_t L, real* dx, real* vn, int* fl) {
     if (L.kind != 0 && *dx > L.s) {
+        int f = TF_CLAMP;
+        if (!(L.s > (real)0)) f |= TF_CLAMP_ZERO;
+        if (!(*vn < L.vl)) f |= TF_CLAMP_V;
         *dx = RMAX(L.s, (real)0);
         *vn = RMIN(*vn, L.vl);
+        if (fl) *fl |= f;
         return 1;
     }
     return 0;
 }
+
+static int clampmv(lead_t L, real* dx, real* vn) { return clampmv_fl(L, dx, vn, NULL); }
 
 /* ------------------------------------------------------------------------ */
 /* step                                                                        */
@@ -346,6 +407,8 @@ typedef struct {
     real X, vc, f;               /* front on the target, speed, crossing fraction */
     int32_t lo, hi;              /* claim cells */
     int clamped;
+    int own_fl, chg_fl;          /* branch flags of the own-lane and the lane-change motion */
+    int32_t own_lead, chg_lead;  /* vehicle ahead used by each (-1: free road) */
 } dec_t;
 
 typedef struct {
@@ -380,12 +443,12 @@ static const veh_t* at(const view_t* W, int32_t o) { return &W->act[W->ord[o]]; 
  * else the rearmost vehicle of lane min(l, lanes-1) of the next link. */
 static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_t next, int32_t l) {
     const osim* S = W->S;
-    lead_t L = {0, 0, 0, 0};
+    lead_t L = {0, 0, 0, 0, -1};
     int32_t f = W->first[k], n = W->cnt[k];
     for (int32_t j = 0; j < n; ++j) {
         const veh_t* q = at(W, f + j);
         if (q->x > x) {
-            L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x;
+            L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x; L.vid = q->vid;
             return L;
         }
     }
@@ -394,7 +457,7 @@ static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_
         int32_t k2 = lane_key(S, next, l2);
         if (W->cnt[k2] > 0) {
             const veh_t* q = at(W, W->first[k2]);
-            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (S->len[e] - x) + (q->x - S->lveh);
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (S->len[e] - x) + (q->x - S->lveh); L.vid = q->vid;
         }
     }
     return L;
@@ -417,26 +480,31 @@ static dec_t decide(const view_t* W, int32_t o) {
     memset(&D, 0, sizeof(D));
 
     /* own leader: the next vehicle of this lane, else look ahead one link */
-    lead_t L = {0, 0, 0, 0};
+    lead_t L = {0, 0, 0, 0, -1};
     if (o + 1 < S->nact && lane_key(S, at(W, o + 1)->edge, at(W, o + 1)->lane) == k) {
         const veh_t* q = at(W, o + 1);
-        L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x;
+        L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x; L.vid = q->vid;
     } else if (me->next >= 0) {
         int32_t n2 = me->next;
         int32_t l2 = l < S->lanes[n2] - 1 ? l : S->lanes[n2] - 1;
         int32_t k2 = lane_key(S, n2, l2);
         if (W->cnt[k2] > 0) {
             const veh_t* q = at(W, W->first[k2]);
-            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (len - x) + (q->x - S->lveh);
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (len - x) + (q->x - S->lveh); L.vid = q->vid;
         }
     }
-    real ac = idm(S, c, iv, v, L);
+    D.own_fl = lead_flags(L);
+    D.own_lead = L.kind ? L.vid : -1;
+    D.chg_lead = -1;
+    real ac = idm_fl(S, c, iv, v, L, &D.own_fl);
     real dx, vn;
-    move(S, v, ac, &dx, &vn);
-    D.clamped = clampmv(L, &dx, &vn);
+    move_fl(S, v, ac, &dx, &vn, &D.own_fl);
+    D.clamped = clampmv_fl(L, &dx, &vn, &D.own_fl);
     real xs = x + dx;
     if (xs > len) { /* the front passes the link end strictly */
-        D.f = dx > (real)0 ? RMIN((len - x) / dx, (real)1) : (real)0;
+        real fq = (len - x) / dx;
+        if (!(fq < (real)1)) D.own_fl |= TF_F_ONE;
+        D.f = dx > (real)0 ? RMIN(fq, (real)1) : (real)0;
         if (me->next < 0) {
             D.kind = K_ARRIVE;
             return D;
@@ -487,7 +555,8 @@ static dec_t decide(const view_t* W, int32_t o) {
     const veh_t* F = NULL;
     if (o > 0 && lane_key(S, at(W, o - 1)->edge, at(W, o - 1)->lane) == k) F = at(W, o - 1);
 
-    int best = -1;
+    int best = -1, best_fl = 0;
+    int32_t best_lead = -1;
     real best_inc = 0, best_X = 0, best_v = 0;
     for (int ci = 0; ci < nc; ++ci) {
         int32_t lt = cand[ci], kt = lane_key(S, e, lt);
@@ -501,20 +570,21 @@ static dec_t decide(const view_t* W, int32_t o) {
         /* gap acceptance */
         if (Lt.kind != 0 && Lt.s < S->s0) continue;
         if (Ft && ((x - S->lveh) - Ft->x) < S->s0) continue;
-        real at_ = idm(S, c, iv, v, Lt);
+        int tfl = lead_flags(Lt);
+        real at_ = idm_fl(S, c, iv, v, Lt, &tfl);
         if (at_ < -S->bsafe) continue;
         real dxt, vt;
-        move(S, v, at_, &dxt, &vt);
-        clampmv(Lt, &dxt, &vt);
+        move_fl(S, v, at_, &dxt, &vt, &tfl);
+        clampmv_fl(Lt, &dxt, &vt, &tfl);
         real Xt = x + dxt;
         if (Xt >= len) continue;
         real an = 0, ant = 0;
         if (Ft) {
             an = idm(S, c, iv, Ft->v, relead(S, e, Lt, Ft->x));
-            lead_t Li = {1, (x - S->lveh) - Ft->x, v, x};
+            lead_t Li = {1, (x - S->lveh) - Ft->x, v, x, me->vid};
             ant = idm(S, c, iv, Ft->v, Li);
             if (ant < -S->bsafe) continue;
-            lead_t none = {0, 0, 0, 0};
+            lead_t none = {0, 0, 0, 0, -1};
             real afree = idm(S, c, iv, Ft->v, none);
             real dxF, vF;
             move(S, Ft->v, afree, &dxF, &vF);
@@ -526,7 +596,7 @@ static dec_t decide(const view_t* W, int32_t o) {
             real d2 = Ft ? (ant - an) : (real)0;
             real d3 = (real)0;
             if (F) {
-                lead_t Lo = {1, (x - S->lveh) - F->x, v, x};
+                lead_t Lo = {1, (x - S->lveh) - F->x, v, x, me->vid};
                 real ao = idm(S, c, iv, F->v, Lo);
                 real aot = idm(S, c, iv, F->v, relead(S, e, L, F->x));
                 d3 = aot - ao;
@@ -536,6 +606,7 @@ static dec_t decide(const view_t* W, int32_t o) {
         }
         if (best < 0 || inc > best_inc) {
             best = lt; best_inc = inc; best_X = Xt; best_v = vt;
+            best_fl = tfl; best_lead = Lt.kind ? Lt.vid : -1;
         }
     }
     if (best >= 0) {
@@ -545,6 +616,8 @@ static dec_t decide(const view_t* W, int32_t o) {
         D.tkey = lane_key(S, e, best);
         D.X = best_X;
         D.vc = best_v;
+        D.chg_fl = best_fl;
+        D.chg_lead = best_lead;
         claim_cells(S, e, best_X, &D.lo, &D.hi);
     }
     return D;
@@ -644,6 +717,13 @@ static int step_once(osim* S) {
         veh_t q = *at(&W, o);
         const dec_t* d = &D[o];
         S->clamps += d->clamped;
+        if (S->tape_on) {
+            int32_t mode = TM_STAY, lead = d->own_lead, fl = d->own_fl;
+            if (d->kind == K_ARRIVE) mode = TM_ARRIVE;
+            else if (d->kind == K_CROSS) mode = cwin_veh[o] ? TM_CROSS : TM_YIELD;
+            else if (d->kind == K_CHANGE && cwin_veh[o]) { mode = TM_CHANGE; lead = d->chg_lead; fl = d->chg_fl; }
+            tape_push(S, t, q.vid, mode, lead, fl, q.edge, 0.0, 0.0);
+        }
         if (d->kind == K_ARRIVE) {
             record_exit(S, &q, d->f, t);
             S->arrive_step[q.vid] = t + 1;
@@ -689,6 +769,7 @@ static int step_once(osim* S) {
             nact[nn++] = q;
             S->depart_actual[v] = t + 1;
             S->departed += 1;
+            tape_push(S, t + 1, v, TM_APPEAR, -1, 0, q.edge, (double)q.x, (double)q.v);
         } else {
             S->pend[np++] = v;
         }
@@ -765,4 +846,22 @@ void or_get_edge_stats(const osim* S, int64_t* cnt, int64_t* steps, int64_t* us)
 }
 
 int32_t or_num_active(const osim* S) { return S->nact; }
+
+/* event tape: recording switch, size, copy-out (records in step order; at one
+ * step, the vehicles that appear come before the moves of that step only in
+ * the sense that APPEAR records carry the state index at which they appear) */
+void or_tape_enable(osim* S, int32_t on) { S->tape_on = on; }
+int64_t or_tape_size(const osim* S) { return S->tp_n; }
+void or_tape_get(const osim* S, int32_t* step, int32_t* vid, int32_t* mode, int32_t* lead, int32_t* flags,
+                 int32_t* edge, double* x0, double* v0) {
+    int64_t n = S->tp_n;
+    memcpy(step, S->tp_step, sizeof(int32_t) * n);
+    memcpy(vid, S->tp_vid, sizeof(int32_t) * n);
+    memcpy(mode, S->tp_mode, sizeof(int32_t) * n);
+    memcpy(lead, S->tp_lead, sizeof(int32_t) * n);
+    memcpy(flags, S->tp_flags, sizeof(int32_t) * n);
+    memcpy(edge, S->tp_edge, sizeof(int32_t) * n);
+    memcpy(x0, S->tp_x0, sizeof(double) * n);
+    memcpy(v0, S->tp_v0, sizeof(double) * n);
+}
 int32_t or_num_pending(const osim* S) { return S->npend; }

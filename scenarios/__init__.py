@@ -459,3 +459,31 @@ def placed_snapshot(net, n_veh: int, *, seed: int = 7, route_len: int = 3, spaci
         "init_x": x.astype(np.float32), "init_v": v.astype(np.float32), "init_lane": l_of.astype(np.int32),
     }
     return {"name": name, "net": net, "params": p, "demand": demand, "steps": 1}
+
+
+def draw_idm(rng, num_classes):
+    """IDM parameters (v0_scale, T, a, b) per class, drawn v0 x U(0.8, 1.2),
+    T ~ U(1, 2), a ~ U(0.7, 1.5), b ~ U(1, 2.5)."""
+    idm = np.zeros((num_classes, 4), np.float32)
+    idm[:, 0] = rng.uniform(0.8, 1.2, num_classes)
+    idm[:, 1] = rng.uniform(1.0, 2.0, num_classes)
+    idm[:, 2] = rng.uniform(0.7, 1.5, num_classes)
+    idm[:, 3] = rng.uniform(1.0, 2.5, num_classes)
+    return idm
+
+
+def diff_scenario(seed: int = 1812, side: int = 50, n_trips: int = 100_000, steps: int = 1800,
+                  depart_s: float = 600.0, num_classes: int = 4):
+    """Differentiation workload: the 50x50 grid network with link classes drawn
+    uniformly over ``num_classes``, uniform O/D trips departing U(0, 600 s),
+    1,800 steps.  ``hidden_idm`` holds the parameters that generate the target
+    travel times; ``params['idm']`` starts at the default values."""
+    rng = np.random.default_rng(seed)
+    net = grid(side, seed=seed, lane_probs=(0.5, 0.35, 0.15), lognormal=(120.0, 0.4), speed=15.0,
+               num_classes=num_classes)
+    p = default_params(num_classes)
+    o, d = uniform_od(rng, side * side, n_trips)
+    dep = rng.uniform(0.0, depart_s, n_trips)
+    return {"name": "diff%d_%d" % (side, n_trips), "net": net, "params": p,
+            "demand": make_demand(net, o, d, dep, p["dt"]), "steps": steps,
+            "hidden_idm": draw_idm(np.random.default_rng(seed + 1), num_classes)}
