@@ -159,6 +159,25 @@ int sim_set_timing(sim_t* sim, int32_t every);
  * *samples; the sampled events are released. */
 int sim_read_timing(sim_t* sim, double* kernel_ms, int64_t* samples);
 
+/* Start a differentiation window at the current step: subsequent sim_step
+ * calls save a full-state checkpoint every `checkpoint_every` steps (device
+ * memory, ~44 B x trips each).  At most 16 link classes.  Errors: SIM_EINVAL,
+ * SIM_ESTATE (no demand). */
+int sim_tape_begin(sim_t* sim, int32_t checkpoint_every);
+
+/* Gradient of a loss of the per-link mean travel times (Sec. 6.4) with respect
+ * to the IDM parameters (Sec. 6.3.2, car-following equation) of every link
+ * class, over the window since sim_tape_begin, with every discrete event of
+ * that window (who is on which link and lane, who follows whom, when a link
+ * end is crossed, which branch each min/max/stop/clamp took) held fixed.
+ *   dL_dmeanTT [num_edges]        DEVICE float: dLoss/d(mean travel time of the
+ *                                 link in seconds), mean = tt_us / count / 1e6
+ *   dL_dtheta  [num_classes * 4]  DEVICE float out: (v0_scale, T, a, b) per class
+ * Each checkpointed segment is recomputed with its event tape, then walked
+ * backwards.  Asynchronous on the handle's stream; live state and statistics
+ * are left as they were.  Errors: SIM_ESTATE (no window), SIM_ENOMEM, SIM_EHIP. */
+int sim_grad(sim_t* sim, const float* dL_dmeanTT, float* dL_dtheta);
+
 /* Route subsequent work to another HIP stream. */
 int sim_set_stream(sim_t* sim, void* hip_stream);
 

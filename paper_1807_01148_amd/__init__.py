@@ -20,8 +20,8 @@ _LIB = None
 SIM_OK, SIM_EINVAL, SIM_EROUTE, SIM_ENOMEM, SIM_EHIP, SIM_ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_vehicles",
-            "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_set_stream",
-            "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
+            "sim_grad", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place")
 
 
@@ -85,6 +85,10 @@ def library(path: str = LIB_PATH):
         lib.sim_set_timing.restype = ctypes.c_int
         lib.sim_read_timing.argtypes = [P, P, ctypes.POINTER(ctypes.c_int64)]
         lib.sim_read_timing.restype = ctypes.c_int
+        lib.sim_tape_begin.argtypes = [P, i32]
+        lib.sim_tape_begin.restype = ctypes.c_int
+        lib.sim_grad.argtypes = [P, P, P]
+        lib.sim_grad.restype = ctypes.c_int
         lib.sim_set_stream.argtypes = [P, P]
         lib.sim_set_stream.restype = ctypes.c_int
         lib.sim_destroy.argtypes = [P]
@@ -248,6 +252,32 @@ class Sim:
         n = ctypes.c_int64(0)
         self._check(self.lib.sim_read_timing(self.h, _p(ms), ctypes.byref(n)))
         return dict(zip(KERNELS, ms.tolist())), int(n.value)
+
+    def tape_begin(self, checkpoint_every: int = 60):
+        """Start a differentiation window at the current step."""
+        self._check(self.lib.sim_tape_begin(self.h, int(checkpoint_every)))
+
+    def mean_travel_times(self):
+        """Mean crossing-interpolated travel time per link in seconds (torch
+        float32 on the device; 0 where no traversal was completed) and the
+        traversal counts."""
+        import torch
+        st = self.edge_stats_device()
+        cnt = st["count"]
+        with torch.cuda.stream(self.stream):
+            tbar = torch.where(cnt > 0, st["tt_us"].double() / cnt.clamp(min=1).double() / 1e6,
+                               torch.zeros((), dtype=torch.float64, device=cnt.device)).float()
+        return tbar, cnt
+
+    def grad(self, dL_dmeanTT):
+        """dLoss/dtheta [num_classes, 4] (torch float32, device) for the window
+        since tape_begin, given dLoss/d(mean link travel time) [num_edges]."""
+        import torch
+        g = dL_dmeanTT.detach().to(device="cuda:%d" % self.device, dtype=torch.float32).contiguous()
+        out = torch.empty(self.num_classes * 4, dtype=torch.float32, device=g.device)
+        with torch.cuda.stream(self.stream):
+            self._check(self.lib.sim_grad(self.h, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out.view(self.num_classes, 4)
 
     def set_idm(self, idm):
         idm = np.ascontiguousarray(idm, np.float32).reshape(self.num_classes, 4)

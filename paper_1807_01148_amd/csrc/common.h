@@ -1,0 +1,313 @@
+// Device-side data structures and helpers shared by the step kernels and the
+// adjoint kernels of libtrafficsim (included once, by trafficsim.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tsim {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kLcNone = -(1 << 30);
+constexpr int kMaxGrid = 2048;
+
+enum : int { kCross = 1, kChange = 2, kInsert = 3 };
+
+// ---------------------------------------------------------------------------
+// device-side data
+// ---------------------------------------------------------------------------
+struct Counters {
+    int t;           // current step
+    int n;           // vehicles on the road (entries of the current buffer)
+    int npend;       // carried insertion candidates (current pending buffer)
+    int nclaim;      // claims this step
+    int nmove;       // winning claims this step
+    int npend_next;  // candidates carried to the next step
+    int n_next;      // entries of the next buffer
+    unsigned scan_tile;
+    unsigned done_blocks;
+    int pad;
+    unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
+};
+
+struct Params {
+    float dt, h, lveh, s0, claim_len, s_eps, b_max, pol, athr, bsafe, dmand, dt_us_f;
+    long long dt_us;
+    int lc_cool;
+};
+
+struct Net {
+    const float* len;
+    const float* inv_v0;
+    const int* lane_base;
+    const int* lanes;
+    const int* cls;
+    const int* head;
+    const int* row_ptr;
+    const long long* cbase;  // first claim cell of lane 0 of the edge
+    const int* ncell;        // cells per lane = floor(len) + 1
+    const float* cT;
+    const float* cA;
+    const float* cKab;
+    const float* cVs;  // v0 scale per class (adjoint chain rule)
+    const float* cB;   // comfortable deceleration per class (adjoint chain rule)
+};
+
+struct Trips {
+    const int* route_edges;
+    const int* rbeg;
+    const int* rend;
+    const int* rel_off;  // rel_off[t] = first vehicle id due at step >= t
+    int rel_len;         // rel_off has rel_len + 1 entries
+    const unsigned char* placed;
+    int* depart_actual;
+    int* arrive_step;
+};
+
+struct Veh {
+    int* key;
+    float* x;
+    float* v;
+    int* edge;
+    int* rcur;
+    int* next;
+    int* lc;
+    int* kin;
+    float* phin;
+    int* vid;
+};
+
+struct Scratch {
+    float* xs;
+    float* vs;
+    unsigned char* stay;
+    int* mcnt;
+    int* cscan;
+    int* cl_vid;
+    int* cl_key;
+    int* cl_lo;
+    int* cl_hi;
+    int* cl_src;
+    int* cl_kind;
+    int* cl_tedge;
+    float* cl_X;
+    float* cl_v;
+    float* cl_f;
+    int* mv_claim;
+    int* mv_p;
+    int* mv_slot;
+    int* mv_g;
+    int* grp_key;
+    float* grp_X;
+    unsigned long long* cells;
+    unsigned long long* tile_status;
+    unsigned long long* st_cnt;
+    unsigned long long* st_steps;
+    unsigned long long* st_us;
+    unsigned* epoch;  // executed-step counter (claims and scan statuses are tagged with it)
+};
+
+// Event tape of one step (recorded during the adjoint's recompute pass): the
+// state and the discrete outcome of every entry of the sorted vehicle arrays.
+enum : int { kModeStay = 0, kModeChange = 1, kModeYield = 2, kModeArrive = 3, kModeCross = 4 };
+enum : int {
+    kFHasLead = 1, kFLeadCross = 2, kFDynFloor = 4, kFSFloor = 8, kFAccFloor = 16, kFStop = 32,
+    kFDxFloor = 64, kFClamp = 128, kFClampZero = 256, kFClampV = 512, kFFOne = 1024
+};
+
+struct Tape {
+    int on;
+    float* x;               // position and speed at the step
+    float* v;
+    int* vid;
+    int* edge;
+    int* lead;              // entry index of the vehicle ahead for the own-lane motion, or -1
+    int* clead;             // ... for the lane-change motion
+    int* next;              // entry index at the next step, -1 if the vehicle left
+    unsigned char* mode;
+    unsigned short* flags;  // branch flags of the own-lane motion
+    unsigned short* cflags; // ... of the lane-change motion
+    int* n;                 // number of entries
+};
+
+struct Lead {
+    int kind;  // 0 free road, 1 same link, 2 rearmost vehicle of the next link
+    float s;   // bumper-to-bumper gap
+    float vl;  // speed of the vehicle ahead
+    float xl;  // its position on its own link
+    int idx;   // its entry index in the sorted arrays
+};
+
+__device__ __forceinline__ int lead_flags(const Lead& L) {
+    return L.kind == 0 ? 0 : (kFHasLead | (L.kind == 2 ? kFLeadCross : 0));
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fmx(float a, float b) { return a > b ? a : b; }
+__device__ __forceinline__ float fmn(float a, float b) { return a < b ? a : b; }
+
+// IDM (Sec. 6.3.2, car-following equation, exponent 4): dynamic part of the
+// desired gap floored at 0, gap floored at s_eps, result floored at -b_max.
+__device__ __forceinline__ float idm_acc_fl(const Params& P, float A, float T, float kab, float iv,
+                                            float v, const Lead& L, int& fl) {
+    float r = v * iv;
+    float r2 = r * r;
+    float r4 = r2 * r2;
+    float fr = 1.0f - r4;
+    float acc;
+    if (L.kind == 0) {
+        acc = A * fr;
+    } else {
+        float dv = v - L.vl;
+        float dyn = v * T + (v * dv) * kab;
+        if (0.0f > dyn) fl |= kFDynFloor;
+        float ss = P.s0 + fmx(0.0f, dyn);
+        if (!(L.s > P.s_eps)) fl |= kFSFloor;
+        float q = ss / fmx(L.s, P.s_eps);
+        acc = A * (fr - q * q);
+    }
+    if (!(acc > -P.b_max)) fl |= kFAccFloor;
+    return fmx(acc, -P.b_max);
+}
+
+__device__ __forceinline__ float idm_acc(const Params& P, float A, float T, float kab, float iv,
+                                         float v, const Lead& L) {
+    int fl = 0;
+    return idm_acc_fl(P, A, T, kab, iv, v, L, fl);
+}
+
+// ballistic update; stop inside the step when the speed would turn negative
+__device__ __forceinline__ void kin_move_fl(const Params& P, float v, float acc, float& dx, float& vn,
+                                            int& fl) {
+    float vv = v + acc * P.dt;
+    if (vv < 0.0f) {
+        dx = (v * v) / (-2.0f * acc);
+        vn = 0.0f;
+        fl |= kFStop;
+    } else {
+        dx = v * P.dt + acc * P.h;
+        vn = vv;
+    }
+    if (!(dx > 0.0f)) fl |= kFDxFloor;
+    dx = fmx(dx, 0.0f);
+}
+
+__device__ __forceinline__ void kin_move(const Params& P, float v, float acc, float& dx, float& vn) {
+    int fl = 0;
+    kin_move_fl(P, v, acc, dx, vn, fl);
+}
+
+__device__ __forceinline__ int clamp_to_leader_fl(const Lead& L, float& dx, float& vn, int& fl) {
+    if (L.kind != 0 && dx > L.s) {
+        fl |= kFClamp;
+        if (!(L.s > 0.0f)) fl |= kFClampZero;
+        if (!(vn < L.vl)) fl |= kFClampV;
+        dx = fmx(L.s, 0.0f);
+        vn = fmn(vn, L.vl);
+        return 1;
+    }
+    return 0;
+}
+
+__device__ __forceinline__ int clamp_to_leader(const Lead& L, float& dx, float& vn) {
+    int fl = 0;
+    return clamp_to_leader_fl(L, dx, vn, fl);
+}
+
+__device__ __forceinline__ Lead relead(const Params& P, float len, const Lead& L, float xf) {
+    Lead R = L;
+    if (L.kind == 1) R.s = (L.xl - P.lveh) - xf;
+    else if (L.kind == 2) R.s = (len - xf) + (L.xl - P.lveh);
+    return R;
+}
+
+// first j in [lo, hi) with key[j] >= k
+__device__ __forceinline__ int lb_key(const int* __restrict__ key, int lo, int hi, int k) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (key[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first j in [lo, hi) with (key[j], x[j]) >= (k, X)
+__device__ __forceinline__ int lb_keyx(const int* __restrict__ key, const float* __restrict__ x, int lo,
+                                       int hi, int k, float X) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int km = key[mid];
+        if (km < k || (km == k && x[mid] < X)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first j in [lo, hi) with (key[j], x[j]) > (k, X)
+__device__ __forceinline__ int ub_keyx(const int* __restrict__ key, const float* __restrict__ x, int lo,
+                                       int hi, int k, float X) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int km = key[mid];
+        if (km < k || (km == k && x[mid] <= X)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// claims of a later executed step always beat those of an earlier one
+__device__ __forceinline__ unsigned long long epoch_tag(unsigned epoch) {
+    return (unsigned long long)(0xFFFFFFFFu - epoch) << 32;
+}
+
+__device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, float X, int& lo,
+                                            int& hi) {
+    int a = (int)floorf(X - P.claim_len);
+    int b = (int)floorf(X);
+    int nc = net.ncell[edge];
+    lo = a < 0 ? 0 : a;
+    hi = b > nc - 1 ? nc - 1 : b;
+}
+
+__device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Counters* ctr,
+                                           unsigned long long tag, int vid, int kind, int src,
+                                           int tedge, int tlane, float X, float vc, float f, int lo,
+                                           int hi) {
+    int ci = atomicAdd(&ctr->nclaim, 1);
+    s.cl_vid[ci] = vid;
+    s.cl_key[ci] = net.lane_base[tedge] + tlane;
+    s.cl_lo[ci] = lo;
+    s.cl_hi[ci] = hi;
+    s.cl_src[ci] = src;
+    s.cl_kind[ci] = kind;
+    s.cl_tedge[ci] = tedge;
+    s.cl_X[ci] = X;
+    s.cl_v[ci] = vc;
+    s.cl_f[ci] = f;
+    unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tlane * net.ncell[tedge];
+    unsigned long long mine = tag | (unsigned)vid;
+    for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
+}
+
+__device__ __forceinline__ void record_exit(const Params& P, const Scratch& s, int edge, int kin,
+                                            float phin, float f, int t) {
+    long long ns = (long long)(t + 1) - kin;
+    float frac = f - phin;
+    long long us = ns * P.dt_us + (long long)rintf(frac * P.dt_us_f);
+    atomicAdd(s.st_cnt + edge, 1ull);
+    atomicAdd(s.st_steps + edge, (unsigned long long)ns);
+    atomicAdd(s.st_us + edge, (unsigned long long)us);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+}  // namespace tsim

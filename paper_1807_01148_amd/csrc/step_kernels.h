@@ -1,0 +1,523 @@
+// The kernels of one synchronous simulation step (included once, by
+// trafficsim.hip).  See trafficsim.hip for the overview.
+#pragma once
+
+#include "common.h"
+
+namespace tsim {
+// ---------------------------------------------------------------------------
+// k_decide
+// ---------------------------------------------------------------------------
+__device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
+                               const Scratch& s, const Tape& tp, Counters* ctr, int N, int t,
+                               unsigned long long tag, int i, int& clamps, int& arrivals) {
+    const int k = in.key[i];
+    const float x = in.x[i];
+    const float v = in.v[i];
+    const int e = in.edge[i];
+    const int nx = in.next[i];
+    const float len = net.len[e];
+    const float iv = net.inv_v0[e];
+    const int c = net.cls[e];
+    const float A = net.cA[c], T = net.cT[c], kab = net.cKab[c];
+    const int lb = net.lane_base[e];
+    const int l = k - lb;
+
+    // own leader: next element of the lane, else the rearmost vehicle of the
+    // mapped lane of the next link of the route
+    Lead L = {0, 0.0f, 0.0f, 0.0f, -1};
+    if (i + 1 < N && in.key[i + 1] == k) {
+        float xl = in.x[i + 1];
+        L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.s = (xl - P.lveh) - x; L.idx = i + 1;
+    } else if (nx >= 0) {
+        int nl2 = net.lanes[nx];
+        int k2 = net.lane_base[nx] + (l < nl2 - 1 ? l : nl2 - 1);
+        int j = lb_key(in.key, 0, N, k2);
+        if (j < N && in.key[j] == k2) {
+            float xl = in.x[j];
+            L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.s = (len - x) + (xl - P.lveh); L.idx = j;
+        }
+    }
+    int own_fl = lead_flags(L);
+    const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
+    float dx, vn;
+    kin_move_fl(P, v, ac, dx, vn, own_fl);
+    clamps += clamp_to_leader_fl(L, dx, vn, own_fl);
+    const float xs = x + dx;
+    const int vid = in.vid[i];
+    if (tp.on) {
+        tp.x[i] = x;
+        tp.v[i] = v;
+        tp.vid[i] = vid;
+        tp.edge[i] = e;
+        tp.lead[i] = L.idx;
+        tp.clead[i] = -1;
+        tp.cflags[i] = 0;
+        tp.next[i] = -1;
+        tp.mode[i] = kModeStay;
+    }
+
+    if (xs > len) {  // the front passes the link end strictly
+        float fq = (len - x) / dx;
+        if (!(fq < 1.0f)) own_fl |= kFFOne;
+        float f = dx > 0.0f ? fmn(fq, 1.0f) : 0.0f;
+        if (tp.on) {
+            tp.flags[i] = (unsigned short)own_fl;
+            tp.mode[i] = nx < 0 ? kModeArrive : kModeCross;
+        }
+        if (nx < 0) {  // arrival at the end of the last link
+            record_exit(P, s, e, in.kin[i], in.phin[i], f, t);
+            tr.arrive_step[vid] = t + 1;
+            s.stay[i] = 0;
+            arrivals += 1;
+            return;
+        }
+        int nl2 = net.lanes[nx];
+        int tl = l < nl2 - 1 ? l : nl2 - 1;
+        float X = xs - len;
+        int lo, hi;
+        claim_cells(P, net, nx, X, lo, hi);
+        s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
+        s.vs[i] = 0.0f;
+        s.stay[i] = 1;
+        push_claim(s, net, ctr, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
+        return;
+    }
+    s.xs[i] = xs;
+    s.vs[i] = vn;
+    s.stay[i] = 1;
+    if (tp.on) tp.flags[i] = (unsigned short)own_fl;
+
+    // lane change: eligibility
+    const int n = net.lanes[e];
+    if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < P.lveh) return;
+    int blo = 0, bhi = n - 1;
+    if (nx >= 0) {
+        int hn = net.head[e];
+        int r0 = net.row_ptr[hn];
+        int m = net.row_ptr[hn + 1] - r0;
+        int j = nx - r0;
+        blo = (j * n) / m;
+        bhi = ((j + 1) * n + m - 1) / m - 1;
+        if (bhi < blo) bhi = blo;
+    }
+    const float d = len - x;
+    const bool inband = blo <= l && l <= bhi;
+    const bool mand = !inband && d <= P.dmand;
+    int cand[2];
+    int nc = 0;
+    if (mand) {
+        cand[nc++] = l < blo ? l + 1 : l - 1;
+    } else {
+        for (int sd = l - 1; sd <= l + 1; sd += 2) {
+            if (sd < 0 || sd >= n) continue;
+            if (inband && d <= P.dmand && (sd < blo || sd > bhi)) continue;
+            cand[nc++] = sd;
+        }
+    }
+    const bool hasF = i > 0 && in.key[i - 1] == k;
+    const float xF = hasF ? in.x[i - 1] : 0.0f;
+    const float vF = hasF ? in.v[i - 1] : 0.0f;
+
+    int best = -1, best_fl = 0, best_lead = -1;
+    float best_inc = 0.0f, best_X = 0.0f, best_v = 0.0f;
+    for (int ci = 0; ci < nc; ++ci) {
+        const int lt = cand[ci];
+        const int kt = lb + lt;
+        // first vehicle of the target lane strictly ahead; the one before it
+        // (position <= x) is the lag
+        int j = lt > l ? ub_keyx(in.key, in.x, i + 1, N, kt, x) : ub_keyx(in.key, in.x, 0, i, kt, x);
+        Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1};
+        if (j < N && in.key[j] == kt) {
+            float xl = in.x[j];
+            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.s = (xl - P.lveh) - x; Lt.idx = j;
+        } else if (nx >= 0) {
+            int nl2 = net.lanes[nx];
+            int k2 = net.lane_base[nx] + (lt < nl2 - 1 ? lt : nl2 - 1);
+            int j2 = lb_key(in.key, 0, N, k2);
+            if (j2 < N && in.key[j2] == k2) {
+                float xl = in.x[j2];
+                Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.s = (len - x) + (xl - P.lveh); Lt.idx = j2;
+            }
+        }
+        const bool hasFt = j > 0 && in.key[j - 1] == kt;
+        const float xFt = hasFt ? in.x[j - 1] : 0.0f;
+        const float vFt = hasFt ? in.v[j - 1] : 0.0f;
+        // gap acceptance (Sec. 6.3.2)
+        if (Lt.kind != 0 && Lt.s < P.s0) continue;
+        if (hasFt && ((x - P.lveh) - xFt) < P.s0) continue;
+        int tfl = lead_flags(Lt);
+        const float at = idm_acc_fl(P, A, T, kab, iv, v, Lt, tfl);
+        if (at < -P.bsafe) continue;
+        float dxt, vt;
+        kin_move_fl(P, v, at, dxt, vt, tfl);
+        clamp_to_leader_fl(Lt, dxt, vt, tfl);
+        const float Xt = x + dxt;
+        if (Xt >= len) continue;
+        float an = 0.0f, ant = 0.0f;
+        if (hasFt) {
+            an = idm_acc(P, A, T, kab, iv, vFt, relead(P, len, Lt, xFt));
+            Lead Li = {1, (x - P.lveh) - xFt, v, x, i};
+            ant = idm_acc(P, A, T, kab, iv, vFt, Li);
+            if (ant < -P.bsafe) continue;
+            Lead none = {0, 0.0f, 0.0f, 0.0f, -1};
+            float afree = idm_acc(P, A, T, kab, iv, vFt, none);
+            float dxF, vF2;
+            kin_move(P, vFt, afree, dxF, vF2);
+            if (((Xt - P.lveh) - xFt) < dxF) continue;
+        }
+        float inc = 0.0f;
+        if (!mand) {
+            float d1 = at - ac;
+            float d2 = hasFt ? (ant - an) : 0.0f;
+            float d3 = 0.0f;
+            if (hasF) {
+                Lead Lo = {1, (x - P.lveh) - xF, v, x, i};
+                float ao = idm_acc(P, A, T, kab, iv, vF, Lo);
+                float aot = idm_acc(P, A, T, kab, iv, vF, relead(P, len, L, xF));
+                d3 = aot - ao;
+            }
+            inc = d1 + P.pol * (d2 + d3);
+            if (!(inc > P.athr)) continue;
+        }
+        if (best < 0 || inc > best_inc) {
+            best = lt; best_inc = inc; best_X = Xt; best_v = vt;
+            best_fl = tfl; best_lead = Lt.idx;
+        }
+    }
+    if (best >= 0) {
+        if (tp.on) {
+            tp.mode[i] = kModeChange;
+            tp.cflags[i] = (unsigned short)best_fl;
+            tp.clead[i] = best_lead;
+        }
+        int lo, hi;
+        claim_cells(P, net, e, best_X, lo, hi);
+        push_claim(s, net, ctr, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+    }
+}
+
+__device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, const Veh& in,
+                              const Scratch& s, Counters* ctr, int* pend_out, int N,
+                              unsigned long long tag, int vid) {
+    if (tr.placed[vid]) return;
+    const int e0 = tr.route_edges[tr.rbeg[vid]];
+    const int n0 = net.lanes[e0];
+    const int lb = net.lane_base[e0];
+    const float len0 = net.len[e0];
+    int j = lb_key(in.key, 0, N, lb);
+    int best = -1;
+    float bsp = 0.0f;
+    for (int l = 0; l < n0; ++l) {
+        const int kk = lb + l;
+        while (j < N && in.key[j] < kk) ++j;
+        float sp = (j < N && in.key[j] == kk) ? (in.x[j] - P.lveh) : len0;
+        if (best < 0 || sp > bsp) { best = l; bsp = sp; }
+    }
+    if (bsp >= P.claim_len) {
+        int lo, hi;
+        claim_cells(P, net, e0, P.lveh, lo, hi);
+        push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.lveh, 0.0f, 1.0f, lo, hi);
+    } else {
+        pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
+                                                   const int* __restrict__ pend_in, int* pend_out,
+                                                   Counters* ctr) {
+    const int t = ctr->t;
+    const int N = ctr->n;
+    const int np = ctr->npend;
+    int rlo = 0, rhi = 0;
+    if (t < tr.rel_len) {
+        rlo = tr.rel_off[t];
+        rhi = tr.rel_off[t + 1];
+    }
+    const int total = N + np + (rhi - rlo);
+    const unsigned long long tag = epoch_tag(*s.epoch);
+    int clamps = 0, arrivals = 0;
+    if (tp.on && blockIdx.x == 0 && threadIdx.x == 0) *tp.n = N;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        if (i < N) {
+            decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, tag, i, clamps, arrivals);
+        } else {
+            int cidx = i - N;
+            int vid = cidx < np ? pend_in[cidx] : rlo + (cidx - np);
+            decide_insert(P, net, tr, in, s, ctr, pend_out, N, tag, vid);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
+    unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
+    unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (cw) atomicAdd(&ctr->clamps, cw);
+        if (aw) atomicAdd(&ctr->arrived, aw);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_resolve
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
+                                                    int* pend_out, Counters* ctr) {
+    const int t = ctr->t;
+    const int N = ctr->n;
+    const int C = ctr->nclaim;
+    const unsigned long long tag = epoch_tag(*s.epoch);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->scan_tile = 0;
+    int lost = 0, departed = 0;
+    for (int ci = blockIdx.x * kBlock + threadIdx.x; ci < C; ci += gridDim.x * kBlock) {
+        const int vid = s.cl_vid[ci];
+        const int tedge = s.cl_tedge[ci];
+        const int key = s.cl_key[ci];
+        const int tl = key - net.lane_base[tedge];
+        const unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tl * net.ncell[tedge];
+        const unsigned long long mine = tag | (unsigned)vid;
+        bool win = true;
+        for (int c = s.cl_lo[ci]; c <= s.cl_hi[ci]; ++c) {
+            if (cell[c] != mine) { win = false; break; }
+        }
+        const int kind = s.cl_kind[ci];
+        const int src = s.cl_src[ci];
+        if (tp.on && src >= 0) {
+            if (kind == kCross) tp.mode[src] = win ? kModeCross : kModeYield;
+            else tp.mode[src] = win ? kModeChange : kModeStay;
+        }
+        if (win) {
+            if (src >= 0) s.stay[src] = 0;
+            int m = atomicAdd(&ctr->nmove, 1);
+            s.mv_claim[m] = ci;
+            int p = lb_keyx(in.key, in.x, 0, N, key, s.cl_X[ci]);
+            s.mv_p[m] = p;
+            s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
+            if (kind == kCross) record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
+            if (kind == kInsert) {
+                tr.depart_actual[vid] = t + 1;
+                departed += 1;
+            }
+        } else {
+            lost += 1;
+            if (kind == kInsert) pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
+        }
+    }
+    unsigned long long lw = wave_sum_u64((unsigned long long)lost);
+    unsigned long long dw = wave_sum_u64((unsigned long long)departed);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (lw) atomicAdd(&ctr->claims_lost, lw);
+        if (dw) atomicAdd(&ctr->departed, dw);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_scan: exclusive scan of w[i] = stay[i] + mcnt[i], i in [0, N], single pass
+// with decoupled look-back; tiles are handed out in order by an atomic counter
+// so a tile only ever waits on tiles already being processed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int block_excl_scan(int v, int& total) {
+    __shared__ int ws[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    int inc = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) ws[w] = inc;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) {
+        if (q < w) pre += ws[q];
+        tot += ws[q];
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - v;
+}
+
+constexpr unsigned long long kFlagA = 1ull, kFlagP = 2ull;
+
+__device__ __forceinline__ unsigned long long pack_status(unsigned ep, unsigned long long flag, int val) {
+    return ((unsigned long long)ep << 34) | (flag << 32) | (unsigned)val;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
+    const int N = ctr->n;
+    const int total = N + 1;
+    const int ntiles = (total + kScanTile - 1) / kScanTile;
+    const unsigned ep = (*s.epoch % 0x3FFFFFFFu) + 1u;
+    __shared__ int s_tile;
+    __shared__ int s_prefix;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr->scan_tile, 1u);
+        __syncthreads();
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        const int base = tile * kScanTile + threadIdx.x * kScanItems;
+        int vals[kScanItems];
+        int tsum = 0;
+        for (int q = 0; q < kScanItems; ++q) {
+            int idx = base + q;
+            int w = 0;
+            if (idx < total) w = s.mcnt[idx] + (idx < N ? (int)s.stay[idx] : 0);
+            vals[q] = w;
+            tsum += w;
+        }
+        int agg;
+        int excl = block_excl_scan(tsum, agg);
+        if (threadIdx.x == 0) {
+            int prefix = 0;
+            if (tile == 0) {
+                __hip_atomic_store(&s.tile_status[0], pack_status(ep, kFlagP, agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagA, agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                int j = tile - 1;
+                for (;;) {
+                    unsigned long long st = __hip_atomic_load(&s.tile_status[j], __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                    unsigned sep = (unsigned)(st >> 34);
+                    unsigned long long flag = (st >> 32) & 3ull;
+                    if (sep != ep || flag == 0ull) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    prefix += (int)(unsigned)(st & 0xFFFFFFFFull);
+                    if (flag == kFlagP) break;
+                    --j;
+                }
+                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagP, prefix + agg),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_prefix = prefix;
+            if (tile == ntiles - 1) ctr->n_next = prefix + agg;
+        }
+        __syncthreads();
+        int run = s_prefix + excl;
+        for (int q = 0; q < kScanItems; ++q) {
+            int idx = base + q;
+            if (idx < total) s.cscan[idx] = run;
+            run += vals[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_scatter: survivors to their new slot; movers stage their sort keys
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
+    const int N = ctr->n;
+    const int M = ctr->nmove;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N + M; i += gridDim.x * kBlock) {
+        if (i < N) {
+            if (!s.stay[i]) continue;
+            const int j = s.cscan[i] + s.mcnt[i];
+            if (tp.on) tp.next[i] = j;
+            out.key[j] = in.key[i];
+            out.x[j] = s.xs[i];
+            out.v[j] = s.vs[i];
+            out.edge[j] = in.edge[i];
+            out.rcur[j] = in.rcur[i];
+            out.next[j] = in.next[i];
+            out.lc[j] = in.lc[i];
+            out.kin[j] = in.kin[i];
+            out.phin[j] = in.phin[i];
+            out.vid[j] = in.vid[i];
+        } else {
+            const int m = i - N;
+            const int p = s.mv_p[m];
+            const int ci = s.mv_claim[m];
+            const int b = s.cscan[p];
+            s.mv_g[m] = s.mcnt[p];
+            s.grp_key[b + s.mv_slot[m]] = s.cl_key[ci];
+            s.grp_X[b + s.mv_slot[m]] = s.cl_X[ci];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_place: movers take their rank inside their gap; last block finalises
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scratch s, Tape tp, int lc_none,
+                                                  Counters* ctr) {
+    const int t = ctr->t;
+    const int M = ctr->nmove;
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+        const int ci = s.mv_claim[m];
+        const int p = s.mv_p[m];
+        const int b = s.cscan[p];
+        const int g = s.mv_g[m];
+        const int key = s.cl_key[ci];
+        const float X = s.cl_X[ci];
+        int r = 0;
+        if (g > 1) {
+            for (int q = 0; q < g; ++q) {
+                int kq = s.grp_key[b + q];
+                if (kq < key || (kq == key && s.grp_X[b + q] < X)) ++r;
+            }
+        }
+        const int j = b + r;
+        const int kind = s.cl_kind[ci];
+        const int src = s.cl_src[ci];
+        const int vid = s.cl_vid[ci];
+        if (tp.on && src >= 0) tp.next[src] = j;
+        out.key[j] = key;
+        out.x[j] = X;
+        out.v[j] = s.cl_v[ci];
+        out.edge[j] = s.cl_tedge[ci];
+        out.vid[j] = vid;
+        if (kind == kCross) {
+            const int rc = in.rcur[src] + 1;
+            out.rcur[j] = rc;
+            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
+            out.lc[j] = in.lc[src];
+            out.kin[j] = t + 1;
+            out.phin[j] = s.cl_f[ci];
+        } else if (kind == kChange) {
+            out.rcur[j] = in.rcur[src];
+            out.next[j] = in.next[src];
+            out.lc[j] = t;
+            out.kin[j] = in.kin[src];
+            out.phin[j] = in.phin[src];
+        } else {
+            const int rc = tr.rbeg[vid];
+            out.rcur[j] = rc;
+            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
+            out.lc[j] = lc_none;
+            out.kin[j] = t + 1;
+            out.phin[j] = 1.0f;
+        }
+        s.mcnt[p] = 0;
+    }
+    // last block to finish advances the step
+    __syncthreads();
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(&ctr->done_blocks, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        ctr->updates += (unsigned long long)ctr->n;
+        ctr->claims += (unsigned long long)ctr->nclaim;
+        ctr->n = ctr->n_next;
+        ctr->npend = ctr->npend_next;
+        ctr->npend_next = 0;
+        ctr->nclaim = 0;
+        ctr->nmove = 0;
+        ctr->done_blocks = 0;
+        ctr->t = t + 1;
+        *s.epoch += 1u;
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+}  // namespace tsim

@@ -40,735 +40,12 @@
 
 #include "trafficsim.h"
 
-namespace {
+#include "common.h"
+#include "step_kernels.h"
+#include "adjoint_kernels.h"
 
-constexpr int kBlock = 256;
-constexpr int kWave = 64;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kLcNone = -(1 << 30);
-constexpr int kMaxGrid = 2048;
+using namespace tsim;
 
-enum : int { kCross = 1, kChange = 2, kInsert = 3 };
-
-// ---------------------------------------------------------------------------
-// device-side data
-// ---------------------------------------------------------------------------
-struct Counters {
-    int t;           // current step
-    int n;           // vehicles on the road (entries of the current buffer)
-    int npend;       // carried insertion candidates (current pending buffer)
-    int nclaim;      // claims this step
-    int nmove;       // winning claims this step
-    int npend_next;  // candidates carried to the next step
-    int n_next;      // entries of the next buffer
-    unsigned scan_tile;
-    unsigned done_blocks;
-    int pad;
-    unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
-};
-
-struct Params {
-    float dt, h, lveh, s0, claim_len, s_eps, b_max, pol, athr, bsafe, dmand, dt_us_f;
-    long long dt_us;
-    int lc_cool;
-};
-
-struct Net {
-    const float* len;
-    const float* inv_v0;
-    const int* lane_base;
-    const int* lanes;
-    const int* cls;
-    const int* head;
-    const int* row_ptr;
-    const long long* cbase;  // first claim cell of lane 0 of the edge
-    const int* ncell;        // cells per lane = floor(len) + 1
-    const float* cT;
-    const float* cA;
-    const float* cKab;
-};
-
-struct Trips {
-    const int* route_edges;
-    const int* rbeg;
-    const int* rend;
-    const int* rel_off;  // rel_off[t] = first vehicle id due at step >= t
-    int rel_len;         // rel_off has rel_len + 1 entries
-    const unsigned char* placed;
-    int* depart_actual;
-    int* arrive_step;
-};
-
-struct Veh {
-    int* key;
-    float* x;
-    float* v;
-    int* edge;
-    int* rcur;
-    int* next;
-    int* lc;
-    int* kin;
-    float* phin;
-    int* vid;
-};
-
-struct Scratch {
-    float* xs;
-    float* vs;
-    unsigned char* stay;
-    int* mcnt;
-    int* cscan;
-    int* cl_vid;
-    int* cl_key;
-    int* cl_lo;
-    int* cl_hi;
-    int* cl_src;
-    int* cl_kind;
-    int* cl_tedge;
-    float* cl_X;
-    float* cl_v;
-    float* cl_f;
-    int* mv_claim;
-    int* mv_p;
-    int* mv_slot;
-    int* mv_g;
-    int* grp_key;
-    float* grp_X;
-    unsigned long long* cells;
-    unsigned long long* tile_status;
-    unsigned long long* st_cnt;
-    unsigned long long* st_steps;
-    unsigned long long* st_us;
-};
-
-struct Lead {
-    int kind;  // 0 free road, 1 same link, 2 rearmost vehicle of the next link
-    float s;   // bumper-to-bumper gap
-    float vl;  // speed of the vehicle ahead
-    float xl;  // its position on its own link
-};
-
-// ---------------------------------------------------------------------------
-// device helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float fmx(float a, float b) { return a > b ? a : b; }
-__device__ __forceinline__ float fmn(float a, float b) { return a < b ? a : b; }
-
-// IDM (Sec. 6.3.2, car-following equation, exponent 4): dynamic part of the
-// desired gap floored at 0, gap floored at s_eps, result floored at -b_max.
-__device__ __forceinline__ float idm_acc(const Params& P, float A, float T, float kab, float iv,
-                                         float v, const Lead& L) {
-    float r = v * iv;
-    float r2 = r * r;
-    float r4 = r2 * r2;
-    float fr = 1.0f - r4;
-    float acc;
-    if (L.kind == 0) {
-        acc = A * fr;
-    } else {
-        float dv = v - L.vl;
-        float dyn = v * T + (v * dv) * kab;
-        float ss = P.s0 + fmx(0.0f, dyn);
-        float q = ss / fmx(L.s, P.s_eps);
-        acc = A * (fr - q * q);
-    }
-    return fmx(acc, -P.b_max);
-}
-
-// ballistic update; stop inside the step when the speed would turn negative
-__device__ __forceinline__ void kin_move(const Params& P, float v, float acc, float& dx, float& vn) {
-    float vv = v + acc * P.dt;
-    if (vv < 0.0f) {
-        dx = (v * v) / (-2.0f * acc);
-        vn = 0.0f;
-    } else {
-        dx = v * P.dt + acc * P.h;
-        vn = vv;
-    }
-    dx = fmx(dx, 0.0f);
-}
-
-__device__ __forceinline__ int clamp_to_leader(const Lead& L, float& dx, float& vn) {
-    if (L.kind != 0 && dx > L.s) {
-        dx = fmx(L.s, 0.0f);
-        vn = fmn(vn, L.vl);
-        return 1;
-    }
-    return 0;
-}
-
-__device__ __forceinline__ Lead relead(const Params& P, float len, const Lead& L, float xf) {
-    Lead R = L;
-    if (L.kind == 1) R.s = (L.xl - P.lveh) - xf;
-    else if (L.kind == 2) R.s = (len - xf) + (L.xl - P.lveh);
-    return R;
-}
-
-// first j in [lo, hi) with key[j] >= k
-__device__ __forceinline__ int lb_key(const int* __restrict__ key, int lo, int hi, int k) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (key[mid] < k) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// first j in [lo, hi) with (key[j], x[j]) >= (k, X)
-__device__ __forceinline__ int lb_keyx(const int* __restrict__ key, const float* __restrict__ x, int lo,
-                                       int hi, int k, float X) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        int km = key[mid];
-        if (km < k || (km == k && x[mid] < X)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// first j in [lo, hi) with (key[j], x[j]) > (k, X)
-__device__ __forceinline__ int ub_keyx(const int* __restrict__ key, const float* __restrict__ x, int lo,
-                                       int hi, int k, float X) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        int km = key[mid];
-        if (km < k || (km == k && x[mid] <= X)) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ unsigned long long epoch_tag(int t) {
-    return (unsigned long long)(0xFFFFFFFFu - (unsigned)t) << 32;
-}
-
-__device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, float X, int& lo,
-                                            int& hi) {
-    int a = (int)floorf(X - P.claim_len);
-    int b = (int)floorf(X);
-    int nc = net.ncell[edge];
-    lo = a < 0 ? 0 : a;
-    hi = b > nc - 1 ? nc - 1 : b;
-}
-
-__device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Counters* ctr,
-                                           unsigned long long tag, int vid, int kind, int src,
-                                           int tedge, int tlane, float X, float vc, float f, int lo,
-                                           int hi) {
-    int ci = atomicAdd(&ctr->nclaim, 1);
-    s.cl_vid[ci] = vid;
-    s.cl_key[ci] = net.lane_base[tedge] + tlane;
-    s.cl_lo[ci] = lo;
-    s.cl_hi[ci] = hi;
-    s.cl_src[ci] = src;
-    s.cl_kind[ci] = kind;
-    s.cl_tedge[ci] = tedge;
-    s.cl_X[ci] = X;
-    s.cl_v[ci] = vc;
-    s.cl_f[ci] = f;
-    unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tlane * net.ncell[tedge];
-    unsigned long long mine = tag | (unsigned)vid;
-    for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
-}
-
-__device__ __forceinline__ void record_exit(const Params& P, const Scratch& s, int edge, int kin,
-                                            float phin, float f, int t) {
-    long long ns = (long long)(t + 1) - kin;
-    float frac = f - phin;
-    long long us = ns * P.dt_us + (long long)rintf(frac * P.dt_us_f);
-    atomicAdd(s.st_cnt + edge, 1ull);
-    atomicAdd(s.st_steps + edge, (unsigned long long)ns);
-    atomicAdd(s.st_us + edge, (unsigned long long)us);
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// k_decide
-// ---------------------------------------------------------------------------
-__device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                               const Scratch& s, Counters* ctr, int N, int t,
-                               unsigned long long tag, int i, int& clamps, int& arrivals) {
-    const int k = in.key[i];
-    const float x = in.x[i];
-    const float v = in.v[i];
-    const int e = in.edge[i];
-    const int nx = in.next[i];
-    const float len = net.len[e];
-    const float iv = net.inv_v0[e];
-    const int c = net.cls[e];
-    const float A = net.cA[c], T = net.cT[c], kab = net.cKab[c];
-    const int lb = net.lane_base[e];
-    const int l = k - lb;
-
-    // own leader: next element of the lane, else the rearmost vehicle of the
-    // mapped lane of the next link of the route
-    Lead L = {0, 0.0f, 0.0f, 0.0f};
-    if (i + 1 < N && in.key[i + 1] == k) {
-        float xl = in.x[i + 1];
-        L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.s = (xl - P.lveh) - x;
-    } else if (nx >= 0) {
-        int nl2 = net.lanes[nx];
-        int k2 = net.lane_base[nx] + (l < nl2 - 1 ? l : nl2 - 1);
-        int j = lb_key(in.key, 0, N, k2);
-        if (j < N && in.key[j] == k2) {
-            float xl = in.x[j];
-            L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.s = (len - x) + (xl - P.lveh);
-        }
-    }
-    const float ac = idm_acc(P, A, T, kab, iv, v, L);
-    float dx, vn;
-    kin_move(P, v, ac, dx, vn);
-    clamps += clamp_to_leader(L, dx, vn);
-    const float xs = x + dx;
-    const int vid = in.vid[i];
-
-    if (xs > len) {  // the front passes the link end strictly
-        float f = dx > 0.0f ? fmn((len - x) / dx, 1.0f) : 0.0f;
-        if (nx < 0) {  // arrival at the end of the last link
-            record_exit(P, s, e, in.kin[i], in.phin[i], f, t);
-            tr.arrive_step[vid] = t + 1;
-            s.stay[i] = 0;
-            arrivals += 1;
-            return;
-        }
-        int nl2 = net.lanes[nx];
-        int tl = l < nl2 - 1 ? l : nl2 - 1;
-        float X = xs - len;
-        int lo, hi;
-        claim_cells(P, net, nx, X, lo, hi);
-        s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
-        s.vs[i] = 0.0f;
-        s.stay[i] = 1;
-        push_claim(s, net, ctr, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
-        return;
-    }
-    s.xs[i] = xs;
-    s.vs[i] = vn;
-    s.stay[i] = 1;
-
-    // lane change: eligibility
-    const int n = net.lanes[e];
-    if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < P.lveh) return;
-    int blo = 0, bhi = n - 1;
-    if (nx >= 0) {
-        int hn = net.head[e];
-        int r0 = net.row_ptr[hn];
-        int m = net.row_ptr[hn + 1] - r0;
-        int j = nx - r0;
-        blo = (j * n) / m;
-        bhi = ((j + 1) * n + m - 1) / m - 1;
-        if (bhi < blo) bhi = blo;
-    }
-    const float d = len - x;
-    const bool inband = blo <= l && l <= bhi;
-    const bool mand = !inband && d <= P.dmand;
-    int cand[2];
-    int nc = 0;
-    if (mand) {
-        cand[nc++] = l < blo ? l + 1 : l - 1;
-    } else {
-        for (int sd = l - 1; sd <= l + 1; sd += 2) {
-            if (sd < 0 || sd >= n) continue;
-            if (inband && d <= P.dmand && (sd < blo || sd > bhi)) continue;
-            cand[nc++] = sd;
-        }
-    }
-    const bool hasF = i > 0 && in.key[i - 1] == k;
-    const float xF = hasF ? in.x[i - 1] : 0.0f;
-    const float vF = hasF ? in.v[i - 1] : 0.0f;
-
-    int best = -1;
-    float best_inc = 0.0f, best_X = 0.0f, best_v = 0.0f;
-    for (int ci = 0; ci < nc; ++ci) {
-        const int lt = cand[ci];
-        const int kt = lb + lt;
-        // first vehicle of the target lane strictly ahead; the one before it
-        // (position <= x) is the lag
-        int j = lt > l ? ub_keyx(in.key, in.x, i + 1, N, kt, x) : ub_keyx(in.key, in.x, 0, i, kt, x);
-        Lead Lt = {0, 0.0f, 0.0f, 0.0f};
-        if (j < N && in.key[j] == kt) {
-            float xl = in.x[j];
-            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.s = (xl - P.lveh) - x;
-        } else if (nx >= 0) {
-            int nl2 = net.lanes[nx];
-            int k2 = net.lane_base[nx] + (lt < nl2 - 1 ? lt : nl2 - 1);
-            int j2 = lb_key(in.key, 0, N, k2);
-            if (j2 < N && in.key[j2] == k2) {
-                float xl = in.x[j2];
-                Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.s = (len - x) + (xl - P.lveh);
-            }
-        }
-        const bool hasFt = j > 0 && in.key[j - 1] == kt;
-        const float xFt = hasFt ? in.x[j - 1] : 0.0f;
-        const float vFt = hasFt ? in.v[j - 1] : 0.0f;
-        // gap acceptance (Sec. 6.3.2)
-        if (Lt.kind != 0 && Lt.s < P.s0) continue;
-        if (hasFt && ((x - P.lveh) - xFt) < P.s0) continue;
-        const float at = idm_acc(P, A, T, kab, iv, v, Lt);
-        if (at < -P.bsafe) continue;
-        float dxt, vt;
-        kin_move(P, v, at, dxt, vt);
-        clamp_to_leader(Lt, dxt, vt);
-        const float Xt = x + dxt;
-        if (Xt >= len) continue;
-        float an = 0.0f, ant = 0.0f;
-        if (hasFt) {
-            an = idm_acc(P, A, T, kab, iv, vFt, relead(P, len, Lt, xFt));
-            Lead Li = {1, (x - P.lveh) - xFt, v, x};
-            ant = idm_acc(P, A, T, kab, iv, vFt, Li);
-            if (ant < -P.bsafe) continue;
-            Lead none = {0, 0.0f, 0.0f, 0.0f};
-            float afree = idm_acc(P, A, T, kab, iv, vFt, none);
-            float dxF, vF2;
-            kin_move(P, vFt, afree, dxF, vF2);
-            if (((Xt - P.lveh) - xFt) < dxF) continue;
-        }
-        float inc = 0.0f;
-        if (!mand) {
-            float d1 = at - ac;
-            float d2 = hasFt ? (ant - an) : 0.0f;
-            float d3 = 0.0f;
-            if (hasF) {
-                Lead Lo = {1, (x - P.lveh) - xF, v, x};
-                float ao = idm_acc(P, A, T, kab, iv, vF, Lo);
-                float aot = idm_acc(P, A, T, kab, iv, vF, relead(P, len, L, xF));
-                d3 = aot - ao;
-            }
-            inc = d1 + P.pol * (d2 + d3);
-            if (!(inc > P.athr)) continue;
-        }
-        if (best < 0 || inc > best_inc) {
-            best = lt; best_inc = inc; best_X = Xt; best_v = vt;
-        }
-    }
-    if (best >= 0) {
-        int lo, hi;
-        claim_cells(P, net, e, best_X, lo, hi);
-        push_claim(s, net, ctr, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
-    }
-}
-
-__device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                              const Scratch& s, Counters* ctr, int* pend_out, int N,
-                              unsigned long long tag, int vid) {
-    if (tr.placed[vid]) return;
-    const int e0 = tr.route_edges[tr.rbeg[vid]];
-    const int n0 = net.lanes[e0];
-    const int lb = net.lane_base[e0];
-    const float len0 = net.len[e0];
-    int j = lb_key(in.key, 0, N, lb);
-    int best = -1;
-    float bsp = 0.0f;
-    for (int l = 0; l < n0; ++l) {
-        const int kk = lb + l;
-        while (j < N && in.key[j] < kk) ++j;
-        float sp = (j < N && in.key[j] == kk) ? (in.x[j] - P.lveh) : len0;
-        if (best < 0 || sp > bsp) { best = l; bsp = sp; }
-    }
-    if (bsp >= P.claim_len) {
-        int lo, hi;
-        claim_cells(P, net, e0, P.lveh, lo, hi);
-        push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.lveh, 0.0f, 1.0f, lo, hi);
-    } else {
-        pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s,
-                                                   const int* __restrict__ pend_in, int* pend_out,
-                                                   Counters* ctr) {
-    const int t = ctr->t;
-    const int N = ctr->n;
-    const int np = ctr->npend;
-    int rlo = 0, rhi = 0;
-    if (t < tr.rel_len) {
-        rlo = tr.rel_off[t];
-        rhi = tr.rel_off[t + 1];
-    }
-    const int total = N + np + (rhi - rlo);
-    const unsigned long long tag = epoch_tag(t);
-    int clamps = 0, arrivals = 0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-        if (i < N) {
-            decide_vehicle(P, net, tr, in, s, ctr, N, t, tag, i, clamps, arrivals);
-        } else {
-            int cidx = i - N;
-            int vid = cidx < np ? pend_in[cidx] : rlo + (cidx - np);
-            decide_insert(P, net, tr, in, s, ctr, pend_out, N, tag, vid);
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
-    unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
-    unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (cw) atomicAdd(&ctr->clamps, cw);
-        if (aw) atomicAdd(&ctr->arrived, aw);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_resolve
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s,
-                                                    int* pend_out, Counters* ctr) {
-    const int t = ctr->t;
-    const int N = ctr->n;
-    const int C = ctr->nclaim;
-    const unsigned long long tag = epoch_tag(t);
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->scan_tile = 0;
-    int lost = 0, departed = 0;
-    for (int ci = blockIdx.x * kBlock + threadIdx.x; ci < C; ci += gridDim.x * kBlock) {
-        const int vid = s.cl_vid[ci];
-        const int tedge = s.cl_tedge[ci];
-        const int key = s.cl_key[ci];
-        const int tl = key - net.lane_base[tedge];
-        const unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tl * net.ncell[tedge];
-        const unsigned long long mine = tag | (unsigned)vid;
-        bool win = true;
-        for (int c = s.cl_lo[ci]; c <= s.cl_hi[ci]; ++c) {
-            if (cell[c] != mine) { win = false; break; }
-        }
-        const int kind = s.cl_kind[ci];
-        const int src = s.cl_src[ci];
-        if (win) {
-            if (src >= 0) s.stay[src] = 0;
-            int m = atomicAdd(&ctr->nmove, 1);
-            s.mv_claim[m] = ci;
-            int p = lb_keyx(in.key, in.x, 0, N, key, s.cl_X[ci]);
-            s.mv_p[m] = p;
-            s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
-            if (kind == kCross) record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
-            if (kind == kInsert) {
-                tr.depart_actual[vid] = t + 1;
-                departed += 1;
-            }
-        } else {
-            lost += 1;
-            if (kind == kInsert) pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
-        }
-    }
-    unsigned long long lw = wave_sum_u64((unsigned long long)lost);
-    unsigned long long dw = wave_sum_u64((unsigned long long)departed);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (lw) atomicAdd(&ctr->claims_lost, lw);
-        if (dw) atomicAdd(&ctr->departed, dw);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_scan: exclusive scan of w[i] = stay[i] + mcnt[i], i in [0, N], single pass
-// with decoupled look-back; tiles are handed out in order by an atomic counter
-// so a tile only ever waits on tiles already being processed.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int block_excl_scan(int v, int& total) {
-    __shared__ int ws[kBlock / kWave];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    int inc = v;
-    for (int o = 1; o < kWave; o <<= 1) {
-        int y = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += y;
-    }
-    if (lane == kWave - 1) ws[w] = inc;
-    __syncthreads();
-    int pre = 0, tot = 0;
-    for (int q = 0; q < kBlock / kWave; ++q) {
-        if (q < w) pre += ws[q];
-        tot += ws[q];
-    }
-    __syncthreads();
-    total = tot;
-    return pre + inc - v;
-}
-
-constexpr unsigned long long kFlagA = 1ull, kFlagP = 2ull;
-
-__device__ __forceinline__ unsigned long long pack_status(unsigned ep, unsigned long long flag, int val) {
-    return ((unsigned long long)ep << 34) | (flag << 32) | (unsigned)val;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
-    const int N = ctr->n;
-    const int total = N + 1;
-    const int ntiles = (total + kScanTile - 1) / kScanTile;
-    const unsigned ep = ((unsigned)ctr->t & 0x3FFFFFFFu) + 1u;
-    __shared__ int s_tile;
-    __shared__ int s_prefix;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr->scan_tile, 1u);
-        __syncthreads();
-        const int tile = s_tile;
-        __syncthreads();
-        if (tile >= ntiles) break;
-        const int base = tile * kScanTile + threadIdx.x * kScanItems;
-        int vals[kScanItems];
-        int tsum = 0;
-        for (int q = 0; q < kScanItems; ++q) {
-            int idx = base + q;
-            int w = 0;
-            if (idx < total) w = s.mcnt[idx] + (idx < N ? (int)s.stay[idx] : 0);
-            vals[q] = w;
-            tsum += w;
-        }
-        int agg;
-        int excl = block_excl_scan(tsum, agg);
-        if (threadIdx.x == 0) {
-            int prefix = 0;
-            if (tile == 0) {
-                __hip_atomic_store(&s.tile_status[0], pack_status(ep, kFlagP, agg), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagA, agg), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                int j = tile - 1;
-                for (;;) {
-                    unsigned long long st = __hip_atomic_load(&s.tile_status[j], __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                    unsigned sep = (unsigned)(st >> 34);
-                    unsigned long long flag = (st >> 32) & 3ull;
-                    if (sep != ep || flag == 0ull) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    prefix += (int)(unsigned)(st & 0xFFFFFFFFull);
-                    if (flag == kFlagP) break;
-                    --j;
-                }
-                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagP, prefix + agg),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            s_prefix = prefix;
-            if (tile == ntiles - 1) ctr->n_next = prefix + agg;
-        }
-        __syncthreads();
-        int run = s_prefix + excl;
-        for (int q = 0; q < kScanItems; ++q) {
-            int idx = base + q;
-            if (idx < total) s.cscan[idx] = run;
-            run += vals[q];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_scatter: survivors to their new slot; movers stage their sort keys
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, Counters* ctr) {
-    const int N = ctr->n;
-    const int M = ctr->nmove;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N + M; i += gridDim.x * kBlock) {
-        if (i < N) {
-            if (!s.stay[i]) continue;
-            const int j = s.cscan[i] + s.mcnt[i];
-            out.key[j] = in.key[i];
-            out.x[j] = s.xs[i];
-            out.v[j] = s.vs[i];
-            out.edge[j] = in.edge[i];
-            out.rcur[j] = in.rcur[i];
-            out.next[j] = in.next[i];
-            out.lc[j] = in.lc[i];
-            out.kin[j] = in.kin[i];
-            out.phin[j] = in.phin[i];
-            out.vid[j] = in.vid[i];
-        } else {
-            const int m = i - N;
-            const int p = s.mv_p[m];
-            const int ci = s.mv_claim[m];
-            const int b = s.cscan[p];
-            s.mv_g[m] = s.mcnt[p];
-            s.grp_key[b + s.mv_slot[m]] = s.cl_key[ci];
-            s.grp_X[b + s.mv_slot[m]] = s.cl_X[ci];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_place: movers take their rank inside their gap; last block finalises
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scratch s, int lc_none,
-                                                  Counters* ctr) {
-    const int t = ctr->t;
-    const int M = ctr->nmove;
-    for (int m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
-        const int ci = s.mv_claim[m];
-        const int p = s.mv_p[m];
-        const int b = s.cscan[p];
-        const int g = s.mv_g[m];
-        const int key = s.cl_key[ci];
-        const float X = s.cl_X[ci];
-        int r = 0;
-        if (g > 1) {
-            for (int q = 0; q < g; ++q) {
-                int kq = s.grp_key[b + q];
-                if (kq < key || (kq == key && s.grp_X[b + q] < X)) ++r;
-            }
-        }
-        const int j = b + r;
-        const int kind = s.cl_kind[ci];
-        const int src = s.cl_src[ci];
-        const int vid = s.cl_vid[ci];
-        out.key[j] = key;
-        out.x[j] = X;
-        out.v[j] = s.cl_v[ci];
-        out.edge[j] = s.cl_tedge[ci];
-        out.vid[j] = vid;
-        if (kind == kCross) {
-            const int rc = in.rcur[src] + 1;
-            out.rcur[j] = rc;
-            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
-            out.lc[j] = in.lc[src];
-            out.kin[j] = t + 1;
-            out.phin[j] = s.cl_f[ci];
-        } else if (kind == kChange) {
-            out.rcur[j] = in.rcur[src];
-            out.next[j] = in.next[src];
-            out.lc[j] = t;
-            out.kin[j] = in.kin[src];
-            out.phin[j] = in.phin[src];
-        } else {
-            const int rc = tr.rbeg[vid];
-            out.rcur[j] = rc;
-            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
-            out.lc[j] = lc_none;
-            out.kin[j] = t + 1;
-            out.phin[j] = 1.0f;
-        }
-        s.mcnt[p] = 0;
-    }
-    // last block to finish advances the step
-    __syncthreads();
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned prev = atomicAdd(&ctr->done_blocks, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        ctr->updates += (unsigned long long)ctr->n;
-        ctr->claims += (unsigned long long)ctr->nclaim;
-        ctr->n = ctr->n_next;
-        ctr->npend = ctr->npend_next;
-        ctr->npend_next = 0;
-        ctr->nclaim = 0;
-        ctr->nmove = 0;
-        ctr->done_blocks = 0;
-        ctr->t = t + 1;
-    }
-}
-
-__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
-    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
-        p[i] = v;
-}
-
-}  // namespace
 
 // ===========================================================================
 // host side
@@ -797,6 +74,9 @@ struct sim_t {
     float* d_cT = nullptr;
     float* d_cA = nullptr;
     float* d_cKab = nullptr;
+    float* d_cVs = nullptr;
+    float* d_cB = nullptr;
+    unsigned* d_epoch = nullptr;
 
     bool loaded = false;
     int cap = 0;
@@ -807,6 +87,30 @@ struct sim_t {
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
     std::vector<std::vector<hipEvent_t>> ev_steps;  // SIM_NUM_KERNELS + 1 events per sampled step
+
+    // differentiation window: checkpoints every `tape_every` steps from tape_t0
+    struct Ckpt {
+        long long t = 0;
+        Veh v{};
+        int* pend = nullptr;
+        Counters* ctr = nullptr;
+    };
+    bool tape_on = false;
+    long long tape_t0 = 0;
+    int tape_every = 0;
+    size_t nckpt = 0;
+    std::vector<Ckpt> ckpt_pool;
+    // recompute state and adjoint work arrays (allocated at the first sim_grad)
+    bool adj_ready = false;
+    Veh rbuf[2]{};
+    int* rpend[2]{nullptr, nullptr};
+    Counters* rctr = nullptr;
+    Tape slab{};  // tape_every slices of cap entries
+    AdjState adj{};
+    float *L0x = nullptr, *L0v = nullptr, *L1x = nullptr, *L1v = nullptr;
+    unsigned long long* sink = nullptr;  // statistics of the recompute pass (discarded)
+    int adj_grid = 0;
+    int adj_k = 0;  // tape slices allocated
 };
 
 namespace {
@@ -853,7 +157,7 @@ void release_all(sim_t* S) {
 }
 
 int upload_idm(sim_t* S, const float* idm) {
-    std::vector<float> T(S->ncls), A(S->ncls), K(S->ncls), inv(S->ne);
+    std::vector<float> T(S->ncls), A(S->ncls), K(S->ncls), VS(S->ncls), B(S->ncls), inv(S->ne);
     for (int c = 0; c < S->ncls; ++c) {
         double s0 = idm[4 * c + 0], t = idm[4 * c + 1], a = idm[4 * c + 2], b = idm[4 * c + 3];
         if (!(s0 > 0) || !(t >= 0) || !(a > 0) || !(b > 0) || !std::isfinite(s0 * t * a * b))
@@ -861,6 +165,8 @@ int upload_idm(sim_t* S, const float* idm) {
         T[c] = (float)t;
         A[c] = (float)a;
         K[c] = (float)(1.0 / (2.0 * std::sqrt(a * b)));
+        VS[c] = (float)s0;
+        B[c] = (float)b;
     }
     for (int e = 0; e < S->ne; ++e)
         inv[e] = (float)(1.0 / ((double)idm[4 * S->cls[e] + 0] * (double)S->speed[e]));
@@ -868,6 +174,8 @@ int upload_idm(sim_t* S, const float* idm) {
     HIPCHECK(S, hipMemcpyAsync(S->d_cA, A.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_cKab, K.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_inv_v0, inv.data(), sizeof(float) * S->ne, hipMemcpyHostToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_cVs, VS.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_cB, B.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipStreamSynchronize(S->stream));
     return SIM_OK;
 }
@@ -883,6 +191,95 @@ int32_t tail_node(const sim_t* S, int32_t e) {
     // largest u with row_ptr[u] <= e
     auto it = std::upper_bound(S->row_ptr.begin(), S->row_ptr.end(), e);
     return (int32_t)(it - S->row_ptr.begin()) - 1;
+}
+
+
+int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, const Scratch& sc, const Tape& tp,
+                Counters* ctr, hipEvent_t* ev) {
+    const dim3 g(S->grid), b(kBlock);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
+    hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pin, pout, ctr);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
+    hipLaunchKernelGGL(k_resolve, g, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pout, ctr);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
+    hipLaunchKernelGGL(k_scan, g, b, 0, S->stream, sc, ctr);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
+    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, in, out, sc, tp, ctr);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
+    hipLaunchKernelGGL(k_place, g, b, 0, S->stream, S->tr, in, out, sc, tp, kLcNone, ctr);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
+    HIPCHECK(S, hipGetLastError());
+    return SIM_OK;
+}
+
+bool alloc_veh(sim_t* S, Veh& V, size_t n) {
+    return dalloc(S, V.key, n) && dalloc(S, V.x, n) && dalloc(S, V.v, n) && dalloc(S, V.edge, n) &&
+           dalloc(S, V.rcur, n) && dalloc(S, V.next, n) && dalloc(S, V.lc, n) && dalloc(S, V.kin, n) &&
+           dalloc(S, V.phin, n) && dalloc(S, V.vid, n);
+}
+
+int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, const Veh& sv, const int* spend,
+               const Counters* sctr) {
+    const size_t n = (size_t)S->cap;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    HIPCHECK(S, hipMemcpyAsync(dv.key, sv.key, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.x, sv.x, sizeof(float) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.v, sv.v, sizeof(float) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.edge, sv.edge, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.rcur, sv.rcur, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.next, sv.next, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.lc, sv.lc, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.kin, sv.kin, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.phin, sv.phin, sizeof(float) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.vid, sv.vid, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dpend, spend, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dctr, sctr, sizeof(Counters), k, S->stream));
+    return SIM_OK;
+}
+
+int take_checkpoint(sim_t* S, int p) {
+    if (S->nckpt == S->ckpt_pool.size()) {
+        sim_t::Ckpt ck;
+        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.pend, S->cap) || !dalloc(S, ck.ctr, 1))
+            return fail(S, SIM_ENOMEM, "checkpoint allocation failed");
+        S->ckpt_pool.push_back(ck);
+    }
+    sim_t::Ckpt& ck = S->ckpt_pool[S->nckpt++];
+    ck.t = S->host_t;
+    return copy_state(S, ck.v, ck.pend, ck.ctr, S->buf[p], S->pend[p], S->ctr);
+}
+
+Tape slice(sim_t* S, int k) {
+    Tape t = S->slab;
+    const size_t o = (size_t)k * S->cap;
+    t.on = 1;
+    t.x += o; t.v += o; t.vid += o; t.edge += o; t.lead += o; t.clead += o; t.next += o;
+    t.mode += o; t.flags += o; t.cflags += o;
+    t.n += k;
+    return t;
+}
+
+int alloc_adjoint(sim_t* S) {
+    if (S->adj_ready) return SIM_OK;
+    const size_t cap = (size_t)S->cap, K = (size_t)S->tape_every, n = cap * K;
+    Tape& t = S->slab;
+    AdjState& a = S->adj;
+    S->adj_grid = S->grid;
+    const size_t nthreads = (size_t)S->adj_grid * kBlock;
+    bool ok = alloc_veh(S, S->rbuf[0], cap) && alloc_veh(S, S->rbuf[1], cap) && dalloc(S, S->rpend[0], cap) &&
+              dalloc(S, S->rpend[1], cap) && dalloc(S, S->rctr, 1) && dalloc(S, t.x, n) && dalloc(S, t.v, n) &&
+              dalloc(S, t.vid, n) && dalloc(S, t.edge, n) && dalloc(S, t.lead, n) && dalloc(S, t.clead, n) &&
+              dalloc(S, t.next, n) && dalloc(S, t.mode, n) && dalloc(S, t.flags, n) && dalloc(S, t.cflags, n) &&
+              dalloc(S, t.n, K) && dalloc(S, S->L0x, cap) && dalloc(S, S->L0v, cap) && dalloc(S, S->L1x, cap) &&
+              dalloc(S, S->L1v, cap) && dalloc(S, a.cgx, cap) && dalloc(S, a.cgv, cap) && dalloc(S, a.cl, cap) &&
+              dalloc(S, a.accx, cap) && dalloc(S, a.accv, cap) && dalloc(S, a.maxbits, 1) &&
+              dalloc(S, a.scale, 1) && dalloc(S, a.lp, cap) && dalloc(S, a.gpart, nthreads * S->ncls * 4) &&
+              dalloc(S, S->sink, 3 * (size_t)S->ne);
+    if (!ok) return fail(S, SIM_ENOMEM, "adjoint allocation failed");
+    a.ncls = S->ncls;
+    S->adj_k = S->tape_every;
+    S->adj_ready = true;
+    return SIM_OK;
 }
 
 }  // namespace
@@ -979,6 +376,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
               dalloc(S, d_lanes, ne) && dalloc(S, d_cls, ne) && dalloc(S, d_head, ne) &&
               dalloc(S, d_row_ptr, nn + 1) && dalloc(S, d_cbase, ne) && dalloc(S, d_ncell, ne) &&
               dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, ncls) && dalloc(S, S->d_cKab, ncls) &&
+              dalloc(S, S->d_cVs, ncls) && dalloc(S, S->d_cB, ncls) && dalloc(S, S->d_epoch, 1) &&
               dalloc(S, S->s.cells, (size_t)cells) && dalloc(S, S->s.st_cnt, ne) &&
               dalloc(S, S->s.st_steps, ne) && dalloc(S, S->s.st_us, ne) && dalloc(S, S->ctr, 1) &&
               dalloc(S, dummy, 1);
@@ -1006,6 +404,10 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     if (he == hipSuccess) he = hipMemsetAsync(S->s.st_us, 0, sizeof(unsigned long long) * ne, S->stream);
     if (he == hipSuccess) he = hipMemsetAsync(S->ctr, 0, sizeof(Counters), S->stream);
     if (he == hipSuccess) {
+        const unsigned one = 1u;
+        he = hipMemcpyAsync(S->d_epoch, &one, sizeof(unsigned), hipMemcpyHostToDevice, S->stream);
+    }
+    if (he == hipSuccess) {
         int g = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, (cells + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kBlock), 0, S->stream, S->s.cells, cells, ~0ull);
         he = hipGetLastError();
@@ -1029,6 +431,9 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     N.cT = S->d_cT;
     N.cA = S->d_cA;
     N.cKab = S->d_cKab;
+    N.cVs = S->d_cVs;
+    N.cB = S->d_cB;
+    S->s.epoch = S->d_epoch;
     *out = S;
     return SIM_OK;
 }
@@ -1198,13 +603,13 @@ int sim_step(sim_t* S, int32_t num_steps) {
     if (!S) return SIM_EINVAL;
     if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
     if (num_steps < 0) return fail(S, SIM_EINVAL, "negative step count");
-    const dim3 g(S->grid), b(kBlock);
+    const Tape off{};
     for (int k = 0; k < num_steps; ++k) {
         const int p = (int)(S->host_t & 1);
-        const Veh& in = S->buf[p];
-        const Veh& out = S->buf[p ^ 1];
-        int* pin = S->pend[p];
-        int* pout = S->pend[p ^ 1];
+        if (S->tape_on && (S->host_t - S->tape_t0) % S->tape_every == 0) {
+            int rc = take_checkpoint(S, p);
+            if (rc) return rc;
+        }
         hipEvent_t ev[SIM_NUM_KERNELS + 1] = {};
         const bool timed = S->timing_every > 0 && (S->host_t % S->timing_every) == 0;
         if (timed) {
@@ -1217,24 +622,83 @@ int sim_step(sim_t* S, int32_t num_steps) {
                 ev[q] = S->ev_free.back();
                 S->ev_free.pop_back();
             }
-            HIPCHECK(S, hipEventRecord(ev[0], S->stream));
         }
-        hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, S->tr, in, S->s, pin, pout, S->ctr);
-        if (timed) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
-        hipLaunchKernelGGL(k_resolve, g, b, 0, S->stream, S->P, S->net, S->tr, in, S->s, pout, S->ctr);
-        if (timed) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-        hipLaunchKernelGGL(k_scan, g, b, 0, S->stream, S->s, S->ctr);
-        if (timed) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
-        hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, in, out, S->s, S->ctr);
-        if (timed) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
-        hipLaunchKernelGGL(k_place, g, b, 0, S->stream, S->tr, in, out, S->s, kLcNone, S->ctr);
-        if (timed) {
-            HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-            S->ev_steps.emplace_back(ev, ev + SIM_NUM_KERNELS + 1);
-        }
-        HIPCHECK(S, hipGetLastError());
+        int rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->pend[p], S->pend[p ^ 1], S->s, off, S->ctr,
+                             timed ? ev : nullptr);
+        if (rc) return rc;
+        if (timed) S->ev_steps.emplace_back(ev, ev + SIM_NUM_KERNELS + 1);
         S->host_t += 1;
     }
+    return SIM_OK;
+}
+
+int sim_tape_begin(sim_t* S, int32_t checkpoint_every) {
+    if (!S || checkpoint_every <= 0) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (S->ncls > 16) return fail(S, SIM_EINVAL, "differentiation supports at most 16 link classes");
+    if (S->adj_ready && checkpoint_every > S->adj_k)
+        return fail(S, SIM_EINVAL, "checkpoint interval larger than the one the adjoint buffers were sized for");
+    S->tape_on = true;
+    S->tape_t0 = S->host_t;
+    S->tape_every = checkpoint_every;
+    S->nckpt = 0;
+    return SIM_OK;
+}
+
+int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
+    if (!S || !dL_dmeanTT || !dL_dtheta) return SIM_EINVAL;
+    if (!S->tape_on) return fail(S, SIM_ESTATE, "sim_grad without sim_tape_begin");
+    int rc = alloc_adjoint(S);
+    if (rc) return rc;
+    const int G = S->adj_grid;
+    const int nvals = S->ncls * 4;
+    const long long nthreads = (long long)G * kBlock;
+    const dim3 g(G), b(kBlock);
+    hipLaunchKernelGGL(k_zero_f64, g, b, 0, S->stream, S->adj.gpart, nthreads * nvals);
+    hipLaunchKernelGGL(k_zero_f32, g, b, 0, S->stream, S->adj.lp, (long long)S->cap);
+    hipLaunchKernelGGL(k_zero_f32, g, b, 0, S->stream, S->L1x, (long long)S->cap);
+    hipLaunchKernelGGL(k_zero_f32, g, b, 0, S->stream, S->L1v, (long long)S->cap);
+    hipLaunchKernelGGL(k_zero_i64, g, b, 0, S->stream, S->adj.accx, (long long)S->cap);
+    hipLaunchKernelGGL(k_zero_i64, g, b, 0, S->stream, S->adj.accv, (long long)S->cap);
+    HIPCHECK(S, hipMemsetAsync(S->adj.maxbits, 0, sizeof(unsigned), S->stream));
+    HIPCHECK(S, hipGetLastError());
+    // the recompute pass must not add to the live statistics
+    Scratch rs = S->s;
+    rs.st_cnt = S->sink;
+    rs.st_steps = S->sink + S->ne;
+    rs.st_us = S->sink + 2 * (size_t)S->ne;
+    AdjState a = S->adj;
+    a.dLdT = dL_dmeanTT;
+    a.cnt = S->s.st_cnt;
+    float *L0x = S->L0x, *L0v = S->L0v, *L1x = S->L1x, *L1v = S->L1v;
+    for (size_t c = S->nckpt; c-- > 0;) {
+        const sim_t::Ckpt& ck = S->ckpt_pool[c];
+        const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
+        const int K = (int)(t_end - ck.t);
+        if ((rc = copy_state(S, S->rbuf[0], S->rpend[0], S->rctr, ck.v, ck.pend, ck.ctr))) return rc;
+        for (int k = 0; k < K; ++k) {
+            if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], S->rpend[k & 1], S->rpend[(k + 1) & 1],
+                                  rs, slice(S, k), S->rctr, nullptr)))
+                return rc;
+        }
+        for (int k = K - 1; k >= 0; --k) {
+            const Tape tk = slice(S, k);
+            a.L1x = L1x;
+            a.L1v = L1v;
+            a.L0x = L0x;
+            a.L0v = L0v;
+            hipLaunchKernelGGL(k_adj_own, g, b, 0, S->stream, S->P, S->net, tk, a);
+            hipLaunchKernelGGL(k_adj_lead, g, b, 0, S->stream, tk, a);
+            hipLaunchKernelGGL(k_adj_sum, g, b, 0, S->stream, tk, a);
+            HIPCHECK(S, hipGetLastError());
+            std::swap(L0x, L1x);
+            std::swap(L0v, L1v);
+        }
+    }
+    double* out64 = nullptr;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((nvals + 63) / 64), dim3(64), 0, S->stream, S->adj.gpart, (int)nthreads,
+                       nvals, dL_dtheta, out64);
+    HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
 

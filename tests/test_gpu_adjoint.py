@@ -1,0 +1,116 @@
+"""GPU adjoint (sim_grad, IDMTravelTime) against the FP64 CPU adjoint.
+
+The FP32 GPU forward equals the FP32 oracle bit for bit, so both record the
+same discrete events.  The CPU reference replays the FP32 oracle's event tape
+in FP64 and differentiates it (itself pinned by central differences); the GPU
+gradient must agree with it to 1e-3 of the gradient's largest component.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+
+def diff_small(seed=21, side=10, n_trips=1500, steps=600):
+    return S.diff_scenario(seed=seed, side=side, n_trips=n_trips, steps=steps, depart_s=200.0)
+
+
+def targets(scen):
+    """Mean link travel times at the hidden parameters (FP32 oracle run)."""
+    sc = dict(scen)
+    sc["params"] = dict(scen["params"])
+    sc["params"]["idm"] = scen["hidden_idm"]
+    o = oracle.Oracle(sc, "f32")
+    o.step(scen["steps"])
+    es = o.edge_stats()
+    return np.where(es["count"] > 0, es["tt_us"] / np.maximum(es["count"], 1) / 1e6, 0.0)
+
+
+def cpu_reference(scen, target):
+    o = oracle.Oracle(scen, "f32", tape=True)
+    o.step(scen["steps"])
+    es = o.edge_stats()
+    mask = es["count"] > 0
+    loss, g, tbar, _, _ = oracle.replay(o.tape(), scen, scen["params"]["idm"].astype(np.float64), target, mask)
+    return loss, g, mask
+
+
+def gpu_grad(scen, target, every):
+    import torch
+
+    import paper_1807_01148_amd as P
+    sim = P.Sim(scen)
+    sim.tape_begin(every)
+    sim.step(scen["steps"])
+    tbar, cnt = sim.mean_travel_times()
+    t = torch.tensor(target, dtype=torch.float32, device=tbar.device)
+    m = cnt > 0
+    nm = int(m.sum())
+    dL = torch.where(m, 2.0 * (tbar - t) / nm, torch.zeros_like(tbar))
+    g = sim.grad(dL).cpu().numpy().astype(np.float64)
+    loss = float(((tbar - t)[m] ** 2).mean())
+    return sim, g, loss
+
+
+@pytest.mark.parametrize("every", [60, 17])
+def test_gpu_adjoint_matches_fp64_cpu_adjoint(every):
+    scen = diff_small()
+    tgt = targets(scen)
+    loss_c, g_c, _ = cpu_reference(scen, tgt)
+    _, g_g, loss_g = gpu_grad(scen, tgt, every)
+    assert abs(loss_g - loss_c) <= 1e-4 * loss_c
+    err = np.abs(g_g - g_c).max() / np.abs(g_c).max()
+    assert err < 1e-3, (err, g_g, g_c)
+
+
+def test_gpu_adjoint_independent_of_checkpoint_interval_and_deterministic():
+    scen = diff_small(seed=22)
+    tgt = targets(scen)
+    _, g60, _ = gpu_grad(scen, tgt, 60)
+    _, g60b, _ = gpu_grad(scen, tgt, 60)
+    _, g7, _ = gpu_grad(scen, tgt, 7)
+    assert np.array_equal(g60, g60b)
+    assert np.array_equal(g60, g7)
+
+
+def test_grad_leaves_live_state_untouched():
+    scen = diff_small(seed=23, steps=300)
+    tgt = targets(scen)
+    import paper_1807_01148_amd as P
+    sim = P.Sim(scen)
+    sim.tape_begin(60)
+    sim.step(scen["steps"])
+    before_v, before_c, before_s = sim.vehicles(), sim.counters(), sim.edge_stats()
+    import torch
+    sim.grad(torch.ones(sim.num_edges, device="cuda"))
+    after_v, after_c, after_s = sim.vehicles(), sim.counters(), sim.edge_stats()
+    for k in before_v:
+        assert np.array_equal(before_v[k], after_v[k])
+    assert before_c == after_c
+    for k in before_s:
+        assert np.array_equal(before_s[k], after_s[k])
+    # and the simulation continues exactly like the oracle
+    o = oracle.Oracle(scen, "f32")
+    o.step(scen["steps"] + 100)
+    sim.step(100)
+    V, O = sim.vehicles(), o.vehicles()
+    for k in ("vid", "edge", "lane", "x", "v"):
+        assert np.array_equal(V[k], O[k])
+
+
+def test_autograd_function():
+    import torch
+
+    from paper_1807_01148_amd.diff import IDMTravelTime, travel_time_loss
+    scen = diff_small(seed=24)
+    tgt = targets(scen)
+    theta = torch.tensor(scen["params"]["idm"], dtype=torch.float32, requires_grad=True)
+    tbar, cnt = IDMTravelTime.apply(theta, scen, scen["steps"], 60)
+    loss = travel_time_loss(tbar, cnt, torch.tensor(tgt, dtype=torch.float32, device=tbar.device))
+    loss.backward()
+    _, g_c, _ = cpu_reference(scen, tgt)
+    err = np.abs(theta.grad.numpy().astype(np.float64) - g_c).max() / np.abs(g_c).max()
+    assert err < 1e-3, err
