@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--timing-every", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
+    ap.add_argument("--tune-at", type=int, default=0,
+                    help="simulate to this step, autotune the launch shape there, store it in the cache, exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -96,6 +99,7 @@ def main():
 
     import torch
     import paper_1807_01148_amd as P
+    from paper_1807_01148_amd import ensemble as E
 
     log("[bench] generating workload", args.workload)
     t = time.perf_counter()
@@ -108,8 +112,36 @@ def main():
     sim = P.Sim(scen, device=0, stream=stream)
     del scen["demand"]
     log("[bench] loaded in %.1f s" % (time.perf_counter() - t))
+    cache = os.path.join(ROOT, "paper_1807_01148_amd", "autotune_cache.json")
+    if args.tune_at > 0:
+        E.step_graph(sim, args.tune_at, args.chunk)
+        torch.cuda.synchronize()
+        res = E.autotune(sim, steps_per_trial=60)
+        res.update({"workload": args.workload, "step": args.tune_at, "device": torch.cuda.get_device_name(0)})
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+        db["%s|%s" % (res["device"], args.workload)] = {"grid": res["grid"], "grid_small": res["grid_small"],
+                                                         "ms_per_step": res["ms_per_step"], "step": args.tune_at}
+        with open(cache, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        print(json.dumps(res), flush=True)
+        return
+    shape = "default"
+    try:
+        with open(cache) as f:
+            hit = json.load(f).get("%s|%s" % (torch.cuda.get_device_name(0), args.workload))
+        if hit:
+            E.set_launch(sim, hit["grid"], hit["grid_small"])
+            shape = "autotuned"
+    except (OSError, ValueError):
+        pass
+    launch = E.get_launch(sim)
+    log("[bench] launch shape %s: grid %d, small grid %d" % (shape, launch[0], launch[1]))
 
-    sim.step(args.warmup)
+    E.step_graph(sim, args.warmup, args.chunk)
     torch.cuda.synchronize()
     c0 = sim.counters()
     log("[bench] warmup done: step %d en_route %d" % (c0["step"], c0["en_route"]))
@@ -122,7 +154,7 @@ def main():
     done = 0
     while done < args.steps:
         n = min(chunk, args.steps - done)
-        sim.step(n)
+        E.step_graph(sim, n, args.chunk)
         done += n
         if done < args.steps:
             log("[bench] enqueued %d / %d steps" % (done, args.steps))
@@ -163,6 +195,7 @@ def main():
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": step_achieved / HBM_PEAK_GBS},
         "kernel_avg_us": {k: v * 1e3 for k, v in avg.items()},
+        "launch": {"grid": launch[0], "grid_small": launch[1], "shape": shape, "graph_chunk": args.chunk},
     }
     sim.close()
     if not args.no_cpu_baseline:

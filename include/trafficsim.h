@@ -149,9 +149,9 @@ int sim_set_idm(sim_t* sim, const float* idm);
 
 /* Per-kernel timing with HIP events on the handle's stream: when every > 0,
  * every `every`-th subsequent step records an event before and after each of
- * its SIM_NUM_KERNELS kernel launches (decide, resolve, scan, scatter, place);
+ * its SIM_NUM_KERNELS kernel launches (decide, resolve, scan, scatter, place, lanes);
  * 0 disables.  Timing adds no synchronisation to sim_step. */
-#define SIM_NUM_KERNELS 5
+#define SIM_NUM_KERNELS 6
 int sim_set_timing(sim_t* sim, int32_t every);
 
 /* Synchronise, then add the elapsed milliseconds of every sampled launch to
@@ -177,6 +177,39 @@ int sim_tape_begin(sim_t* sim, int32_t checkpoint_every);
  * backwards.  Asynchronous on the handle's stream; live state and statistics
  * are left as they were.  Errors: SIM_ESTATE (no window), SIM_ENOMEM, SIM_EHIP. */
 int sim_grad(sim_t* sim, const float* dL_dmeanTT, float* dL_dtheta);
+
+/* Batched ensemble: n scenarios simulated as one (their networks side by side:
+ * node, edge, lane and class ids of scenario q are offset by the totals of
+ * scenarios 0..q-1).  Every field of params[q] except idm/num_classes must
+ * equal params[0].  Vehicles of different scenarios never share a lane, and a
+ * trip's vehicle id keeps its scenario's (departure, index) order, so every
+ * scenario evolves exactly as in its own simulation.  Errors as sim_create. */
+int sim_create_batch(int32_t n, const sim_network* nets, const sim_params* params, void* hip_stream,
+                     sim_alloc_fn alloc, sim_free_fn free_fn, void* alloc_ctx, sim_t** out);
+
+/* Demand of a batch: for each scenario q the arrays of sim_load_demand (HOST,
+ * edge ids local to scenario q); placed trips are not supported here.  Trips
+ * are concatenated in scenario order.  Errors as sim_load_demand. */
+int sim_load_demand_batch(sim_t* sim, int32_t n, const int32_t* num_trips, const int32_t* const* depart_step,
+                          const int32_t* const* trip_route, const int32_t* num_routes,
+                          const int64_t* const* route_ptr, const int32_t* const* route_edges);
+
+/* Launch shape: blocks of 256 threads for the per-vehicle kernels (grid) and
+ * for the per-claim kernels (grid_small).  Results do not depend on it. */
+int sim_set_launch(sim_t* sim, int32_t grid, int32_t grid_small);
+int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
+
+/* As sim_step, with runs of `chunk` consecutive steps replayed from captured
+ * HIP graphs (captured on first use per run length and step parity).  With
+ * timing on (sim_set_timing), each sampled step runs alone and the runs stop
+ * at it.  Falls back to sim_step while a differentiation window is active. */
+int sim_step_graph(sim_t* sim, int32_t num_steps, int32_t chunk);
+
+/* Time `steps_per_trial` steps for each candidate launch shape, all from the
+ * current state, then restore that state (vehicles, counters, statistics,
+ * per-trip outcomes) and keep the fastest shape.  Outputs the shape and its
+ * time per step (ms).  Allocates a copy of the state.  Synchronises. */
+int sim_autotune(sim_t* sim, int32_t steps_per_trial, int32_t* best_grid, int32_t* best_small, float* best_ms);
 
 /* Route subsequent work to another HIP stream. */
 int sim_set_stream(sim_t* sim, void* hip_stream);

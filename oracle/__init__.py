@@ -44,7 +44,7 @@ def _adjlib():
         lib = ctypes.CDLL(os.path.join(_HERE, "libadjoint.so"))
         P = ctypes.c_void_p
         lib.adj_eval.argtypes = [ctypes.c_int64] + [P] * 8 + [ctypes.c_int32, ctypes.c_int32, P, P, P,
-                                                            ctypes.c_int32] + [P] * 9
+                                                            ctypes.c_int32] + [P] * 9 + [ctypes.c_int32]
         lib.adj_eval.restype = ctypes.c_int
         _LIBS["adj"] = lib
     return _LIBS["adj"]
@@ -102,10 +102,12 @@ TAPE_INT = ("step", "vid", "mode", "lead", "flags", "edge")
 TAPE_F64 = ("x0", "v0")
 
 
-def replay(tape, scen, theta, target, mask, grad=True):
+def replay(tape, scen, theta, target, mask, grad=True, at_tape_states=False):
     """Frozen-event FP64 replay of ``tape`` at parameters ``theta``
     [num_classes, 4] = (v0_scale, T, a, b): returns (loss, gradient or None,
-    mean link travel times [E], final x [V], final v [V])."""
+    mean link travel times [E], final x [V], final v [V]).  With
+    ``at_tape_states`` the states are taken from the tape instead of being
+    replayed (linearization along the recording forward's trajectory)."""
     lib = _adjlib()
     net, p = scen["net"], scen["params"]
     ne = int(net["col_idx"].size)
@@ -126,7 +128,7 @@ def replay(tape, scen, theta, target, mask, grad=True):
     tp = {k: np.ascontiguousarray(tape[k]) for k in TAPE_INT + TAPE_F64}
     rc = lib.adj_eval(int(tp["step"].size), *[_p(tp[k]) for k in TAPE_INT + TAPE_F64], nveh, ne,
                       _p(length), _p(speed), _p(cls), int(th.shape[0]), _p(th), _p(fp), _p(tgt), _p(msk),
-                      ctypes.byref(loss), _p(g), _p(tbar), _p(xf), _p(vf))
+                      ctypes.byref(loss), _p(g), _p(tbar), _p(xf), _p(vf), 1 if at_tape_states else 0)
     if rc != 0:
         raise OracleError("adj_eval failed: %d" % rc)
     return loss.value, (None if g is None else g.reshape(th.shape)), tbar, xf[:nveh], vf[:nveh]

@@ -26,6 +26,11 @@
  * of these expressions; a leader's adjoint collects the terms of all its
  * followers.  Pinned by central finite differences of the replay itself and by
  * the replay reproducing the FP64 forward trajectory exactly.
+ *
+ * at_tape_states: instead of replaying the positions and speeds, take each
+ * vehicle's state before every step from the tape (as the recording forward
+ * computed it) and linearize there; the loss and gradient are then those of
+ * that forward's own trajectory, evaluated in FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -174,7 +179,7 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
              const int32_t* flags, const int32_t* edge, const double* x0, const double* v0, int32_t nveh,
              int32_t ne, const double* len, const double* speed, const int32_t* cls, int32_t ncls,
              const double* theta, const double* fp, const double* target, const uint8_t* mask, double* loss,
-             double* grad, double* tbar, double* xfin, double* vfin) {
+             double* grad, double* tbar, double* xfin, double* vfin, int32_t at_tape_states) {
     cst_t K;
     K.dt = fp[0];
     K.h = 0.5 * fp[0] * fp[0];
@@ -229,8 +234,9 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
         for (int64_t k = g0; k < g1; ++k) where[vid[k]] = (int32_t)k;
         for (int64_t k = g0; k < g1; ++k) {
             int32_t i = vid[k];
-            rx[k] = x[i];
-            rv[k] = v[i];
+            /* the state before the step: replayed, or as recorded by the forward */
+            rx[k] = at_tape_states ? x0[k] : x[i];
+            rv[k] = at_tape_states ? v0[k] : v[i];
             rlead[k] = (flags[k] & TF_HAS_LEAD) ? where[lead[k]] : -1;
             rtrav[k] = -1;
         }

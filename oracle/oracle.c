@@ -722,7 +722,7 @@ static int step_once(osim* S) {
             if (d->kind == K_ARRIVE) mode = TM_ARRIVE;
             else if (d->kind == K_CROSS) mode = cwin_veh[o] ? TM_CROSS : TM_YIELD;
             else if (d->kind == K_CHANGE && cwin_veh[o]) { mode = TM_CHANGE; lead = d->chg_lead; fl = d->chg_fl; }
-            tape_push(S, t, q.vid, mode, lead, fl, q.edge, 0.0, 0.0);
+            tape_push(S, t, q.vid, mode, lead, fl, q.edge, (double)q.x, (double)q.v);
         }
         if (d->kind == K_ARRIVE) {
             record_exit(S, &q, d->f, t);

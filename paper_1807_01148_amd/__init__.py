@@ -22,7 +22,7 @@ SIM_OK, SIM_EINVAL, SIM_EROUTE, SIM_ENOMEM, SIM_EHIP, SIM_ESTATE = 0, -1, -2, -3
 EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_vehicles",
             "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
             "sim_grad", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
-KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place")
+KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 class SimError(RuntimeError):

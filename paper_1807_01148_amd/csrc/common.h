@@ -10,7 +10,7 @@ namespace tsim {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kLcNone = -(1 << 30);
 constexpr int kMaxGrid = 2048;
@@ -29,7 +29,7 @@ struct Counters {
     int npend_next;  // candidates carried to the next step
     int n_next;      // entries of the next buffer
     unsigned scan_tile;
-    unsigned done_blocks;
+    unsigned epoch_next;  // epoch of the next step (set during the step, committed at its end)
     int pad;
     unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
 };
@@ -81,6 +81,22 @@ struct Veh {
     int* vid;
 };
 
+// Entries [lo, hi] of the sorted arrays are the vehicles of one lane, valid
+// when ep equals the current step's epoch (so the table is never cleared).
+struct LaneIx {
+    unsigned ep;
+    int lo;
+    int hi;
+    int pad;
+};
+
+__device__ __forceinline__ bool lane_range(const LaneIx* __restrict__ lanes, int key, unsigned ep, int& lo, int& hi) {
+    const int4 w = *reinterpret_cast<const int4*>(lanes + key);
+    lo = w.y;
+    hi = w.z;
+    return (unsigned)w.x == ep;
+}
+
 struct Scratch {
     float* xs;
     float* vs;
@@ -108,7 +124,8 @@ struct Scratch {
     unsigned long long* st_cnt;
     unsigned long long* st_steps;
     unsigned long long* st_us;
-    unsigned* epoch;  // executed-step counter (claims and scan statuses are tagged with it)
+    unsigned* epoch;  // executed-step counter (claims, scan statuses, lane index are tagged with it)
+    LaneIx* lanes;  // per global lane: first and last entry in the sorted arrays
 };
 
 // Event tape of one step (recorded during the adjoint's recompute pass): the

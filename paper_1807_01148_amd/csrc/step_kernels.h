@@ -5,11 +5,31 @@
 #include "common.h"
 
 namespace tsim {
+// first j in [lo, hi) with x[j] > X (x sorted ascending within a lane)
+__device__ __forceinline__ int ub_x(const float* __restrict__ x, int lo, int hi, float X) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (x[mid] <= X) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first j in [lo, hi) with x[j] >= X
+__device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi, float X) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (x[mid] < X) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                               const Scratch& s, const Tape& tp, Counters* ctr, int N, int t,
+                               const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
                                unsigned long long tag, int i, int& clamps, int& arrivals) {
     const int k = in.key[i];
     const float x = in.x[i];
@@ -32,8 +52,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     } else if (nx >= 0) {
         int nl2 = net.lanes[nx];
         int k2 = net.lane_base[nx] + (l < nl2 - 1 ? l : nl2 - 1);
-        int j = lb_key(in.key, 0, N, k2);
-        if (j < N && in.key[j] == k2) {
+        int j, jh;
+        if (lane_range(s.lanes, k2, ep, j, jh)) {
             float xl = in.x[j];
             L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.s = (len - x) + (xl - P.lveh); L.idx = j;
         }
@@ -126,21 +146,23 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         const int kt = lb + lt;
         // first vehicle of the target lane strictly ahead; the one before it
         // (position <= x) is the lag
-        int j = lt > l ? ub_keyx(in.key, in.x, i + 1, N, kt, x) : ub_keyx(in.key, in.x, 0, i, kt, x);
+        int tlo, thi;
+        const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
+        int j = occ ? ub_x(in.x, tlo, thi + 1, x) : -1;
         Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1};
-        if (j < N && in.key[j] == kt) {
+        if (occ && j <= thi) {
             float xl = in.x[j];
             Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.s = (xl - P.lveh) - x; Lt.idx = j;
         } else if (nx >= 0) {
             int nl2 = net.lanes[nx];
             int k2 = net.lane_base[nx] + (lt < nl2 - 1 ? lt : nl2 - 1);
-            int j2 = lb_key(in.key, 0, N, k2);
-            if (j2 < N && in.key[j2] == k2) {
+            int j2, j2h;
+            if (lane_range(s.lanes, k2, ep, j2, j2h)) {
                 float xl = in.x[j2];
                 Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.s = (len - x) + (xl - P.lveh); Lt.idx = j2;
             }
         }
-        const bool hasFt = j > 0 && in.key[j - 1] == kt;
+        const bool hasFt = occ && j - 1 >= tlo;
         const float xFt = hasFt ? in.x[j - 1] : 0.0f;
         const float vFt = hasFt ? in.v[j - 1] : 0.0f;
         // gap acceptance (Sec. 6.3.2)
@@ -198,20 +220,18 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 }
 
 __device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                              const Scratch& s, Counters* ctr, int* pend_out, int N,
+                              const Scratch& s, Counters* ctr, int* pend_out, unsigned ep,
                               unsigned long long tag, int vid) {
     if (tr.placed[vid]) return;
     const int e0 = tr.route_edges[tr.rbeg[vid]];
     const int n0 = net.lanes[e0];
     const int lb = net.lane_base[e0];
     const float len0 = net.len[e0];
-    int j = lb_key(in.key, 0, N, lb);
     int best = -1;
     float bsp = 0.0f;
     for (int l = 0; l < n0; ++l) {
-        const int kk = lb + l;
-        while (j < N && in.key[j] < kk) ++j;
-        float sp = (j < N && in.key[j] == kk) ? (in.x[j] - P.lveh) : len0;
+        int jl, jh;
+        float sp = lane_range(s.lanes, lb + l, ep, jl, jh) ? (in.x[jl] - P.lveh) : len0;
         if (best < 0 || sp > bsp) { best = l; bsp = sp; }
     }
     if (bsp >= P.claim_len) {
@@ -235,16 +255,17 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
         rhi = tr.rel_off[t + 1];
     }
     const int total = N + np + (rhi - rlo);
-    const unsigned long long tag = epoch_tag(*s.epoch);
+    const unsigned ep = *s.epoch;
+    const unsigned long long tag = epoch_tag(ep);
     int clamps = 0, arrivals = 0;
     if (tp.on && blockIdx.x == 0 && threadIdx.x == 0) *tp.n = N;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
         if (i < N) {
-            decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, tag, i, clamps, arrivals);
+            decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals);
         } else {
             int cidx = i - N;
             int vid = cidx < np ? pend_in[cidx] : rlo + (cidx - np);
-            decide_insert(P, net, tr, in, s, ctr, pend_out, N, tag, vid);
+            decide_insert(P, net, tr, in, s, ctr, pend_out, ep, tag, vid);
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
@@ -264,8 +285,12 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
     const int t = ctr->t;
     const int N = ctr->n;
     const int C = ctr->nclaim;
-    const unsigned long long tag = epoch_tag(*s.epoch);
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->scan_tile = 0;
+    const unsigned ep = *s.epoch;
+    const unsigned long long tag = epoch_tag(ep);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr->scan_tile = 0;
+        ctr->epoch_next = ep + 1u;
+    }
     int lost = 0, departed = 0;
     for (int ci = blockIdx.x * kBlock + threadIdx.x; ci < C; ci += gridDim.x * kBlock) {
         const int vid = s.cl_vid[ci];
@@ -288,7 +313,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
             if (src >= 0) s.stay[src] = 0;
             int m = atomicAdd(&ctr->nmove, 1);
             s.mv_claim[m] = ci;
-            int p = lb_keyx(in.key, in.x, 0, N, key, s.cl_X[ci]);
+            // its gap in the sorted order: inside its lane's run if the lane is
+            // occupied, else before the first entry of a later lane
+            int lo, hi;
+            int p = lane_range(s.lanes, key, ep, lo, hi) ? lb_x(in.x, lo, hi + 1, s.cl_X[ci])
+                                                         : lb_key(in.key, 0, N, key);
             s.mv_p[m] = p;
             s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
             if (kind == kCross) record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
@@ -346,6 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
     const int total = N + 1;
     const int ntiles = (total + kScanTile - 1) / kScanTile;
     const unsigned ep = (*s.epoch % 0x3FFFFFFFu) + 1u;
+    const int lane = threadIdx.x & (kWave - 1);
     __shared__ int s_tile;
     __shared__ int s_prefix;
     for (;;) {
@@ -366,33 +396,46 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
         }
         int agg;
         int excl = block_excl_scan(tsum, agg);
-        if (threadIdx.x == 0) {
-            int prefix = 0;
-            if (tile == 0) {
-                __hip_atomic_store(&s.tile_status[0], pack_status(ep, kFlagP, agg), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagA, agg), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                int j = tile - 1;
-                for (;;) {
-                    unsigned long long st = __hip_atomic_load(&s.tile_status[j], __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
-                    unsigned sep = (unsigned)(st >> 34);
-                    unsigned long long flag = (st >> 32) & 3ull;
-                    if (sep != ep || flag == 0ull) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    prefix += (int)(unsigned)(st & 0xFFFFFFFFull);
-                    if (flag == kFlagP) break;
-                    --j;
-                }
-                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagP, prefix + agg),
+        if (threadIdx.x < kWave) {
+            // publish this tile's aggregate, then look back over up to 64
+            // predecessors at a time: sum aggregates down to the nearest tile
+            // that has published its inclusive prefix
+            if (lane == 0)
+                __hip_atomic_store(&s.tile_status[tile], pack_status(ep, tile == 0 ? kFlagP : kFlagA, agg),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int prefix = 0;
+            int hi = tile - 1;  // nearest predecessor not yet summed
+            while (hi >= 0) {
+                const int j = hi - lane;
+                unsigned long long flag = kFlagP;  // before tile 0: an inclusive prefix of 0
+                int val = 0;
+                if (j >= 0) {
+                    unsigned long long st =
+                        __hip_atomic_load(&s.tile_status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    flag = ((unsigned)(st >> 34) == ep) ? ((st >> 32) & 3ull) : 0ull;
+                    val = (int)(unsigned)(st & 0xFFFFFFFFull);
+                }
+                const unsigned long long isP = __ballot(flag == kFlagP);
+                const unsigned long long notready = __ballot(flag == 0ull);
+                const int firstP = isP ? (__ffsll((long long)isP) - 1) : kWave;
+                const unsigned long long need = firstP >= kWave - 1 ? ~0ull : ((2ull << firstP) - 1ull);
+                if (notready & need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;  // a predecessor this tile depends on is still running
+                }
+                int mine = lane <= firstP ? val : 0;
+                for (int o = kWave / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o, kWave);
+                prefix += mine;
+                if (firstP < kWave) break;
+                hi -= kWave;
             }
-            s_prefix = prefix;
-            if (tile == ntiles - 1) ctr->n_next = prefix + agg;
+            if (lane == 0) {
+                if (tile > 0)
+                    __hip_atomic_store(&s.tile_status[tile], pack_status(ep, kFlagP, prefix + agg), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                s_prefix = prefix;
+                if (tile == ntiles - 1) ctr->n_next = prefix + agg;
+            }
         }
         __syncthreads();
         int run = s_prefix + excl;
@@ -438,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, 
 }
 
 // ---------------------------------------------------------------------------
-// k_place: movers take their rank inside their gap; last block finalises
+// k_place: movers take their rank inside their gap
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scratch s, Tape tp, int lc_none,
                                                   Counters* ctr) {
@@ -491,17 +534,26 @@ __global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scr
         }
         s.mcnt[p] = 0;
     }
-    // last block to finish advances the step
-    __syncthreads();
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned prev = atomicAdd(&ctr->done_blocks, 1u);
-        last = (prev == gridDim.x - 1);
+}
+
+// ---------------------------------------------------------------------------
+// k_lanes: index the lanes of the new sorted arrays (first and last entry per
+// lane, tagged with the next step's epoch).  With `finalize` it also commits
+// the step: the kernels of the step are the only readers of the counters it
+// advances, and they have all completed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_lanes(Veh buf, Scratch s, Counters* ctr, int finalize) {
+    const int N = finalize ? ctr->n_next : ctr->n;
+    const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
+        const int k = buf.key[j];
+        if (j == 0 || buf.key[j - 1] != k) {
+            s.lanes[k].lo = j;
+            s.lanes[k].ep = ep;
+        }
+        if (j == N - 1 || buf.key[j + 1] != k) s.lanes[k].hi = j;
     }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
+    if (finalize && blockIdx.x == 0 && threadIdx.x == 0) {
         ctr->updates += (unsigned long long)ctr->n;
         ctr->claims += (unsigned long long)ctr->nclaim;
         ctr->n = ctr->n_next;
@@ -509,9 +561,8 @@ __global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scr
         ctr->npend_next = 0;
         ctr->nclaim = 0;
         ctr->nmove = 0;
-        ctr->done_blocks = 0;
-        ctr->t = t + 1;
-        *s.epoch += 1u;
+        ctr->t = ctr->t + 1;
+        *s.epoch = ep;
     }
 }
 

@@ -83,6 +83,7 @@ struct sim_t {
     int ntrips = 0;
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
+    int grid_small = 1;  // kernels that work on claims and movers (a few % of the vehicles)
     std::vector<int> h_rbeg;
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
@@ -111,6 +112,15 @@ struct sim_t {
     unsigned long long* sink = nullptr;  // statistics of the recompute pass (discarded)
     int adj_grid = 0;
     int adj_k = 0;  // tape slices allocated
+
+    // batch of scenarios: edge offset of each scenario (size n+1), empty otherwise
+    std::vector<int> batch_edge_off;
+    // captured multi-step graphs, by (parity of the first step, chunk length)
+    struct GraphEntry {
+        int parity = 0, chunk = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -196,18 +206,20 @@ int32_t tail_node(const sim_t* S, int32_t e) {
 
 int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
-    const dim3 g(S->grid), b(kBlock);
+    const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
     hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pin, pout, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
-    hipLaunchKernelGGL(k_resolve, g, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pout, ctr);
+    hipLaunchKernelGGL(k_resolve, gs, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pout, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-    hipLaunchKernelGGL(k_scan, g, b, 0, S->stream, sc, ctr);
+    hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
     hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, in, out, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
-    hipLaunchKernelGGL(k_place, g, b, 0, S->stream, S->tr, in, out, sc, tp, kLcNone, ctr);
+    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
+    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, out, sc, ctr, 1);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
@@ -257,6 +269,11 @@ Tape slice(sim_t* S, int k) {
     t.mode += o; t.flags += o; t.cflags += o;
     t.n += k;
     return t;
+}
+
+void drop_graphs(sim_t* S) {
+    for (auto& g : S->graphs) (void)hipGraphExecDestroy(g.exec);
+    S->graphs.clear();
 }
 
 int alloc_adjoint(sim_t* S) {
@@ -377,6 +394,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
               dalloc(S, d_row_ptr, nn + 1) && dalloc(S, d_cbase, ne) && dalloc(S, d_ncell, ne) &&
               dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, ncls) && dalloc(S, S->d_cKab, ncls) &&
               dalloc(S, S->d_cVs, ncls) && dalloc(S, S->d_cB, ncls) && dalloc(S, S->d_epoch, 1) &&
+              dalloc(S, S->s.lanes, (size_t)S->nlanes) &&
               dalloc(S, S->s.cells, (size_t)cells) && dalloc(S, S->s.st_cnt, ne) &&
               dalloc(S, S->s.st_steps, ne) && dalloc(S, S->s.st_us, ne) && dalloc(S, S->ctr, 1) &&
               dalloc(S, dummy, 1);
@@ -403,6 +421,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     if (he == hipSuccess) he = hipMemsetAsync(S->s.st_steps, 0, sizeof(unsigned long long) * ne, S->stream);
     if (he == hipSuccess) he = hipMemsetAsync(S->s.st_us, 0, sizeof(unsigned long long) * ne, S->stream);
     if (he == hipSuccess) he = hipMemsetAsync(S->ctr, 0, sizeof(Counters), S->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(S->s.lanes, 0, sizeof(LaneIx) * (size_t)S->nlanes, S->stream);
     if (he == hipSuccess) {
         const unsigned one = 1u;
         he = hipMemcpyAsync(S->d_epoch, &one, sizeof(unsigned), hipMemcpyHostToDevice, S->stream);
@@ -595,6 +614,10 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     S->tr.placed = d_placed;
     S->h_rbeg = rbeg;
     S->grid = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)cap + kBlock - 1) / kBlock));
+    S->grid_small = std::max(1, S->grid / 4);
+    hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
+    HIPCHECK(S, hipGetLastError());
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
     S->loaded = true;
     return SIM_OK;
 }
@@ -676,6 +699,7 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
         const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
         const int K = (int)(t_end - ck.t);
         if ((rc = copy_state(S, S->rbuf[0], S->rpend[0], S->rctr, ck.v, ck.pend, ck.ctr))) return rc;
+        hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->rbuf[0], rs, S->rctr, 0);
         for (int k = 0; k < K; ++k) {
             if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], S->rpend[k & 1], S->rpend[(k + 1) & 1],
                                   rs, slice(S, k), S->rctr, nullptr)))
@@ -695,6 +719,8 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
             std::swap(L0v, L1v);
         }
     }
+    // the recompute pass re-indexed the lanes: index the live state again
+    hipLaunchKernelGGL(k_lanes, dim3(S->grid), b, 0, S->stream, S->buf[S->host_t & 1], S->s, S->ctr, 0);
     double* out64 = nullptr;
     hipLaunchKernelGGL(k_adj_reduce, dim3((nvals + 63) / 64), dim3(64), 0, S->stream, S->adj.gpart, (int)nthreads,
                        nvals, dL_dtheta, out64);
@@ -813,11 +839,249 @@ int sim_set_stream(sim_t* S, void* hip_stream) {
 
 void sim_destroy(sim_t* S) {
     if (!S) return;
+    drop_graphs(S);
     release_all(S);
     for (auto& evs : S->ev_steps)
         for (hipEvent_t e : evs) S->ev_free.push_back(e);
     for (hipEvent_t e : S->ev_free) (void)hipEventDestroy(e);
     delete S;
+}
+
+
+int sim_create_batch(int32_t n, const sim_network* nets, const sim_params* prms, void* hip_stream,
+                     sim_alloc_fn alloc, sim_free_fn free_fn, void* alloc_ctx, sim_t** out) {
+    if (n <= 0 || !nets || !prms || !out) return SIM_EINVAL;
+    const sim_params& p0 = prms[0];
+    std::vector<int32_t> row_ptr(1, 0), col_idx, lanes, cls;
+    std::vector<float> len, speed, idm;
+    std::vector<int> edge_off(1, 0);
+    int node_off = 0, class_off = 0;
+    for (int q = 0; q < n; ++q) {
+        const sim_network& N = nets[q];
+        const sim_params& P = prms[q];
+        if (!N.row_ptr || !N.col_idx || !N.lanes || !N.length_m || !N.speed_mps || !P.idm || N.num_nodes <= 0 ||
+            N.num_edges <= 0 || P.num_classes <= 0 || N.row_ptr[0] != 0 || N.row_ptr[N.num_nodes] != N.num_edges)
+            return SIM_EINVAL;
+        // everything but the car-following parameters is shared by the batch
+        if (P.dt != p0.dt || P.veh_length != p0.veh_length || P.s0 != p0.s0 || P.s_eps != p0.s_eps ||
+            P.b_max != p0.b_max || P.mobil_p != p0.mobil_p || P.mobil_athr != p0.mobil_athr ||
+            P.mobil_bsafe != p0.mobil_bsafe || P.mand_dist != p0.mand_dist ||
+            P.lc_cooldown_steps != p0.lc_cooldown_steps)
+            return SIM_EINVAL;
+        const int e0 = (int)col_idx.size();
+        for (int u = 0; u < N.num_nodes; ++u) row_ptr.push_back(e0 + N.row_ptr[u + 1]);
+        for (int e = 0; e < N.num_edges; ++e) {
+            if (N.col_idx[e] < 0 || N.col_idx[e] >= N.num_nodes) return SIM_EINVAL;
+            const int c = N.link_class ? N.link_class[e] : 0;
+            if (c < 0 || c >= P.num_classes) return SIM_EINVAL;
+            col_idx.push_back(N.col_idx[e] + node_off);
+            lanes.push_back(N.lanes[e]);
+            len.push_back(N.length_m[e]);
+            speed.push_back(N.speed_mps[e]);
+            cls.push_back(c + class_off);
+        }
+        idm.insert(idm.end(), P.idm, P.idm + 4 * (size_t)P.num_classes);
+        node_off += N.num_nodes;
+        class_off += P.num_classes;
+        edge_off.push_back((int)col_idx.size());
+        if ((long long)col_idx.size() > INT32_MAX / 2) return SIM_EINVAL;
+    }
+    sim_network net = {node_off, (int32_t)col_idx.size(), row_ptr.data(), col_idx.data(), lanes.data(), len.data(),
+                       speed.data(), cls.data()};
+    sim_params prm = p0;
+    prm.num_classes = class_off;
+    prm.idm = idm.data();
+    int rc = sim_create(&net, &prm, hip_stream, alloc, free_fn, alloc_ctx, out);
+    if (rc == SIM_OK) (*out)->batch_edge_off = edge_off;
+    return rc;
+}
+
+int sim_load_demand_batch(sim_t* S, int32_t n, const int32_t* num_trips, const int32_t* const* depart_step,
+                          const int32_t* const* trip_route, const int32_t* num_routes,
+                          const int64_t* const* route_ptr, const int32_t* const* route_edges) {
+    if (!S) return SIM_EINVAL;
+    if ((int)S->batch_edge_off.size() != n + 1 || n <= 0)
+        return fail(S, SIM_ESTATE, "handle was not created by sim_create_batch with this many scenarios");
+    if (!num_trips || !depart_step || !trip_route || !num_routes || !route_ptr || !route_edges)
+        return fail(S, SIM_EINVAL, "null batch demand arrays");
+    std::vector<int32_t> dep, trt, re;
+    std::vector<int64_t> rp(1, 0);
+    int route_off = 0;
+    for (int q = 0; q < n; ++q) {
+        const int ne_q = S->batch_edge_off[q + 1] - S->batch_edge_off[q];
+        if (num_trips[q] < 0 || num_routes[q] < 0 || !route_ptr[q] || route_ptr[q][0] != 0 ||
+            (num_trips[q] > 0 && (!depart_step[q] || !trip_route[q] || num_routes[q] == 0)))
+            return fail(S, SIM_EINVAL, "invalid demand of scenario " + std::to_string(q));
+        for (int i = 0; i < num_trips[q]; ++i) {
+            if (trip_route[q][i] < 0 || trip_route[q][i] >= num_routes[q])
+                return fail(S, SIM_EINVAL, "trip_route out of range in scenario " + std::to_string(q));
+            dep.push_back(depart_step[q][i]);
+            trt.push_back(trip_route[q][i] + route_off);
+        }
+        const long long base = (long long)re.size();
+        for (int r = 0; r < num_routes[q]; ++r) {
+            for (long long k = route_ptr[q][r]; k < route_ptr[q][r + 1]; ++k) {
+                const int e = route_edges[q][k];
+                if (e < 0 || e >= ne_q) return fail(S, SIM_EROUTE, "edge id out of range in scenario " + std::to_string(q));
+                re.push_back(e + S->batch_edge_off[q]);
+            }
+            rp.push_back(base + route_ptr[q][r + 1]);
+        }
+        route_off += num_routes[q];
+        if ((long long)re.size() > INT32_MAX - 2) return fail(S, SIM_EROUTE, "route_edges too long");
+    }
+    return sim_load_demand(S, (int32_t)dep.size(), dep.data(), trt.data(), route_off, rp.data(), re.data(), nullptr,
+                           nullptr, nullptr);
+}
+
+int sim_set_launch(sim_t* S, int32_t grid, int32_t grid_small) {
+    if (!S || grid <= 0 || grid_small <= 0 || grid > 65536 || grid_small > 65536) return SIM_EINVAL;
+    if (S->adj_ready) return fail(S, SIM_ESTATE, "launch shape is fixed once the adjoint buffers exist");
+    S->grid = grid;
+    S->grid_small = grid_small;
+    drop_graphs(S);
+    return SIM_OK;
+}
+
+int sim_get_launch(sim_t* S, int32_t* grid, int32_t* grid_small) {
+    if (!S || !grid || !grid_small) return SIM_EINVAL;
+    *grid = S->grid;
+    *grid_small = S->grid_small;
+    return SIM_OK;
+}
+
+int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
+    if (!S || num_steps < 0 || chunk <= 0) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (S->tape_on) return sim_step(S, num_steps);  // checkpoints are per-step host work: no capture
+    int done = 0;
+    for (;;) {
+        // with timing on, every timing_every-th step runs alone (timed) and the
+        // steps between are replayed from graphs of that length
+        int len = chunk;
+        if (S->timing_every > 0) {
+            const int to_timed = (int)(S->timing_every - (S->host_t % S->timing_every));
+            if (to_timed == S->timing_every) {
+                if (done >= num_steps) break;
+                int rc = sim_step(S, 1);
+                if (rc) return rc;
+                done += 1;
+                continue;
+            }
+            len = std::min(chunk, to_timed);
+        }
+        if (num_steps - done < len || len < 2) break;
+        const int parity = (int)(S->host_t & 1);
+        hipGraphExec_t exec = nullptr;
+        for (auto& g : S->graphs)
+            if (g.parity == parity && g.chunk == len) exec = g.exec;
+        if (!exec) {
+            if (S->graphs.size() >= 8) drop_graphs(S);
+            hipGraph_t graph;
+            HIPCHECK(S, hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal));
+            const Tape off{};
+            int rc = SIM_OK;
+            for (int k = 0; k < len && rc == SIM_OK; ++k) {
+                const int p = (parity + k) & 1;
+                rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->pend[p], S->pend[p ^ 1], S->s, off, S->ctr, nullptr);
+            }
+            hipError_t ce = hipStreamEndCapture(S->stream, &graph);
+            if (rc) return rc;
+            if (ce != hipSuccess) return fail(S, SIM_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+            ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ce != hipSuccess) return fail(S, SIM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+            sim_t::GraphEntry ge;
+            ge.parity = parity;
+            ge.chunk = len;
+            ge.exec = exec;
+            S->graphs.push_back(ge);
+        }
+        HIPCHECK(S, hipGraphLaunch(exec, S->stream));
+        S->host_t += len;
+        done += len;
+    }
+    return sim_step(S, num_steps - done);
+}
+
+int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t* best_small, float* best_ms) {
+    if (!S || steps_per_trial <= 0 || !best_grid || !best_small || !best_ms) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (S->tape_on || S->adj_ready) return fail(S, SIM_ESTATE, "no tuning inside a differentiation window");
+    // save the state and the statistics, try every candidate from the same
+    // state, restore; the step's results do not depend on the launch shape
+    sim_t::Ckpt save;
+    const int p = (int)(S->host_t & 1);
+    unsigned long long* st_save = nullptr;
+    int* trip_save = nullptr;
+    if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.pend, S->cap) || !dalloc(S, save.ctr, 1) ||
+        !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 2 * (size_t)S->cap))
+        return fail(S, SIM_ENOMEM, "autotune allocation failed");
+    const size_t tb = sizeof(int) * (size_t)S->cap;
+    HIPCHECK(S, hipMemcpyAsync(trip_save, S->tr.depart_actual, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
+    int rc = copy_state(S, save.v, save.pend, save.ctr, S->buf[p], S->pend[p], S->ctr);
+    if (rc) return rc;
+    const size_t eb = sizeof(unsigned long long) * (size_t)S->ne;
+    HIPCHECK(S, hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(st_save + S->ne, S->s.st_steps, eb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(st_save + 2 * (size_t)S->ne, S->s.st_us, eb, hipMemcpyDeviceToDevice, S->stream));
+    const long long t_save = S->host_t;
+    const int g0 = S->grid;
+    const int gcand[] = {g0 / 4, g0 / 2, g0, g0 * 2};
+    const int scand[] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    HIPCHECK(S, hipEventCreate(&e0));
+    HIPCHECK(S, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bg = S->grid, bs = S->grid_small;
+    const Tape off{};
+    for (int gc : gcand) {
+        if (gc < 1) continue;
+        for (int sd : scand) {
+            const int gs = std::max(1, gc / sd);
+            S->grid = gc;
+            S->grid_small = gs;
+            S->host_t = t_save;
+            if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, save.v, save.pend, save.ctr))) return rc;
+            hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
+            HIPCHECK(S, hipEventRecord(e0, S->stream));
+            for (int k = 0; k < steps_per_trial && rc == SIM_OK; ++k) {
+                const int q = (int)(S->host_t & 1);
+                rc = launch_step(S, S->buf[q], S->buf[q ^ 1], S->pend[q], S->pend[q ^ 1], S->s, off, S->ctr, nullptr);
+                S->host_t += 1;
+            }
+            if (rc) return rc;
+            HIPCHECK(S, hipEventRecord(e1, S->stream));
+            HIPCHECK(S, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHECK(S, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bg = gc;
+                bs = gs;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    S->host_t = t_save;
+    S->grid = bg;
+    S->grid_small = bs;
+    drop_graphs(S);
+    if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, save.v, save.pend, save.ctr))) return rc;
+    HIPCHECK(S, hipMemcpyAsync(S->s.st_cnt, st_save, eb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->s.st_steps, st_save + S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->tr.depart_actual, trip_save, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->tr.arrive_step, trip_save + S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
+    hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
+    HIPCHECK(S, hipGetLastError());
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    *best_grid = bg;
+    *best_small = bs;
+    *best_ms = best / (float)steps_per_trial;
+    return SIM_OK;
 }
 
 }  // extern "C"

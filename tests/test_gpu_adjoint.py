@@ -1,9 +1,12 @@
 """GPU adjoint (sim_grad, IDMTravelTime) against the FP64 CPU adjoint.
 
 The FP32 GPU forward equals the FP32 oracle bit for bit, so both record the
-same discrete events.  The CPU reference replays the FP32 oracle's event tape
-in FP64 and differentiates it (itself pinned by central differences); the GPU
-gradient must agree with it to 1e-3 of the gradient's largest component.
+same discrete events.  Two FP64 CPU references differentiate the FP32 oracle's
+event tape (the adjoint oracle is pinned by central differences):
+  * linearized at the recorded FP32 states -- the same trajectory the GPU
+    adjoint linearizes at: agreement to 1e-5 of the largest component;
+  * with the states replayed in FP64 -- differs from the FP32 trajectory by
+    rounding that the traffic dynamics amplify: agreement to 3e-3.
 """
 import numpy as np
 import pytest
@@ -29,12 +32,13 @@ def targets(scen):
     return np.where(es["count"] > 0, es["tt_us"] / np.maximum(es["count"], 1) / 1e6, 0.0)
 
 
-def cpu_reference(scen, target):
+def cpu_reference(scen, target, at_tape_states=True):
     o = oracle.Oracle(scen, "f32", tape=True)
     o.step(scen["steps"])
     es = o.edge_stats()
     mask = es["count"] > 0
-    loss, g, tbar, _, _ = oracle.replay(o.tape(), scen, scen["params"]["idm"].astype(np.float64), target, mask)
+    loss, g, tbar, _, _ = oracle.replay(o.tape(), scen, scen["params"]["idm"].astype(np.float64), target, mask,
+                                        at_tape_states=at_tape_states)
     return loss, g, mask
 
 
@@ -59,11 +63,14 @@ def gpu_grad(scen, target, every):
 def test_gpu_adjoint_matches_fp64_cpu_adjoint(every):
     scen = diff_small()
     tgt = targets(scen)
-    loss_c, g_c, _ = cpu_reference(scen, tgt)
+    loss_c, g_c, _ = cpu_reference(scen, tgt, at_tape_states=True)
     _, g_g, loss_g = gpu_grad(scen, tgt, every)
-    assert abs(loss_g - loss_c) <= 1e-4 * loss_c
+    assert abs(loss_g - loss_c) <= 1e-5 * loss_c
     err = np.abs(g_g - g_c).max() / np.abs(g_c).max()
-    assert err < 1e-3, (err, g_g, g_c)
+    assert err < 1e-5, (err, g_g, g_c)
+    _, g_r, _ = cpu_reference(scen, tgt, at_tape_states=False)
+    err_r = np.abs(g_g - g_r).max() / np.abs(g_r).max()
+    assert err_r < 3e-3, err_r
 
 
 def test_gpu_adjoint_independent_of_checkpoint_interval_and_deterministic():
@@ -113,4 +120,4 @@ def test_autograd_function():
     loss.backward()
     _, g_c, _ = cpu_reference(scen, tgt)
     err = np.abs(theta.grad.numpy().astype(np.float64) - g_c).max() / np.abs(g_c).max()
-    assert err < 1e-3, err
+    assert err < 1e-5, err

@@ -1,0 +1,115 @@
+"""GPU: batched ensembles, graph-captured steps, launch shapes and the autotuner.
+
+Every one of these must leave the simulated results bit-identical:
+  * a batch of scenarios equals the scenarios run one by one;
+  * graph-captured chunks equal plain launches;
+  * any launch shape gives the same results; the autotuner restores the state.
+"""
+import numpy as np
+import pytest
+
+import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+
+def small_scenarios(n=5, seed=40):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        side = int(rng.integers(4, 9))
+        net = S.grid(side, seed=seed + q, link_len=60.0, lanes=2, speed=15.0)
+        p = S.default_params()
+        p["idm"] = S.draw_idm(rng, 1)
+        ntr = int(rng.integers(100, 400))
+        o, d = S.uniform_od(rng, side * side, ntr)
+        dep = rng.uniform(0.0, 120.0, ntr)
+        out.append({"name": "e%d" % q, "net": net, "params": p,
+                    "demand": S.make_demand(net, o, d, dep, p["dt"]), "steps": 500})
+    return out
+
+
+def per_trip(sim, dep):
+    from paper_1807_01148_amd.ensemble import vehicle_ids
+    tr = sim.trips()
+    v = vehicle_ids(dep)
+    return {k: a[v] for k, a in tr.items()}
+
+
+def test_batch_equals_separate_runs():
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import Ensemble
+    scens = small_scenarios()
+    ens = Ensemble(scens)
+    ens.step(500)
+    est, etr = ens.edge_stats(), ens.trips()
+    total = 0
+    for q, sc in enumerate(scens):
+        one = P.Sim(sc)
+        one.step(500)
+        a, b = ens.scenario_edge_stats(q, est), one.edge_stats()
+        for k in b:
+            assert np.array_equal(a[k], b[k]), (q, k)
+        ta, tb = ens.scenario_trips(q, etr), per_trip(one, sc["demand"]["depart_step"])
+        for k in tb:
+            assert np.array_equal(ta[k], tb[k]), (q, k)
+        total += one.counters()["vehicle_updates"]
+    assert ens.counters()["vehicle_updates"] == total
+
+
+def test_graph_chunks_equal_plain_steps():
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import step_graph
+    sc = S.small_grid()
+    a, b = P.Sim(sc), P.Sim(sc)
+    a.step(3600)
+    step_graph(b, 3600, 60)
+    step_graph(b, 0, 60)
+    Va, Vb = a.vehicles(), b.vehicles()
+    for k in Va:
+        assert np.array_equal(Va[k], Vb[k])
+    assert a.counters() == b.counters()
+    for k, v in a.edge_stats().items():
+        assert np.array_equal(v, b.edge_stats()[k])
+    # odd start parity and a remainder
+    c, d = P.Sim(sc), P.Sim(sc)
+    c.step(1001)
+    d.step(1)
+    step_graph(d, 1000, 60)
+    assert c.counters() == d.counters()
+    for k, v in c.vehicles().items():
+        assert np.array_equal(v, d.vehicles()[k])
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 1), (64, 8), (4096, 512)])
+def test_launch_shape_does_not_change_results(shape):
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import set_launch
+    sc = S.mid_grid(n_trips=20000)
+    ref, alt = P.Sim(sc), P.Sim(sc)
+    set_launch(alt, *shape)
+    ref.step(1500)
+    alt.step(1500)
+    assert ref.counters() == alt.counters()
+    for k, v in ref.vehicles().items():
+        assert np.array_equal(v, alt.vehicles()[k])
+
+
+def test_autotune_restores_state():
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import autotune, get_launch
+    sc = S.mid_grid(n_trips=20000)
+    ref, tun = P.Sim(sc), P.Sim(sc)
+    ref.step(600)
+    tun.step(600)
+    before = tun.counters()
+    res = autotune(tun, steps_per_trial=30)
+    assert tun.counters() == before
+    assert get_launch(tun) == (res["grid"], res["grid_small"])
+    ref.step(900)
+    tun.step(900)
+    assert ref.counters() == tun.counters()
+    for k, v in ref.vehicles().items():
+        assert np.array_equal(v, tun.vehicles()[k])
+    for k, v in ref.trips().items():
+        assert np.array_equal(v, tun.trips()[k])

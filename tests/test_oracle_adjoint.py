@@ -99,3 +99,18 @@ def test_adjoint_chain_exact(n):
     fd = fd_grad(o.tape(), scen, th, tgt, mask, 1e-5)
     assert np.abs(fd - g).max() <= 1e-8 * max(1.0, np.abs(g).max())
     assert abs(g[0, 2]) > 0.1  # the acceleration matters
+
+
+def test_tape_states_equal_replay_on_fp64_tape():
+    """Linearizing at the recorded states is the same computation as replaying
+    them when the tape comes from the FP64 forward (whose states the replay
+    reproduces exactly)."""
+    scen = small_diff(seed=7)
+    o = run_taped(scen, "f64")
+    es = o.edge_stats()
+    mask = es["count"] > 0
+    th = scen["params"]["idm"].astype(np.float64)
+    tgt = np.where(mask, es["tt_us"] / np.maximum(es["count"], 1) / 1e6 * 1.1, 0.0)
+    a = oracle.replay(o.tape(), scen, th, tgt, mask)
+    b = oracle.replay(o.tape(), scen, th, tgt, mask, at_tape_states=True)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
