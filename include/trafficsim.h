@@ -133,15 +133,35 @@ int sim_stats(sim_t* sim, sim_stats_t* host_out, int64_t* edge_count, int64_t* e
  * library's lane order; synchronises).  *n_out = number on the road (if it
  * exceeds cap nothing is copied and SIM_EINVAL is returned).  Any array may
  * be NULL.  cursor = index of the current edge within the vehicle's route;
- * lc = step of the last lane change; kin/phin = entry step / fraction. */
+ * lc = step of the last lane change; kin/phin = entry step / fraction; fuel (mL)
+ * and co (g) = accumulated so far (Sec. 6.3.4). */
 int sim_read_vehicles(sim_t* sim, int32_t cap, int32_t* n_out, int32_t* vid, int32_t* edge,
                       int32_t* lane, int32_t* cursor, int32_t* lc, int32_t* kin, float* x,
-                      float* v, float* phin);
+                      float* v, float* phin, float* fuel, float* co);
 
 /* Copy per-vehicle-id outcomes to HOST arrays [num_trips]: the step at which the
  * vehicle appeared on the road (-1 if not yet) and the first step after its
  * arrival (-1 if not arrived).  Synchronises. */
 int sim_read_trips(sim_t* sim, int32_t* depart_actual, int32_t* arrive_step);
+
+/* Fuel (mL) and CO (g) of every vehicle id over its whole trip, written at its
+ * arrival (0 before), to HOST arrays [num_trips].  Per step each vehicle adds
+ * rate*dt: fuel rate 0.666 + 0.072*max(0, 0.269v + 0.0171v^2 + 0.000672v^3 +
+ * 1.680av + P_ea), P_ea = 0.79296a^2v for a > 0 (v in m/s, a = realized
+ * acceleration of the step); CO rate -0.064 + 0.0056vm + 0.00026(vm-50)^2 (vm in
+ * mph) -- the two equations of Sec. 6.3.4.  Synchronises. */
+int sim_read_emissions(sim_t* sim, float* fuel, float* co);
+
+/* Utilization / speed sampler (Sec. 6.4): every `every` steps (120 = 1 min at
+ * dt = 0.5 s) each link adds its number of vehicles and the sum of their speeds
+ * (micrometres per second, rounded) to sample group floor(t/every)/group
+ * (group 6 = 6-minute averages); groups beyond max_groups are dropped.
+ * Allocates 16 B x max_groups x num_edges of device memory.  Utilization of a
+ * link in a group = count / (group * length * lanes / (veh_length + s0)). */
+int sim_set_sampler(sim_t* sim, int32_t every, int32_t group, int32_t max_groups);
+
+/* Copy the sampler sums to HOST arrays [max_groups][num_edges].  Synchronises. */
+int sim_read_samples(sim_t* sim, int64_t* count, int64_t* speed_um);
 
 /* Replace the IDM parameters (same num_classes) between steps; derived
  * constants are recomputed as in sim_create.  Errors: SIM_EINVAL. */

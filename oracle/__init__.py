@@ -72,6 +72,10 @@ def _lib(prec):
         lib.or_num_active.restype = i32
         lib.or_num_pending.argtypes = [P]
         lib.or_num_pending.restype = i32
+        lib.or_get_emissions.argtypes = [P, P, P]
+        lib.or_set_sampler.argtypes = [P, i32, i32, i32]
+        lib.or_set_sampler.restype = ctypes.c_int
+        lib.or_get_samples.argtypes = [P, P, P]
         lib.or_tape_enable.argtypes = [P, i32]
         lib.or_tape_size.argtypes = [P]
         lib.or_tape_size.restype = ctypes.c_int64
@@ -194,13 +198,33 @@ class Oracle:
     def vehicles(self) -> dict:
         n = self.lib.or_num_active(self.h)
         iv = np.zeros((max(n, 1), 6), np.int32)
-        rv = np.zeros((max(n, 1), 3), np.float64)
+        rv = np.zeros((max(n, 1), 5), np.float64)
         n = self.lib.or_get_vehicles(self.h, _p(iv), _p(rv))
         iv, rv = iv[:n], rv[:n]
         dt = np.float32 if self.precision == "f32" else np.float64
         return {"vid": iv[:, 0].copy(), "edge": iv[:, 1].copy(), "lane": iv[:, 2].copy(),
                 "cursor": iv[:, 3].copy(), "lc": iv[:, 4].copy(), "kin": iv[:, 5].copy(),
-                "x": rv[:, 0].astype(dt), "v": rv[:, 1].astype(dt), "phin": rv[:, 2].astype(dt)}
+                "x": rv[:, 0].astype(dt), "v": rv[:, 1].astype(dt), "phin": rv[:, 2].astype(dt),
+                "fuel": rv[:, 3].astype(dt), "co": rv[:, 4].astype(dt)}
+
+    def emissions(self) -> dict:
+        """Fuel (mL) and CO (g) of every vehicle id at its arrival (0 before)."""
+        f = np.zeros(self.ntrips, np.float64)
+        c = np.zeros(self.ntrips, np.float64)
+        self.lib.or_get_emissions(self.h, _p(f), _p(c))
+        dt = np.float32 if self.precision == "f32" else np.float64
+        return {"fuel": f.astype(dt), "co": c.astype(dt)}
+
+    def set_sampler(self, every: int = 120, group: int = 6, max_groups: int = 32):
+        if self.lib.or_set_sampler(self.h, int(every), int(group), int(max_groups)) != 0:
+            raise OracleError("or_set_sampler failed")
+        self._samp = int(max_groups)
+
+    def samples(self) -> dict:
+        cnt = np.zeros((self._samp, self.ne), np.int64)
+        spd = np.zeros((self._samp, self.ne), np.int64)
+        self.lib.or_get_samples(self.h, _p(cnt), _p(spd))
+        return {"count": cnt, "speed_um": spd}
 
     def trips(self) -> dict:
         da = np.zeros(self.ntrips, np.int32)

@@ -57,6 +57,7 @@ enum { TM_STAY = 0, TM_CHANGE = 1, TM_YIELD = 2, TM_ARRIVE = 3, TM_CROSS = 4, TM
 typedef struct {
     int32_t vid, edge, lane, rcur, next, lc, kin;
     real x, v, phin;
+    real fuel, co; /* accumulated fuel (mL) and CO (g) */
 } veh_t;
 
 typedef struct {
@@ -69,6 +70,7 @@ typedef struct {
     real dt, h, lveh, s0, claim_len, s_eps, b_max, p, athr, bsafe, dmand, dt_us_f;
     int64_t dt_us;
     real *T, *A, *kab;
+    real mph; /* miles per hour per m/s */
     /* demand, indexed by vehicle id */
     int32_t ntrips, loaded;
     int32_t *dep, *rbeg, *rend, *route_edges;
@@ -80,6 +82,11 @@ typedef struct {
     int32_t* pend;
     int64_t *st_cnt, *st_steps, *st_us;
     int64_t departed, arrived, updates, claims_lost, clamps;
+    real *fuel_total, *co_total; /* per vehicle id, at arrival */
+    /* sampler: every `samp_every` steps, per link vehicle count and speed sum
+     * (micrometres per second), accumulated in groups of `samp_group` samples */
+    int32_t samp_every, samp_group, samp_max;
+    int64_t *samp_cnt, *samp_spd;
     /* event tape (discrete outcomes of every step, for the frozen-event replay) */
     int tape_on;
     int64_t tp_n, tp_cap;
@@ -144,6 +151,7 @@ osim* or_create(int32_t nn, int32_t ne, const int32_t* row_ptr, const int32_t* c
     S->claim_len = (real)((double)fp[1] + (double)fp[2]);
     S->dt_us = llround((double)fp[0] * 1e6);
     S->dt_us_f = (real)((double)fp[0] * 1e6);
+    S->mph = (real)(1.0 / 0.44704);
     for (int c = 0; c < ncls; ++c) {
         double a = idm[4 * c + 2], b = idm[4 * c + 3];
         if (!(a > 0) || !(b > 0) || !(idm[4 * c + 0] > 0) || !(idm[4 * c + 1] >= 0)) goto bad;
@@ -184,6 +192,7 @@ void or_destroy(osim* S) {
     free(S->st_cnt); free(S->st_steps); free(S->st_us);
     free(S->tp_step); free(S->tp_vid); free(S->tp_mode); free(S->tp_lead); free(S->tp_flags);
     free(S->tp_edge); free(S->tp_x0); free(S->tp_v0);
+    free(S->fuel_total); free(S->co_total); free(S->samp_cnt); free(S->samp_spd);
     free(S);
 }
 
@@ -250,6 +259,8 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
     S->rend = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
     S->depart_actual = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
     S->arrive_step = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
+    S->fuel_total = (real*)calloc(ntrips + 1, sizeof(real));
+    S->co_total = (real*)calloc(ntrips + 1, sizeof(real));
     S->nroute_edges = nre;
     S->route_edges = (int32_t*)malloc(sizeof(int32_t) * (nre + 1));
     memcpy(S->route_edges, route_edges, sizeof(int32_t) * nre);
@@ -283,6 +294,8 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
             q->lc = LC_NONE;
             q->kin = S->t;
             q->phin = (real)1;
+            q->fuel = (real)0;
+            q->co = (real)0;
             if (q->lane < 0 || q->lane >= S->lanes[q->edge] || !(init_x[i] >= 0) ||
                 !(init_x[i] <= (float)S->len[q->edge]) || (init_v && !(init_v[i] >= 0))) {
                 free(ord);
@@ -407,6 +420,7 @@ typedef struct {
     real X, vc, f;               /* front on the target, speed, crossing fraction */
     int32_t lo, hi;              /* claim cells */
     int clamped;
+    real vn;                     /* speed after the own-lane motion */
     int own_fl, chg_fl;          /* branch flags of the own-lane and the lane-change motion */
     int32_t own_lead, chg_lead;  /* vehicle ahead used by each (-1: free road) */
 } dec_t;
@@ -500,6 +514,7 @@ static dec_t decide(const view_t* W, int32_t o) {
     real dx, vn;
     move_fl(S, v, ac, &dx, &vn, &D.own_fl);
     D.clamped = clampmv_fl(L, &dx, &vn, &D.own_fl);
+    D.vn = vn;
     real xs = x + dx;
     if (xs > len) { /* the front passes the link end strictly */
         real fq = (len - x) / dx;
@@ -623,6 +638,24 @@ static dec_t decide(const view_t* W, int32_t o) {
     return D;
 }
 
+/* Fuel and CO over one step (Sec. 6.3.4): the fuel-consumption equation with
+ * v in m/s and the realized acceleration a = (v' - v)/dt, its bracket floored
+ * at 0 (fuel never below idle), P_ea = 0.79296 a^2 v only while accelerating;
+ * the CO equation with v in miles per hour; both rates integrated over dt. */
+static void emissions(const osim* S, veh_t* q, real v1) {
+    real v = q->v;
+    real a = (v1 - v) / S->dt;
+    real vm = v * S->mph;
+    real d = vm - (real)50;
+    real c = (real)-0.064 + (real)0.0056 * vm + (real)0.00026 * (d * d);
+    real pea = a > (real)0 ? ((real)0.79296 * (a * a)) * v : (real)0;
+    real br = (real)0.269 * v + (real)0.0171 * (v * v) + (real)0.000672 * ((v * v) * v) + (real)1.680 * (a * v) + pea;
+    br = RMAX(br, (real)0);
+    real f = (real)0.666 + (real)0.072 * br;
+    q->fuel = q->fuel + f * S->dt;
+    q->co = q->co + c * S->dt;
+}
+
 static void record_exit(osim* S, const veh_t* q, real f, int32_t t) {
     int64_t ns = (int64_t)(t + 1) - q->kin;
     real frac = f - q->phin;
@@ -647,6 +680,18 @@ static int step_once(osim* S) {
         cnt[k] += 1;
     }
     view_t W = {S, S->act, ord, first, cnt};
+
+    /* utilization / speed sample of the state at t (Sec. 6.4) */
+    if (S->samp_every > 0 && t % S->samp_every == 0) {
+        int32_t g = (t / S->samp_every) / S->samp_group;
+        if (g < S->samp_max) {
+            for (int32_t o = 0; o < N; ++o) {
+                const veh_t* q = at(&W, o);
+                S->samp_cnt[(int64_t)g * S->ne + q->edge] += 1;
+                S->samp_spd[(int64_t)g * S->ne + q->edge] += (int64_t)RRINT(q->v * (real)1e6);
+            }
+        }
+    }
 
     /* 1. decisions of the vehicles on the road */
     dec_t* D = (dec_t*)malloc(sizeof(dec_t) * (N + 1));
@@ -726,9 +771,18 @@ static int step_once(osim* S) {
         }
         if (d->kind == K_ARRIVE) {
             record_exit(S, &q, d->f, t);
+            emissions(S, &q, d->vn);
+            S->fuel_total[q.vid] = q.fuel;
+            S->co_total[q.vid] = q.co;
             S->arrive_step[q.vid] = t + 1;
             S->arrived += 1;
             continue;
+        }
+        {
+            real v1 = d->vs; /* the speed the vehicle ends the step with */
+            if (d->kind == K_CROSS && cwin_veh[o]) v1 = d->vc;
+            else if (d->kind == K_CHANGE && cwin_veh[o]) v1 = d->vc;
+            emissions(S, &q, v1);
         }
         if (d->kind == K_CROSS && cwin_veh[o]) {
             record_exit(S, &q, d->f, t);
@@ -766,6 +820,8 @@ static int step_once(osim* S) {
             q.lc = LC_NONE;
             q.kin = t + 1;
             q.phin = (real)1;
+            q.fuel = (real)0;
+            q.co = (real)0;
             nact[nn++] = q;
             S->depart_actual[v] = t + 1;
             S->departed += 1;
@@ -816,7 +872,7 @@ static int cmp_vid(const void* a, const void* b) {
 }
 
 /* active vehicles sorted by vehicle id; ints: vid, edge, lane, cursor (index
- * in the route), lc, kin; reals (as double): x, v, phin */
+ * in the route), lc, kin; reals (as double): x, v, phin, fuel, co */
 int32_t or_get_vehicles(osim* S, int32_t* iv, double* rv) {
     qsort(S->act, S->nact, sizeof(veh_t), cmp_vid);
     for (int32_t i = 0; i < S->nact; ++i) {
@@ -827,11 +883,37 @@ int32_t or_get_vehicles(osim* S, int32_t* iv, double* rv) {
         iv[6 * i + 3] = q->rcur - S->rbeg[q->vid];
         iv[6 * i + 4] = q->lc;
         iv[6 * i + 5] = q->kin;
-        rv[3 * i + 0] = (double)q->x;
-        rv[3 * i + 1] = (double)q->v;
-        rv[3 * i + 2] = (double)q->phin;
+        rv[5 * i + 0] = (double)q->x;
+        rv[5 * i + 1] = (double)q->v;
+        rv[5 * i + 2] = (double)q->phin;
+        rv[5 * i + 3] = (double)q->fuel;
+        rv[5 * i + 4] = (double)q->co;
     }
     return S->nact;
+}
+
+void or_get_emissions(const osim* S, double* fuel, double* co) {
+    for (int32_t v = 0; v < S->ntrips; ++v) {
+        fuel[v] = (double)S->fuel_total[v];
+        co[v] = (double)S->co_total[v];
+    }
+}
+
+int or_set_sampler(osim* S, int32_t every, int32_t group, int32_t max_groups) {
+    if (every <= 0 || group <= 0 || max_groups <= 0) return OR_EINVAL;
+    free(S->samp_cnt);
+    free(S->samp_spd);
+    S->samp_every = every;
+    S->samp_group = group;
+    S->samp_max = max_groups;
+    S->samp_cnt = (int64_t*)calloc((size_t)max_groups * S->ne, sizeof(int64_t));
+    S->samp_spd = (int64_t*)calloc((size_t)max_groups * S->ne, sizeof(int64_t));
+    return OR_OK;
+}
+
+void or_get_samples(const osim* S, int64_t* cnt, int64_t* spd) {
+    memcpy(cnt, S->samp_cnt, sizeof(int64_t) * (size_t)S->samp_max * S->ne);
+    memcpy(spd, S->samp_spd, sizeof(int64_t) * (size_t)S->samp_max * S->ne);
 }
 
 void or_get_trips(const osim* S, int32_t* depart_actual, int32_t* arrive_step) {

@@ -21,7 +21,9 @@ SIM_OK, SIM_EINVAL, SIM_EROUTE, SIM_ENOMEM, SIM_EHIP, SIM_ESTATE = 0, -1, -2, -3
 
 EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_vehicles",
             "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
-            "sim_grad", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
+            "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
+            "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -75,10 +77,16 @@ def library(path: str = LIB_PATH):
         lib.sim_step.restype = ctypes.c_int
         lib.sim_stats.argtypes = [P, ctypes.POINTER(SimStats), P, P, P]
         lib.sim_stats.restype = ctypes.c_int
-        lib.sim_read_vehicles.argtypes = [P, i32, ctypes.POINTER(i32), P, P, P, P, P, P, P, P, P]
+        lib.sim_read_vehicles.argtypes = [P, i32, ctypes.POINTER(i32), P, P, P, P, P, P, P, P, P, P, P]
         lib.sim_read_vehicles.restype = ctypes.c_int
         lib.sim_read_trips.argtypes = [P, P, P]
         lib.sim_read_trips.restype = ctypes.c_int
+        lib.sim_read_emissions.argtypes = [P, P, P]
+        lib.sim_read_emissions.restype = ctypes.c_int
+        lib.sim_set_sampler.argtypes = [P, i32, i32, i32]
+        lib.sim_set_sampler.restype = ctypes.c_int
+        lib.sim_read_samples.argtypes = [P, P, P]
+        lib.sim_read_samples.restype = ctypes.c_int
         lib.sim_set_idm.argtypes = [P, P]
         lib.sim_set_idm.restype = ctypes.c_int
         lib.sim_set_timing.argtypes = [P, i32]
@@ -226,10 +234,11 @@ class Sim:
         n = ctypes.c_int32(0)
         cap = self.num_trips
         iv = {k: np.zeros(max(cap, 1), np.int32) for k in ("vid", "edge", "lane", "cursor", "lc", "kin")}
-        fv = {k: np.zeros(max(cap, 1), np.float32) for k in ("x", "v", "phin")}
+        fv = {k: np.zeros(max(cap, 1), np.float32) for k in ("x", "v", "phin", "fuel", "co")}
         self._check(self.lib.sim_read_vehicles(self.h, cap, ctypes.byref(n), _p(iv["vid"]), _p(iv["edge"]),
                                                _p(iv["lane"]), _p(iv["cursor"]), _p(iv["lc"]), _p(iv["kin"]),
-                                               _p(fv["x"]), _p(fv["v"]), _p(fv["phin"])))
+                                               _p(fv["x"]), _p(fv["v"]), _p(fv["phin"]), _p(fv["fuel"]),
+                                               _p(fv["co"])))
         m = n.value
         o = np.argsort(iv["vid"][:m], kind="stable")
         out = {k: a[:m][o] for k, a in iv.items()}
@@ -241,6 +250,25 @@ class Sim:
         ar = np.zeros(self.num_trips, np.int32)
         self._check(self.lib.sim_read_trips(self.h, _p(da), _p(ar)))
         return {"depart_actual": da, "arrive_step": ar}
+
+    def emissions(self) -> dict:
+        """Fuel (mL) and CO (g) of every vehicle id over its trip (0 before arrival)."""
+        f = np.zeros(self.num_trips, np.float32)
+        c = np.zeros(self.num_trips, np.float32)
+        self._check(self.lib.sim_read_emissions(self.h, _p(f), _p(c)))
+        return {"fuel": f, "co": c}
+
+    def set_sampler(self, every: int = 120, group: int = 6, max_groups: int = 32):
+        """Sample link utilization and speed every ``every`` steps, in groups."""
+        self._check(self.lib.sim_set_sampler(self.h, int(every), int(group), int(max_groups)))
+        self._samp = (int(max_groups), int(group))
+
+    def samples(self) -> dict:
+        g = self._samp[0]
+        cnt = np.zeros((g, self.num_edges), np.int64)
+        spd = np.zeros((g, self.num_edges), np.int64)
+        self._check(self.lib.sim_read_samples(self.h, _p(cnt), _p(spd)))
+        return {"count": cnt, "speed_um": spd}
 
     def set_timing(self, every: int):
         """Sample per-kernel HIP-event timings on every ``every``-th step."""

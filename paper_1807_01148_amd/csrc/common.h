@@ -36,6 +36,7 @@ struct Counters {
 
 struct Params {
     float dt, h, lveh, s0, claim_len, s_eps, b_max, pol, athr, bsafe, dmand, dt_us_f;
+    float mph;  // miles per hour per m/s
     long long dt_us;
     int lc_cool;
 };
@@ -50,6 +51,7 @@ struct Net {
     const int* row_ptr;
     const long long* cbase;  // first claim cell of lane 0 of the edge
     const int* ncell;        // cells per lane = floor(len) + 1
+    int ne;                  // number of edges
     const float* cT;
     const float* cA;
     const float* cKab;
@@ -66,6 +68,8 @@ struct Trips {
     const unsigned char* placed;
     int* depart_actual;
     int* arrive_step;
+    float* fuel_total;  // per vehicle id, at arrival
+    float* co_total;
 };
 
 struct Veh {
@@ -79,6 +83,8 @@ struct Veh {
     int* kin;
     float* phin;
     int* vid;
+    float* fuel;  // accumulated fuel (mL)
+    float* co;    // accumulated CO (g)
 };
 
 // Entries [lo, hi] of the sorted arrays are the vehicles of one lane, valid
@@ -124,6 +130,11 @@ struct Scratch {
     unsigned long long* st_cnt;
     unsigned long long* st_steps;
     unsigned long long* st_us;
+    // sampler: every samp_every steps, per link vehicle count and speed sum
+    // (micrometres per second), accumulated in groups of samp_group samples
+    int samp_every, samp_group, samp_max;
+    unsigned long long* samp_cnt;
+    unsigned long long* samp_spd;
     unsigned* epoch;  // executed-step counter (claims, scan statuses, lane index are tagged with it)
     LaneIx* lanes;  // per global lane: first and last entry in the sorted arrays
 };
@@ -276,6 +287,22 @@ __device__ __forceinline__ int ub_keyx(const int* __restrict__ key, const float*
         else hi = mid;
     }
     return lo;
+}
+
+// Fuel and CO over one step (Sec. 6.3.4): fuel-consumption equation with v in
+// m/s and the realized acceleration a = (v1 - v)/dt, bracket floored at 0,
+// P_ea only while accelerating; CO equation with v in miles per hour.
+__device__ __forceinline__ void emissions(const Params& P, float v, float v1, float& fuel, float& co) {
+    const float a = (v1 - v) / P.dt;
+    const float vm = v * P.mph;
+    const float d = vm - 50.0f;
+    const float c = -0.064f + 0.0056f * vm + 0.00026f * (d * d);
+    const float pea = a > 0.0f ? (0.79296f * (a * a)) * v : 0.0f;
+    float br = 0.269f * v + 0.0171f * (v * v) + 0.000672f * ((v * v) * v) + 1.680f * (a * v) + pea;
+    br = fmx(br, 0.0f);
+    const float f = 0.666f + 0.072f * br;
+    fuel = fuel + f * P.dt;
+    co = co + c * P.dt;
 }
 
 // claims of a later executed step always beat those of an earlier one

@@ -65,6 +65,15 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     clamps += clamp_to_leader_fl(L, dx, vn, own_fl);
     const float xs = x + dx;
     const int vid = in.vid[i];
+    // utilization / speed sample of the state at t (Sec. 6.4)
+    if (s.samp_every > 0 && t % s.samp_every == 0) {
+        const int g = (t / s.samp_every) / s.samp_group;
+        if (g < s.samp_max) {
+            const size_t o = (size_t)g * (size_t)net.ne + (size_t)e;
+            atomicAdd(s.samp_cnt + o, 1ull);
+            atomicAdd(s.samp_spd + o, (unsigned long long)(long long)rintf(v * 1e6f));
+        }
+    }
     if (tp.on) {
         tp.x[i] = x;
         tp.v[i] = v;
@@ -87,6 +96,10 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         }
         if (nx < 0) {  // arrival at the end of the last link
             record_exit(P, s, e, in.kin[i], in.phin[i], f, t);
+            float fu = in.fuel[i], co = in.co[i];
+            emissions(P, v, vn, fu, co);
+            tr.fuel_total[vid] = fu;
+            tr.co_total[vid] = co;
             tr.arrive_step[vid] = t + 1;
             s.stay[i] = 0;
             arrivals += 1;
@@ -450,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
 // ---------------------------------------------------------------------------
 // k_scatter: survivors to their new slot; movers stage their sort keys
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
+__global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
     const int N = ctr->n;
     const int M = ctr->nmove;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N + M; i += gridDim.x * kBlock) {
@@ -468,6 +481,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, 
             out.kin[j] = in.kin[i];
             out.phin[j] = in.phin[i];
             out.vid[j] = in.vid[i];
+            float fu = in.fuel[i], co = in.co[i];
+            emissions(P, in.v[i], s.vs[i], fu, co);
+            out.fuel[j] = fu;
+            out.co[j] = co;
         } else {
             const int m = i - N;
             const int p = s.mv_p[m];
@@ -483,8 +500,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Veh in, Veh out, Scratch s, 
 // ---------------------------------------------------------------------------
 // k_place: movers take their rank inside their gap
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scratch s, Tape tp, int lc_none,
-                                                  Counters* ctr) {
+__global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Veh out, Scratch s, Tape tp,
+                                                  int lc_none, Counters* ctr) {
     const int t = ctr->t;
     const int M = ctr->nmove;
     for (int m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
@@ -511,6 +528,15 @@ __global__ __launch_bounds__(kBlock) void k_place(Trips tr, Veh in, Veh out, Scr
         out.v[j] = s.cl_v[ci];
         out.edge[j] = s.cl_tedge[ci];
         out.vid[j] = vid;
+        if (src >= 0) {
+            float fu = in.fuel[src], co = in.co[src];
+            emissions(P, in.v[src], s.cl_v[ci], fu, co);
+            out.fuel[j] = fu;
+            out.co[j] = co;
+        } else {
+            out.fuel[j] = 0.0f;
+            out.co[j] = 0.0f;
+        }
         if (kind == kCross) {
             const int rc = in.rcur[src] + 1;
             out.rcur[j] = rc;

@@ -214,9 +214,9 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, co
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
     hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
-    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, in, out, sc, tp, ctr);
+    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
-    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->tr, in, out, sc, tp, kLcNone, ctr);
+    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->P, S->tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
     hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, out, sc, ctr, 1);
     if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
@@ -227,7 +227,7 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, co
 bool alloc_veh(sim_t* S, Veh& V, size_t n) {
     return dalloc(S, V.key, n) && dalloc(S, V.x, n) && dalloc(S, V.v, n) && dalloc(S, V.edge, n) &&
            dalloc(S, V.rcur, n) && dalloc(S, V.next, n) && dalloc(S, V.lc, n) && dalloc(S, V.kin, n) &&
-           dalloc(S, V.phin, n) && dalloc(S, V.vid, n);
+           dalloc(S, V.phin, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) && dalloc(S, V.co, n);
 }
 
 int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, const Veh& sv, const int* spend,
@@ -244,6 +244,8 @@ int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, const Veh& s
     HIPCHECK(S, hipMemcpyAsync(dv.kin, sv.kin, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.phin, sv.phin, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.vid, sv.vid, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.fuel, sv.fuel, sizeof(float) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.co, sv.co, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dpend, spend, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dctr, sctr, sizeof(Counters), k, S->stream));
     return SIM_OK;
@@ -385,6 +387,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     P.dt_us = std::llround((double)prm->dt * 1e6);
     P.dt_us_f = (float)((double)prm->dt * 1e6);
     P.lc_cool = prm->lc_cooldown_steps;
+    P.mph = (float)(1.0 / 0.44704);
 
     float *d_len, *dummy;
     int *d_lane_base, *d_lanes, *d_cls, *d_head, *d_row_ptr, *d_ncell;
@@ -452,6 +455,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     N.cKab = S->d_cKab;
     N.cVs = S->d_cVs;
     N.cB = S->d_cB;
+    N.ne = ne;
     S->s.epoch = S->d_epoch;
     *out = S;
     return SIM_OK;
@@ -560,12 +564,14 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     bool ok = dalloc(S, d_re, (size_t)nre) && dalloc(S, d_rbeg, cap) && dalloc(S, d_rend, cap) &&
               dalloc(S, d_rel, rel_len + 1) && dalloc(S, d_placed, cap) &&
               dalloc(S, S->tr.depart_actual, cap) && dalloc(S, S->tr.arrive_step, cap) &&
+              dalloc(S, S->tr.fuel_total, cap) && dalloc(S, S->tr.co_total, cap) &&
               dalloc(S, S->pend[0], cap) && dalloc(S, S->pend[1], cap);
     for (int b = 0; b < 2 && ok; ++b) {
         Veh& V = S->buf[b];
         ok = dalloc(S, V.key, cap) && dalloc(S, V.x, cap) && dalloc(S, V.v, cap) && dalloc(S, V.edge, cap) &&
              dalloc(S, V.rcur, cap) && dalloc(S, V.next, cap) && dalloc(S, V.lc, cap) &&
-             dalloc(S, V.kin, cap) && dalloc(S, V.phin, cap) && dalloc(S, V.vid, cap);
+             dalloc(S, V.kin, cap) && dalloc(S, V.phin, cap) && dalloc(S, V.vid, cap) &&
+             dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap);
     }
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
     ok = ok && dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
@@ -587,6 +593,12 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<int> da(cap, init_x ? t0 : -1);
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
     HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
+    HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));
+    HIPCHECK(S, hipMemsetAsync(S->tr.co_total, 0, sizeof(float) * cap, S->stream));
+    for (int b = 0; b < 2; ++b) {
+        HIPCHECK(S, hipMemsetAsync(S->buf[b].fuel, 0, sizeof(float) * cap, S->stream));
+        HIPCHECK(S, hipMemsetAsync(S->buf[b].co, 0, sizeof(float) * cap, S->stream));
+    }
     HIPCHECK(S, hipMemsetAsync(s.stay, 0, cap + 1, S->stream));
     HIPCHECK(S, hipMemsetAsync(s.tile_status, 0, sizeof(unsigned long long) * ntiles, S->stream));
     const int p = (int)(S->host_t & 1);
@@ -687,6 +699,7 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
     HIPCHECK(S, hipGetLastError());
     // the recompute pass must not add to the live statistics
     Scratch rs = S->s;
+    rs.samp_every = 0;  // and it takes no samples
     rs.st_cnt = S->sink;
     rs.st_steps = S->sink + S->ne;
     rs.st_us = S->sink + 2 * (size_t)S->ne;
@@ -757,7 +770,8 @@ int sim_stats(sim_t* S, sim_stats_t* host_out, int64_t* edge_count, int64_t* edg
 }
 
 int sim_read_vehicles(sim_t* S, int32_t cap, int32_t* n_out, int32_t* vid, int32_t* edge, int32_t* lane,
-                      int32_t* cursor, int32_t* lc, int32_t* kin, float* x, float* v, float* phin) {
+                      int32_t* cursor, int32_t* lc, int32_t* kin, float* x, float* v, float* phin, float* fuel,
+                      float* co) {
     if (!S || !n_out || cap < 0) return SIM_EINVAL;
     if (!S->loaded) {
         *n_out = 0;
@@ -781,6 +795,8 @@ int sim_read_vehicles(sim_t* S, int32_t cap, int32_t* n_out, int32_t* vid, int32
         if (x) HIPCHECK(S, hipMemcpyAsync(x, V.x, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         if (v) HIPCHECK(S, hipMemcpyAsync(v, V.v, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         if (phin) HIPCHECK(S, hipMemcpyAsync(phin, V.phin, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
+        if (fuel) HIPCHECK(S, hipMemcpyAsync(fuel, V.fuel, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
+        if (co) HIPCHECK(S, hipMemcpyAsync(co, V.co, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         HIPCHECK(S, hipStreamSynchronize(S->stream));
     }
     for (int i = 0; i < n; ++i) {
@@ -799,6 +815,45 @@ int sim_read_trips(sim_t* S, int32_t* depart_actual, int32_t* arrive_step) {
         HIPCHECK(S, hipMemcpyAsync(depart_actual, S->tr.depart_actual, sizeof(int) * S->ntrips, hipMemcpyDeviceToHost, S->stream));
     if (arrive_step)
         HIPCHECK(S, hipMemcpyAsync(arrive_step, S->tr.arrive_step, sizeof(int) * S->ntrips, hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
+int sim_read_emissions(sim_t* S, float* fuel, float* co) {
+    if (!S) return SIM_EINVAL;
+    if (!S->loaded || S->ntrips == 0) return SIM_OK;
+    if (fuel)
+        HIPCHECK(S, hipMemcpyAsync(fuel, S->tr.fuel_total, sizeof(float) * S->ntrips, hipMemcpyDeviceToHost, S->stream));
+    if (co)
+        HIPCHECK(S, hipMemcpyAsync(co, S->tr.co_total, sizeof(float) * S->ntrips, hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
+int sim_set_sampler(sim_t* S, int32_t every, int32_t group, int32_t max_groups) {
+    if (!S || every <= 0 || group <= 0 || max_groups <= 0) return SIM_EINVAL;
+    const size_t n = (size_t)max_groups * (size_t)S->ne;
+    if (n > ((size_t)1 << 34)) return fail(S, SIM_EINVAL, "sampler too large");
+    unsigned long long *cnt = nullptr, *spd = nullptr;
+    if (!dalloc(S, cnt, n) || !dalloc(S, spd, n)) return fail(S, SIM_ENOMEM, "sampler allocation failed");
+    HIPCHECK(S, hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * n, S->stream));
+    HIPCHECK(S, hipMemsetAsync(spd, 0, sizeof(unsigned long long) * n, S->stream));
+    S->s.samp_cnt = cnt;
+    S->s.samp_spd = spd;
+    S->s.samp_every = every;
+    S->s.samp_group = group;
+    S->s.samp_max = max_groups;
+    drop_graphs(S);
+    return SIM_OK;
+}
+
+int sim_read_samples(sim_t* S, int64_t* count, int64_t* speed_um) {
+    if (!S) return SIM_EINVAL;
+    if (S->s.samp_every <= 0) return fail(S, SIM_ESTATE, "no sampler");
+    const size_t n = (size_t)S->s.samp_max * (size_t)S->ne;
+    if (count) HIPCHECK(S, hipMemcpyAsync(count, S->s.samp_cnt, sizeof(int64_t) * n, hipMemcpyDeviceToHost, S->stream));
+    if (speed_um)
+        HIPCHECK(S, hipMemcpyAsync(speed_um, S->s.samp_spd, sizeof(int64_t) * n, hipMemcpyDeviceToHost, S->stream));
     HIPCHECK(S, hipStreamSynchronize(S->stream));
     return SIM_OK;
 }
@@ -1015,11 +1070,13 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     unsigned long long* st_save = nullptr;
     int* trip_save = nullptr;
     if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.pend, S->cap) || !dalloc(S, save.ctr, 1) ||
-        !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 2 * (size_t)S->cap))
+        !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap))
         return fail(S, SIM_ENOMEM, "autotune allocation failed");
     const size_t tb = sizeof(int) * (size_t)S->cap;
     HIPCHECK(S, hipMemcpyAsync(trip_save, S->tr.depart_actual, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
     int rc = copy_state(S, save.v, save.pend, save.ctr, S->buf[p], S->pend[p], S->ctr);
     if (rc) return rc;
     const size_t eb = sizeof(unsigned long long) * (size_t)S->ne;
@@ -1033,6 +1090,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     hipEvent_t e0, e1;
     HIPCHECK(S, hipEventCreate(&e0));
     HIPCHECK(S, hipEventCreate(&e1));
+    const int samp_every = S->s.samp_every;
+    S->s.samp_every = 0;  // trials take no samples
     float best = 1e30f;
     int bg = S->grid, bs = S->grid_small;
     const Tape off{};
@@ -1065,6 +1124,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    S->s.samp_every = samp_every;
     S->host_t = t_save;
     S->grid = bg;
     S->grid_small = bs;
@@ -1075,6 +1135,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     HIPCHECK(S, hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->tr.depart_actual, trip_save, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->tr.arrive_step, trip_save + S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->tr.fuel_total, trip_save + 2 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->tr.co_total, trip_save + 3 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
     hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
     HIPCHECK(S, hipGetLastError());
     HIPCHECK(S, hipStreamSynchronize(S->stream));

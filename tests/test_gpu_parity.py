@@ -20,7 +20,7 @@ from tiny import tiny_grid
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("vid", "edge", "lane", "cursor", "lc", "kin", "x", "v", "phin")
+KEYS = ("vid", "edge", "lane", "cursor", "lc", "kin", "x", "v", "phin", "fuel", "co")
 
 
 def sim(scen):
@@ -47,6 +47,9 @@ def assert_same_outputs(g, o, tag):
     tg, to = g.trips(), o.trips()
     for k in to:
         assert np.array_equal(tg[k], to[k]), (tag, k)
+    eg, eo = g.emissions(), o.emissions()
+    for k in eo:
+        assert np.array_equal(eg[k], eo[k]), (tag, k)
 
 
 def lockstep(scen, steps, every, tag):
@@ -102,6 +105,23 @@ def test_metro_snapshot_bit_exact():
     net.pop("xy", None)
     scen = S.placed_snapshot(net, 1_000_000, seed=11)
     lockstep(scen, 3, 1, "metro-snapshot")
+
+
+def test_sampler_and_emissions_grid50():
+    """Utilization/speed sampler sums and per-trip fuel/CO on the 50x50 grid
+    (first 3,600 steps): identical to the FP32 oracle."""
+    scen = S.mid_grid(n_trips=40000)
+    g, o = sim(scen), oracle.Oracle(scen, "f32")
+    g.set_sampler(120, 6, 8)
+    o.set_sampler(120, 6, 8)
+    g.step(3600)
+    o.step(3600)
+    assert_same(g, o, "grid50 sampler")
+    assert_same_outputs(g, o, "grid50 sampler")
+    sg, so = g.samples(), o.samples()
+    for k in so:
+        assert np.array_equal(sg[k], so[k]), k
+    assert so["count"].sum() > 0
 
 
 def test_snapshot_vs_fp64_one_step():

@@ -214,7 +214,7 @@ def test_fp32_fp64_link_times_agree():
 # ---------------------------------------------------------------------------
 def same_state(o, b):
     A, B = o.vehicles(), b.vehicles()
-    for k in A:
+    for k in B:  # the brute force models the dynamics, not the emission accumulators
         if A[k].shape != B[k].shape or not np.array_equal(A[k].astype(np.float64), B[k].astype(np.float64)):
             return k
     return None
