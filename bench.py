@@ -78,6 +78,162 @@ def cpu_baseline(seconds_budget=20.0):
                       "snapshot of %d placed vehicles, %d steps, %.1f s" % (scen["demand"]["init_x"].size, steps, el)}
 
 
+def ensemble_scenarios(seed=1811, n=64, steps=3600):
+    """Uneven grid scenarios: side U{20..120}, trips log-uniform in [1e4, 3e5],
+    IDM parameters per scenario (v0 x U(0.8,1.2), T U(1,2), a U(0.7,1.5),
+    b U(1,2.5)), 100 m links, 2 lanes, 15 m/s, departures U(0, 1800 s)."""
+    import numpy as np
+    import scenarios as S
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        side = int(rng.integers(20, 121))
+        ntr = int(np.exp(rng.uniform(np.log(1e4), np.log(3e5))))
+        net = S.grid(side, seed=seed * 1000 + q, link_len=100.0, lanes=2, speed=15.0)
+        p = S.default_params()
+        p["idm"] = S.draw_idm(rng, 1)
+        o, d = S.uniform_od(rng, side * side, ntr)
+        dep = rng.uniform(0.0, 1800.0, ntr)
+        out.append({"name": "ens%d" % q, "net": net, "params": p,
+                    "demand": S.make_demand(net, o, d, dep, p["dt"]), "steps": steps})
+    return out
+
+
+def bench_ensemble(args):
+    """Batched ensemble (one simulation, graph-captured 60-step chunks, tuned
+    launch shape) against the plain loop (each scenario its own simulation,
+    plain launches), same steps; per-scenario results compared bit for bit."""
+    import numpy as np
+    import torch
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd import ensemble as E
+    steps = 3600
+    log("[ensemble] generating %d scenarios" % args.scenarios)
+    t = time.perf_counter()
+    scens = ensemble_scenarios(n=args.scenarios, steps=steps)
+    log("[ensemble] generated in %.1f s, %d trips" % (time.perf_counter() - t,
+                                                      sum(s["demand"]["depart_step"].size for s in scens)))
+    ens = E.Ensemble(scens)
+    E.step_graph(ens, 60, args.chunk)
+    tune = E.autotune(ens, steps_per_trial=60)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step_graph(ens, steps - 60, args.chunk)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    cb = ens.counters()
+    est, etr = ens.edge_stats(), ens.trips()
+    log("[ensemble] batched: %.3f s, %d vehicle-updates" % (t_batch, cb["vehicle_updates"]))
+    t_loop = 0.0
+    upd_loop = 0
+    same = True
+    for q, sc in enumerate(scens):
+        one = P.Sim(sc)
+        one.step(60)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.step(steps - 60)
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t0
+        upd_loop += one.counters()["vehicle_updates"]
+        a, b = ens.scenario_edge_stats(q, est), one.edge_stats()
+        same &= all(np.array_equal(a[k], b[k]) for k in b)
+        vid = E.vehicle_ids(sc["demand"]["depart_step"])
+        ta, tb = ens.scenario_trips(q, etr), one.trips()
+        same &= all(np.array_equal(ta[k], tb[k][vid]) for k in tb)
+        one.close()
+        if q % 8 == 7:
+            log("[ensemble] plain loop: %d / %d scenarios" % (q + 1, len(scens)))
+    out = {"metric": "ensemble speed-up over the plain per-scenario GPU loop", "value": t_loop / t_batch,
+           "unit": "x", "n_gpus": 1, "steps": steps - 60, "warmup": 60, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "%d grid scenarios, side 20-120, 1e4-3e5 trips each, per-scenario IDM, "
+                                  "3,600 steps" % len(scens), "launch": tune},
+           "batched_s": t_batch, "plain_loop_s": t_loop,
+           "batched_vehicle_updates_per_s": (cb["vehicle_updates"]) / t_batch,
+           "plain_loop_vehicle_updates_per_s": upd_loop / t_loop,
+           "bitwise_identical_per_scenario": bool(same)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Gradient of the link travel-time MSE w.r.t. 16 IDM parameters (4 link
+    classes) on the differentiation workload: adjoint (one taped forward + one
+    backward) against central finite differences with 32 plain GPU runs;
+    both compared with the FP64 CPU adjoint linearized at the same trajectory."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1807_01148_amd as P
+    import scenarios as S
+    scen = S.diff_scenario()
+    steps = scen["steps"]
+    log("[adjoint] generated")
+
+    def run(idm, tape=False):
+        sc = dict(scen)
+        sc["params"] = dict(scen["params"])
+        sc["params"]["idm"] = np.asarray(idm, np.float32)
+        sim = P.Sim(sc)
+        if tape:
+            sim.tape_begin(60)
+        sim.step(steps)
+        return sim
+
+    hid = run(scen["hidden_idm"])
+    tgt, cnt_t = hid.mean_travel_times()
+    hid.close()
+    theta = scen["params"]["idm"].astype(np.float64)
+
+    def loss_of(sim):
+        tb, cnt = sim.mean_travel_times()
+        m = cnt > 0
+        return tb, m, float(((tb - tgt)[m] ** 2).mean())
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = run(theta, tape=True)
+    tb, m, L = loss_of(sim)
+    dL = torch.where(m, 2.0 * (tb - tgt) / int(m.sum()), torch.zeros_like(tb))
+    g_adj = sim.grad(dL).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    log("[adjoint] adjoint gradient in %.3f s" % t_adj)
+    h = 1e-3
+    g_fd = np.zeros_like(theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(theta.shape[0]):
+        for j in range(4):
+            a, b = theta.copy(), theta.copy()
+            a[c, j] += h
+            b[c, j] -= h
+            sa, sb = run(a), run(b)
+            g_fd[c, j] = (loss_of(sa)[2] - loss_of(sb)[2]) / (2 * h)
+            sa.close()
+            sb.close()
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    log("[adjoint] finite differences in %.3f s; FP64 CPU reference" % t_fd)
+    o = oracle.Oracle(scen, "f32", tape=True)
+    o.step(steps)
+    es = o.edge_stats()
+    mask = es["count"] > 0
+    tgt_np = tgt.cpu().numpy().astype(np.float64)
+    _, g_ref, _, _, _ = oracle.replay(o.tape(), scen, theta, tgt_np, mask, at_tape_states=True)
+    scale = np.abs(g_ref).max()
+    out = {"metric": "adjoint gradient speed-up over the plain per-scenario GPU loop (central differences)",
+           "value": t_fd / t_adj, "unit": "x", "n_gpus": 1, "steps": steps, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "50x50 grid, 100,000 trips, 1,800 steps, 4 link classes x (v0_scale, T, a, b)",
+                      "fd_step": h, "checkpoint_every": 60},
+           "adjoint_s": t_adj, "fd_32_runs_s": t_fd, "loss": L,
+           "adjoint_rel_err_vs_fp64": float(np.abs(g_adj - g_ref).max() / scale),
+           "fd_rel_err_vs_fp64": float(np.abs(g_fd - g_ref).max() / scale)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +246,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
     ap.add_argument("--tune-at", type=int, default=0,
                     help="simulate to this step, autotune the launch shape there, store it in the cache, exit")
+    ap.add_argument("--mode", default="plain", choices=["plain", "ensemble", "adjoint"],
+                    help="plain: the metric; ensemble / adjoint: speed-up of the batched and adjoint forms "
+                         "over the plain per-scenario GPU loop")
+    ap.add_argument("--scenarios", type=int, default=64)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -100,6 +260,10 @@ def main():
     import torch
     import paper_1807_01148_amd as P
     from paper_1807_01148_amd import ensemble as E
+    if args.mode == "ensemble":
+        return bench_ensemble(args)
+    if args.mode == "adjoint":
+        return bench_adjoint(args)
 
     log("[bench] generating workload", args.workload)
     t = time.perf_counter()

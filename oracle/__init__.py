@@ -72,6 +72,8 @@ def _lib(prec):
         lib.or_num_active.restype = i32
         lib.or_num_pending.argtypes = [P]
         lib.or_num_pending.restype = i32
+        lib.or_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
+        lib.or_set_control.restype = ctypes.c_int
         lib.or_get_emissions.argtypes = [P, P, P]
         lib.or_set_sampler.argtypes = [P, i32, i32, i32]
         lib.or_set_sampler.restype = ctypes.c_int
@@ -163,6 +165,13 @@ class Oracle:
             _p(idm), _p(arr(fparams(p), np.float32)), int(p["lc_cooldown"]), ctypes.byref(err))
         if not self.h:
             raise OracleError("or_create failed: %d" % err.value)
+        if net.get("node_control") is not None:
+            ctrl = arr(net["node_control"], np.int32)
+            if self.lib.or_set_control(self.h, _p(ctrl), int(p.get("signal_green", 20)),
+                                       float(p.get("stop_dist", 3.0)), float(p.get("stop_speed", 0.5))) != 0:
+                self.lib.or_destroy(self.h)
+                self.h = None
+                raise OracleError("or_set_control failed")
         d = scen["demand"]
         self.ntrips = int(d["depart_step"].size)
         ix = d.get("init_x")

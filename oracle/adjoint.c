@@ -12,7 +12,7 @@
  * equation), and so are the crossing-interpolated link travel times
  * (Sec. 6.4 outputs).  The replay re-evaluates the same formulas as the step,
  * in the same order, with each branch forced to the recorded one:
- *   s   = (xL - l) - x            (same link)   or (len - x) + (xL - l)   (next link)
+ *   s   = (xL - l) - x  (same link),  (len - x) + (xL - l)  (next link),  len - x  (stop line)
  *   r   = v / v0,  fr = 1 - r^4
  *   acc = a fr                     (free road)
  *       = a (fr - (ss/max(s, s_eps))^2),  ss = s0 + max(0, vT + v(v - vL)/(2 sqrt(ab)))
@@ -39,7 +39,8 @@
 
 enum {
     TF_HAS_LEAD = 1, TF_LEAD_CROSS = 2, TF_DYN_FLOOR = 4, TF_S_FLOOR = 8, TF_ACC_FLOOR = 16,
-    TF_STOP = 32, TF_DX_FLOOR = 64, TF_CLAMP = 128, TF_CLAMP_ZERO = 256, TF_CLAMP_V = 512, TF_F_ONE = 1024
+    TF_STOP = 32, TF_DX_FLOOR = 64, TF_CLAMP = 128, TF_CLAMP_ZERO = 256, TF_CLAMP_V = 512, TF_F_ONE = 1024,
+    TF_VIRTUAL = 2048 /* the vehicle ahead is the stop line of a held movement: s = len - x, speed 0 */
 };
 enum { TM_STAY = 0, TM_CHANGE = 1, TM_YIELD = 2, TM_ARRIVE = 3, TM_CROSS = 4, TM_APPEAR = 5 };
 
@@ -55,7 +56,8 @@ typedef struct {
 static void motion(const cst_t* K, const par_t* P, int fl, double len, double x, double v, double xL,
                    double vL, double* dxo, double* vno, double* fo) {
     double s = 0.0;
-    if (fl & TF_HAS_LEAD) s = (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
+    if (fl & TF_HAS_LEAD)
+        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
     double r = v * P->iv;
     double r2 = r * r;
     double fr = 1.0 - r2 * r2;
@@ -95,7 +97,8 @@ static void motion_rev(const cst_t* K, const par_t* P, int fl, double len, doubl
                        double* gvL, double* ga, double* gT, double* gkab, double* giv) {
     /* recompute the forward intermediates */
     double s = 0.0;
-    if (fl & TF_HAS_LEAD) s = (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
+    if (fl & TF_HAS_LEAD)
+        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
     double r = v * P->iv;
     double r2 = r * r;
     double fr = 1.0 - r2 * r2;
@@ -237,7 +240,7 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
             /* the state before the step: replayed, or as recorded by the forward */
             rx[k] = at_tape_states ? x0[k] : x[i];
             rv[k] = at_tape_states ? v0[k] : v[i];
-            rlead[k] = (flags[k] & TF_HAS_LEAD) ? where[lead[k]] : -1;
+            rlead[k] = ((flags[k] & TF_HAS_LEAD) && !(flags[k] & TF_VIRTUAL)) ? where[lead[k]] : -1;
             rtrav[k] = -1;
         }
         for (int64_t k = g0; k < g1; ++k) {

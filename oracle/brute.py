@@ -64,6 +64,12 @@ class Brute:
         self.cool = int(p["lc_cooldown"])
         self.dt_us = int(round(self.dt * 1e6))
         self.dt_us_f = self.dt * 1e6
+        ctrl = net.get("node_control")
+        self.ctrl = None if ctrl is None else [int(c) for c in ctrl]
+        self.green = int(p.get("signal_green", 20))
+        self.stop_dist = _f(p.get("stop_dist", 3.0))
+        self.stop_speed = _f(p.get("stop_speed", 0.5))
+        self.holder = {}
         dep = np.asarray(d["depart_step"], np.int64)
         order = np.lexsort((np.arange(dep.size), dep))
         rp = np.asarray(d["route_ptr"], np.int64)
@@ -130,12 +136,28 @@ class Brute:
         on = self._on(e, l)
         return min(on, key=lambda q: (q["x"], q["vid"])) if on else None
 
-    def _ahead(self, e, l, x, nxt):
+    def _held(self, e, nxt, vid):
+        """is the movement e -> nxt held at the end of e (stop sign, red signal)?"""
+        if self.ctrl is None or nxt < 0:
+            return False
+        h = self.head[e]
+        if self.ctrl[h] == 1:
+            return self.holder.get(h, -1) != vid
+        if self.ctrl[h] == 2:
+            inbound = [f for f in range(len(self.head)) if self.head[f] == h]
+            outs = range(self.row_ptr[h], self.row_ptr[h + 1])
+            movements = [(i, o) for i in inbound for o in outs]
+            return movements[(self.t // self.green) % len(movements)] != (e, nxt)
+        return False
+
+    def _ahead(self, e, l, x, nxt, held=False):
         """vehicle ahead at lane l of link e for position x: (kind, xl, vl)"""
         ahead = [q for q in self._on(e, l) if q["x"] > x]
         if ahead:
             q = min(ahead, key=lambda q: (q["x"], q["vid"]))
             return (1, q["x"], q["v"])
+        if held:
+            return (3, self.len[e], 0.0)
         if nxt >= 0:
             q = self._rearmost(nxt, min(l, self.lanes[nxt] - 1))
             if q is not None:
@@ -146,6 +168,8 @@ class Brute:
         if ah is None:
             return None
         kind, xl, vl = ah
+        if kind == 3:
+            return (self.len[e] - x, 0.0)
         s = (xl - self.lveh) - x if kind == 1 else (self.len[e] - x) + (xl - self.lveh)
         return (s, vl)
 
@@ -156,10 +180,13 @@ class Brute:
     def _decide(self, q):
         e, l, x, v = q["edge"], q["lane"], q["x"], q["v"]
         nxt = self._next(q)
+        held = self._held(e, nxt, q["vid"])
         same = [w for w in self._on(e, l) if (w["x"], w["vid"]) > (x, q["vid"])]
         if same:
             w = min(same, key=lambda w: (w["x"], w["vid"]))
             own = (1, w["x"], w["v"])
+        elif held:
+            own = (3, self.len[e], 0.0)
         elif nxt >= 0:
             w = self._rearmost(nxt, min(l, self.lanes[nxt] - 1))
             own = None if w is None else (2, w["x"], w["v"])
@@ -205,7 +232,7 @@ class Brute:
         F = max(behind, key=lambda w: (w["x"], w["vid"])) if behind else None
         best = None
         for lt in cands:
-            ah = self._ahead(e, lt, x, nxt)
+            ah = self._ahead(e, lt, x, nxt, held)
             Lt = self._gap(e, ah, x)
             lag = [w for w in self._on(e, lt) if w["x"] <= x]
             Ft = max(lag, key=lambda w: (w["x"], w["vid"])) if lag else None
@@ -261,6 +288,16 @@ class Brute:
 
     def _step(self):
         t = self.t
+        if self.ctrl is not None:
+            # a free stop node admits the lowest id waiting at its line
+            waiting = {}
+            for q in self.active:
+                h = self.head[q["edge"]]
+                if self.ctrl[h] != 1 or self._next(q) < 0 or self.holder.get(h, -1) >= 0:
+                    continue
+                if self.len[q["edge"]] - q["x"] <= self.stop_dist and q["v"] <= self.stop_speed:
+                    waiting[h] = min(waiting.get(h, q["vid"]), q["vid"])
+            self.holder.update(waiting)
         dec = [self._decide(q) for q in self.active]
         cands = list(self.pending) + [v for v, tr in enumerate(self.trips)
                                       if tr["dep"] == t and self.depart_actual[v] < 0]
@@ -294,6 +331,8 @@ class Brute:
                 self.arrive_step[q["vid"]] = t + 1
                 continue
             if d["kind"] == "cross" and ("veh", i) in won:
+                if self.holder.get(self.head[q["edge"]], -1) == q["vid"]:
+                    self.holder[self.head[q["edge"]]] = -1
                 self._exit(q, d["f"])
                 q.update(cur=q["cur"] + 1, edge=d["tedge"], lane=d["tlane"], x=d["X"], v=d["vc"],
                          kin=t + 1, phin=d["f"])

@@ -63,6 +63,10 @@ typedef struct {
 typedef struct {
     /* network */
     int32_t nn, ne, nlanes;
+    /* intersection control per node: 0 none, 1 stop, 2 signal (Sec. 6.3.2) */
+    int32_t *ctrl, *holder, *in_rank, *in_deg;
+    int32_t green;
+    real stop_dist, stop_speed;
     int32_t *row_ptr, *col_idx, *lanes, *cls, *lane_base, *ncell;
     real *len, *inv_v0;
     /* parameters */
@@ -183,8 +187,33 @@ bad:
     return NULL;
 }
 
+/* Intersection control (Sec. 6.3.2): ctrl[node] = 0 none, 1 stop, 2 signal;
+ * a signal cycles through its n_in * m_out movements, `green` steps each; a
+ * stop admits one vehicle at a time, chosen among vehicles stopped (speed <=
+ * stop_speed) within stop_dist of the line. */
+int or_set_control(osim* S, const int32_t* ctrl, int32_t green, float stop_dist, float stop_speed) {
+    if (green <= 0 || !(stop_dist > 0) || !(stop_speed >= 0)) return OR_EINVAL;
+    if (!S->ctrl) {
+        S->ctrl = (int32_t*)calloc(S->nn + 1, sizeof(int32_t));
+        S->holder = (int32_t*)malloc(sizeof(int32_t) * (S->nn + 1));
+        S->in_rank = (int32_t*)malloc(sizeof(int32_t) * (S->ne + 1));
+        S->in_deg = (int32_t*)calloc(S->nn + 1, sizeof(int32_t));
+        for (int32_t e = 0; e < S->ne; ++e) S->in_rank[e] = S->in_deg[S->col_idx[e]]++;
+    }
+    for (int32_t u = 0; u < S->nn; ++u) {
+        if (ctrl[u] < 0 || ctrl[u] > 2) return OR_EINVAL;
+        S->ctrl[u] = ctrl[u];
+        S->holder[u] = -1;
+    }
+    S->green = green;
+    S->stop_dist = (real)stop_dist;
+    S->stop_speed = (real)stop_speed;
+    return OR_OK;
+}
+
 void or_destroy(osim* S) {
     if (!S) return;
+    free(S->ctrl); free(S->holder); free(S->in_rank); free(S->in_deg);
     free(S->row_ptr); free(S->col_idx); free(S->lanes); free(S->cls); free(S->lane_base);
     free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab);
     free(S->dep); free(S->rbeg); free(S->rend); free(S->route_edges);
@@ -331,7 +360,7 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
 /* ------------------------------------------------------------------------ */
 /* the car-following law and the kinematic update                             */
 typedef struct {
-    int kind;   /* 0 free road, 1 same link, 2 first vehicle of the next link */
+    int kind;   /* 0 free road, 1 same link, 2 first vehicle of the next link, 3 stop line */
     real s;     /* bumper-to-bumper gap (m) */
     real vl;    /* speed of the vehicle ahead */
     real xl;    /* its front position on its own link */
@@ -341,9 +370,13 @@ typedef struct {
 /* branch flags of one applied motion (recorded in the event tape) */
 enum {
     TF_HAS_LEAD = 1, TF_LEAD_CROSS = 2, TF_DYN_FLOOR = 4, TF_S_FLOOR = 8, TF_ACC_FLOOR = 16,
-    TF_STOP = 32, TF_DX_FLOOR = 64, TF_CLAMP = 128, TF_CLAMP_ZERO = 256, TF_CLAMP_V = 512, TF_F_ONE = 1024
+    TF_STOP = 32, TF_DX_FLOOR = 64, TF_CLAMP = 128, TF_CLAMP_ZERO = 256, TF_CLAMP_V = 512, TF_F_ONE = 1024,
+    TF_VIRTUAL = 2048
 };
-static int lead_flags(lead_t L) { return L.kind == 0 ? 0 : (TF_HAS_LEAD | (L.kind == 2 ? TF_LEAD_CROSS : 0)); }
+static int lead_flags(lead_t L) {
+    if (L.kind == 0) return 0;
+    return TF_HAS_LEAD | (L.kind == 2 ? TF_LEAD_CROSS : 0) | (L.kind == 3 ? TF_VIRTUAL : 0);
+}
 
 /* IDM acceleration (Sec. 6.3.2, car-following equation), with the dynamic
  * part of the desired gap floored at 0, the gap floored at s_eps and the
@@ -453,9 +486,29 @@ typedef struct {
 
 static const veh_t* at(const view_t* W, int32_t o) { return &W->act[W->ord[o]]; }
 
+/* Is the movement e -> next held at the end of e this step? */
+static int blocked(const osim* S, int32_t e, int32_t next, int32_t vid) {
+    if (!S->ctrl || next < 0) return 0;
+    int32_t h = S->col_idx[e];
+    if (S->ctrl[h] == 1) return S->holder[h] != vid;
+    if (S->ctrl[h] == 2) {
+        int32_t m = S->row_ptr[h + 1] - S->row_ptr[h];
+        int32_t phase = (S->t / S->green) % (S->in_deg[h] * m);
+        return phase != S->in_rank[e] * m + (next - S->row_ptr[h]);
+    }
+    return 0;
+}
+
+/* a stopped virtual vehicle whose rear is at the link end */
+static lead_t stop_line(const osim* S, int32_t e, real x) {
+    lead_t L = {3, S->len[e] - x, (real)0, S->len[e], -1};
+    return L;
+}
+
 /* vehicle ahead on lane key k of link e for a vehicle at x (strictly ahead),
- * else the rearmost vehicle of lane min(l, lanes-1) of the next link. */
-static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_t next, int32_t l) {
+ * else the stop line if the vehicle's movement is held, else the rearmost
+ * vehicle of lane min(l, lanes-1) of the next link. */
+static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_t next, int32_t l, int held) {
     const osim* S = W->S;
     lead_t L = {0, 0, 0, 0, -1};
     int32_t f = W->first[k], n = W->cnt[k];
@@ -466,6 +519,7 @@ static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_
             return L;
         }
     }
+    if (held) return stop_line(S, e, x);
     if (next >= 0) {
         int32_t l2 = l < S->lanes[next] - 1 ? l : S->lanes[next] - 1;
         int32_t k2 = lane_key(S, next, l2);
@@ -482,6 +536,7 @@ static lead_t relead(const osim* S, int32_t e, lead_t L, real xf) {
     lead_t R = L;
     if (L.kind == 1) R.s = (L.xl - S->lveh) - xf;
     else if (L.kind == 2) R.s = (S->len[e] - xf) + (L.xl - S->lveh);
+    else if (L.kind == 3) R.s = S->len[e] - xf;
     return R;
 }
 
@@ -494,10 +549,13 @@ static dec_t decide(const view_t* W, int32_t o) {
     memset(&D, 0, sizeof(D));
 
     /* own leader: the next vehicle of this lane, else look ahead one link */
+    const int held = blocked(S, e, me->next, me->vid);
     lead_t L = {0, 0, 0, 0, -1};
     if (o + 1 < S->nact && lane_key(S, at(W, o + 1)->edge, at(W, o + 1)->lane) == k) {
         const veh_t* q = at(W, o + 1);
         L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x; L.vid = q->vid;
+    } else if (held) {
+        L = stop_line(S, e, x);
     } else if (me->next >= 0) {
         int32_t n2 = me->next;
         int32_t l2 = l < S->lanes[n2] - 1 ? l : S->lanes[n2] - 1;
@@ -575,7 +633,7 @@ static dec_t decide(const view_t* W, int32_t o) {
     real best_inc = 0, best_X = 0, best_v = 0;
     for (int ci = 0; ci < nc; ++ci) {
         int32_t lt = cand[ci], kt = lane_key(S, e, lt);
-        lead_t Lt = lead_in_lane(W, e, kt, x, me->next, lt);
+        lead_t Lt = lead_in_lane(W, e, kt, x, me->next, lt, held);
         /* lag: last vehicle of the target lane with position <= x */
         const veh_t* Ft = NULL;
         for (int32_t j = 0; j < W->cnt[kt]; ++j) {
@@ -681,6 +739,22 @@ static int step_once(osim* S) {
     }
     view_t W = {S, S->act, ord, first, cnt};
 
+    /* stop control: a free stop node admits the lowest-id vehicle waiting at
+     * its line (front within stop_dist of the link end, speed <= stop_speed,
+     * going on to another link) */
+    if (S->ctrl) {
+        /* a pending choice is kept as -2 - vid until every vehicle is seen */
+        for (int32_t o = 0; o < N; ++o) {
+            const veh_t* q = at(&W, o);
+            int32_t h = S->col_idx[q->edge];
+            if (S->ctrl[h] != 1 || q->next < 0 || S->holder[h] >= 0) continue;
+            if (!((S->len[q->edge] - q->x) <= S->stop_dist) || !(q->v <= S->stop_speed)) continue;
+            if (S->holder[h] == -1 || q->vid < -2 - S->holder[h]) S->holder[h] = -2 - q->vid;
+        }
+        for (int32_t u = 0; u < S->nn; ++u)
+            if (S->holder[u] <= -2) S->holder[u] = -2 - S->holder[u];
+    }
+
     /* utilization / speed sample of the state at t (Sec. 6.4) */
     if (S->samp_every > 0 && t % S->samp_every == 0) {
         int32_t g = (t / S->samp_every) / S->samp_group;
@@ -785,6 +859,7 @@ static int step_once(osim* S) {
             emissions(S, &q, v1);
         }
         if (d->kind == K_CROSS && cwin_veh[o]) {
+            if (S->ctrl && S->holder[S->col_idx[q.edge]] == q.vid) S->holder[S->col_idx[q.edge]] = -1;
             record_exit(S, &q, d->f, t);
             q.rcur += 1;
             q.edge = d->tedge;

@@ -95,6 +95,11 @@ def default_params(num_classes: int = 1, *, v0_scale=1.0, T=1.5, a=1.0, b=1.5,
         # mandatory-change distance D*sqrt(ln(1/theta)), D = 100 m, theta = 0.5
         "mand_dist": float(100.0 * math.sqrt(math.log(2.0))),
         "lc_cooldown": 4,
+        # intersection control (used where the network has "node_control"):
+        # green time of each signal movement, and the stop-sign waiting zone
+        "signal_green": 20,
+        "stop_dist": 3.0,
+        "stop_speed": 0.5,
     }
 
 
@@ -211,6 +216,14 @@ def metro(n_nodes: int = 1_000_000, n_edges: int = 2_500_000, *, seed: int = 181
     net = _undirected_to_net(n_nodes, u, v, lanes, length, speed, np.zeros(m, np.int64))
     net["xy"] = pts
     return net
+
+
+def random_control(net, seed, p_stop=0.3, p_signal=0.3):
+    """Node control drawn per node: 0 none, 1 stop sign, 2 traffic signal."""
+    rng = np.random.default_rng(seed)
+    n = net["row_ptr"].size - 1
+    u = rng.uniform(0.0, 1.0, n)
+    return np.where(u < p_stop, 1, np.where(u < p_stop + p_signal, 2, 0)).astype(np.int32)
 
 
 def tails_of(net) -> np.ndarray:
