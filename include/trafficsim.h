@@ -167,6 +167,27 @@ int sim_read_samples(sim_t* sim, int64_t* count, int64_t* speed_um);
  * constants are recomputed as in sim_create.  Errors: SIM_EINVAL. */
 int sim_set_idm(sim_t* sim, const float* idm);
 
+/* Intersection control (Sec. 6.3.2, stop signs and traffic signals).
+ * node_control: HOST int32[num_nodes] (copied), 0 = uncontrolled, 1 = stop
+ * sign, 2 = signal.  A vehicle whose next movement (link e -> link e') is held
+ * sees a stopped vehicle with its rear at the end of e (the stop line).
+ *   signal: the node's n inbound x m outbound movements get the green in
+ *     turn, signal_green_steps steps each; movement (i, j) is green in phase
+ *     i*m + j, where i ranks e among the node's inbound links by link id and
+ *     j ranks e' among its outbound links (CSR order);
+ *   stop sign: every movement is held except for one admitted vehicle.  A
+ *     free node admits, at the start of a step, the lowest-id vehicle whose
+ *     front is within stop_dist of its line at speed <= stop_speed and which
+ *     goes on to another link; the node is free again once that vehicle has
+ *     entered its next link.
+ * May be called before or after sim_load_demand, outside a differentiation
+ * window; every stop node starts free.  Ensemble handles take the
+ * concatenation of the member networks' node arrays.
+ * Errors: SIM_EINVAL (null, value not in 0..2, signal_green_steps <= 0,
+ * stop_dist <= 0, stop_speed < 0), SIM_ESTATE (inside a window), SIM_ENOMEM. */
+int sim_set_control(sim_t* sim, const int32_t* node_control, int32_t signal_green_steps, float stop_dist,
+                    float stop_speed);
+
 /* Per-kernel timing with HIP events on the handle's stream: when every > 0,
  * every `every`-th subsequent step records an event before and after each of
  * its SIM_NUM_KERNELS kernel launches (decide, resolve, scan, scatter, place, lanes);

@@ -224,6 +224,13 @@ class Oracle:
         dt = np.float32 if self.precision == "f32" else np.float64
         return {"fuel": f.astype(dt), "co": c.astype(dt)}
 
+    def set_control(self, node_control, signal_green: int = 20, stop_dist: float = 3.0, stop_speed: float = 0.5):
+        """Change intersection control between steps; every stop node starts free."""
+        ctrl = np.ascontiguousarray(node_control, np.int32)
+        self._keep.append(ctrl)
+        if self.lib.or_set_control(self.h, _p(ctrl), int(signal_green), float(stop_dist), float(stop_speed)) != 0:
+            raise OracleError("or_set_control failed")
+
     def set_sampler(self, every: int = 120, group: int = 6, max_groups: int = 32):
         if self.lib.or_set_sampler(self.h, int(every), int(group), int(max_groups)) != 0:
             raise OracleError("or_set_sampler failed")

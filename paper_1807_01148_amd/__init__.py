@@ -23,7 +23,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
-            "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -97,6 +97,8 @@ def library(path: str = LIB_PATH):
         lib.sim_tape_begin.restype = ctypes.c_int
         lib.sim_grad.argtypes = [P, P, P]
         lib.sim_grad.restype = ctypes.c_int
+        lib.sim_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
+        lib.sim_set_control.restype = ctypes.c_int
         lib.sim_set_stream.argtypes = [P, P]
         lib.sim_set_stream.restype = ctypes.c_int
         lib.sim_destroy.argtypes = [P]
@@ -178,6 +180,9 @@ class Sim:
         if rc != SIM_OK:
             raise SimError(rc, self.lib.sim_strerror(rc).decode())
         self.h = h
+        if net.get("node_control") is not None:
+            self.set_control(net["node_control"], p.get("signal_green", 20), p.get("stop_dist", 3.0),
+                             p.get("stop_speed", 0.5))
         d = scen["demand"]
         self.num_trips = int(d["depart_step"].size)
         ix = d.get("init_x")
@@ -189,6 +194,14 @@ class Sim:
                 None if d.get("init_v") is None else arr(d["init_v"], np.float32),
                 None if d.get("init_lane") is None else arr(d["init_lane"], np.int32))
         self._check(rc)
+
+    def set_control(self, node_control, signal_green=20, stop_dist=3.0, stop_speed=0.5):
+        """Stop signs (1) and signals (2) per node, 0 = uncontrolled."""
+        import torch
+        ctrl = np.ascontiguousarray(node_control, np.int32)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.sim_set_control(self.h, _p(ctrl), int(signal_green), float(stop_dist),
+                                                 float(stop_speed)))
 
     def _check(self, rc):
         if rc != SIM_OK:

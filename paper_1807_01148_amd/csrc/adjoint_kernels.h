@@ -40,7 +40,7 @@ __device__ void motion_rev(const Params& P, float A, float T, float kab, float i
                            float& gxL, float& gvL, float& ga, float& gT, float& gkab, float& giv) {
     const bool lead = fl & kFHasLead;
     float s = 0.0f;
-    if (lead) s = (fl & kFLeadCross) ? (len - x) + (xL - P.lveh) : (xL - P.lveh) - x;
+    if (lead) s = (fl & kFVirtual) ? len - x : (fl & kFLeadCross) ? (len - x) + (xL - P.lveh) : (xL - P.lveh) - x;
     float r = v * iv;
     float r2 = r * r;
     float fr = 1.0f - r2 * r2;

@@ -37,6 +37,8 @@ struct Counters {
 struct Params {
     float dt, h, lveh, s0, claim_len, s_eps, b_max, pol, athr, bsafe, dmand, dt_us_f;
     float mph;  // miles per hour per m/s
+    int green;  // steps of green per signal movement
+    float stop_dist, stop_speed;  // a vehicle within stop_dist of a stop line at <= stop_speed is waiting
     long long dt_us;
     int lc_cool;
 };
@@ -52,6 +54,9 @@ struct Net {
     const long long* cbase;  // first claim cell of lane 0 of the edge
     const int* ncell;        // cells per lane = floor(len) + 1
     int ne;                  // number of edges
+    const int* ctrl;         // per node: 0 none, 1 stop, 2 signal; NULL = no control anywhere
+    const int* in_rank;      // per edge: rank among the inbound links of its head node
+    const int* in_deg;       // per node: number of inbound links
     const float* cT;
     const float* cA;
     const float* cKab;
@@ -135,6 +140,8 @@ struct Scratch {
     int samp_every, samp_group, samp_max;
     unsigned long long* samp_cnt;
     unsigned long long* samp_spd;
+    int* holder;                    // per stop node: vehicle admitted into the intersection, or -1
+    unsigned long long* stop_req;   // per stop node: lowest (epoch, id) waiting at the line
     unsigned* epoch;  // executed-step counter (claims, scan statuses, lane index are tagged with it)
     LaneIx* lanes;  // per global lane: first and last entry in the sorted arrays
 };
@@ -144,7 +151,8 @@ struct Scratch {
 enum : int { kModeStay = 0, kModeChange = 1, kModeYield = 2, kModeArrive = 3, kModeCross = 4 };
 enum : int {
     kFHasLead = 1, kFLeadCross = 2, kFDynFloor = 4, kFSFloor = 8, kFAccFloor = 16, kFStop = 32,
-    kFDxFloor = 64, kFClamp = 128, kFClampZero = 256, kFClampV = 512, kFFOne = 1024
+    kFDxFloor = 64, kFClamp = 128, kFClampZero = 256, kFClampV = 512, kFFOne = 1024,
+    kFVirtual = 2048  // the vehicle ahead is the stop line of a held movement
 };
 
 struct Tape {
@@ -163,7 +171,7 @@ struct Tape {
 };
 
 struct Lead {
-    int kind;  // 0 free road, 1 same link, 2 rearmost vehicle of the next link
+    int kind;  // 0 free road, 1 same link, 2 rearmost vehicle of the next link, 3 stop line
     float s;   // bumper-to-bumper gap
     float vl;  // speed of the vehicle ahead
     float xl;  // its position on its own link
@@ -171,7 +179,8 @@ struct Lead {
 };
 
 __device__ __forceinline__ int lead_flags(const Lead& L) {
-    return L.kind == 0 ? 0 : (kFHasLead | (L.kind == 2 ? kFLeadCross : 0));
+    if (L.kind == 0) return 0;
+    return kFHasLead | (L.kind == 2 ? kFLeadCross : 0) | (L.kind == 3 ? kFVirtual : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +261,7 @@ __device__ __forceinline__ Lead relead(const Params& P, float len, const Lead& L
     Lead R = L;
     if (L.kind == 1) R.s = (L.xl - P.lveh) - xf;
     else if (L.kind == 2) R.s = (len - xf) + (L.xl - P.lveh);
+    else if (L.kind == 3) R.s = len - xf;
     return R;
 }
 
@@ -303,6 +313,39 @@ __device__ __forceinline__ void emissions(const Params& P, float v, float v1, fl
     const float f = 0.666f + 0.072f * br;
     fuel = fuel + f * P.dt;
     co = co + c * P.dt;
+}
+
+// Intersection control (Sec. 6.3.2): is the movement e -> nx held at the end of
+// e this step?  A stop node holds everyone but the vehicle it admitted (the
+// lowest id waiting at its line when it was free, requested at the end of the
+// previous step); a signal gives movement (inbound rank i, outbound rank j) the
+// green in phase i*m + j of its n*m phases, `green` steps each.
+__device__ __forceinline__ bool movement_held(const Params& P, const Net& net, const Scratch& s, int e, int nx,
+                                             int vid, int t, unsigned long long tag) {
+    if (!net.ctrl || nx < 0) return false;
+    const int h = net.head[e];
+    const int c = net.ctrl[h];
+    if (c == 1) {
+        const int hd = s.holder[h];
+        if (hd == vid) return false;
+        if (hd == -1 && s.stop_req[h] == (tag | (unsigned)vid)) {
+            s.holder[h] = vid;  // admitted now
+            return false;
+        }
+        return true;
+    }
+    if (c == 2) {
+        const int r0 = net.row_ptr[h];
+        const int m = net.row_ptr[h + 1] - r0;
+        const int phase = (t / P.green) % (net.in_deg[h] * m);
+        return phase != net.in_rank[e] * m + (nx - r0);
+    }
+    return false;
+}
+
+__device__ __forceinline__ Lead stop_line_lead(float len, float x) {
+    Lead L = {3, len - x, 0.0f, len, -1};
+    return L;
 }
 
 // claims of a later executed step always beat those of an earlier one

@@ -45,10 +45,14 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 
     // own leader: next element of the lane, else the rearmost vehicle of the
     // mapped lane of the next link of the route
+    const int vid = in.vid[i];
+    const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
     Lead L = {0, 0.0f, 0.0f, 0.0f, -1};
     if (i + 1 < N && in.key[i + 1] == k) {
         float xl = in.x[i + 1];
         L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.s = (xl - P.lveh) - x; L.idx = i + 1;
+    } else if (held) {
+        L = stop_line_lead(len, x);
     } else if (nx >= 0) {
         int nl2 = net.lanes[nx];
         int k2 = net.lane_base[nx] + (l < nl2 - 1 ? l : nl2 - 1);
@@ -64,7 +68,6 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     kin_move_fl(P, v, ac, dx, vn, own_fl);
     clamps += clamp_to_leader_fl(L, dx, vn, own_fl);
     const float xs = x + dx;
-    const int vid = in.vid[i];
     // utilization / speed sample of the state at t (Sec. 6.4)
     if (s.samp_every > 0 && t % s.samp_every == 0) {
         const int g = (t / s.samp_every) / s.samp_group;
@@ -166,6 +169,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         if (occ && j <= thi) {
             float xl = in.x[j];
             Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.s = (xl - P.lveh) - x; Lt.idx = j;
+        } else if (held) {
+            Lt = stop_line_lead(len, x);
         } else if (nx >= 0) {
             int nl2 = net.lanes[nx];
             int k2 = net.lane_base[nx] + (lt < nl2 - 1 ? lt : nl2 - 1);
@@ -333,7 +338,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
                                                          : lb_key(in.key, 0, N, key);
             s.mv_p[m] = p;
             s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
-            if (kind == kCross) record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
+            if (kind == kCross) {
+                record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
+                if (net.ctrl) {  // reaching the next link frees a stop node
+                    const int h = net.head[in.edge[src]];
+                    if (s.holder[h] == vid) s.holder[h] = -1;
+                }
+            }
             if (kind == kInsert) {
                 tr.depart_actual[vid] = t + 1;
                 departed += 1;
@@ -568,11 +579,19 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
 // the step: the kernels of the step are the only readers of the counters it
 // advances, and they have all completed.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_lanes(Veh buf, Scratch s, Counters* ctr, int finalize) {
+__global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Scratch s, Counters* ctr, int finalize) {
     const int N = finalize ? ctr->n_next : ctr->n;
     const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
+    const unsigned long long tag = epoch_tag(ep);
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
         const int k = buf.key[j];
+        if (net.ctrl) {  // waiting at the line of a free stop node: ask to be admitted next step
+            const int e = buf.edge[j];
+            const int h = net.head[e];
+            if (net.ctrl[h] == 1 && buf.next[j] >= 0 && s.holder[h] == -1 && (net.len[e] - buf.x[j]) <= P.stop_dist &&
+                buf.v[j] <= P.stop_speed)
+                atomicMin(s.stop_req + h, tag | (unsigned)buf.vid[j]);
+        }
         if (j == 0 || buf.key[j - 1] != k) {
             s.lanes[k].lo = j;
             s.lanes[k].ep = ep;
@@ -590,6 +609,12 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Veh buf, Scratch s, Counters* 
         ctr->t = ctr->t + 1;
         *s.epoch = ep;
     }
+}
+
+// a restored or replaced state is indexed under a fresh epoch, so that no entry
+// left by the state before it (tagged with the old epoch) reads as current
+__global__ void k_next_epoch(unsigned* epoch) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *epoch += 1u;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {

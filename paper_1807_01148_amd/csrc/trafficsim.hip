@@ -77,6 +77,11 @@ struct sim_t {
     float* d_cVs = nullptr;
     float* d_cB = nullptr;
     unsigned* d_epoch = nullptr;
+    // intersection control: per node kind, per edge inbound rank, per node inbound degree
+    int* d_ctrl = nullptr;
+    int* d_in_rank = nullptr;
+    int* d_in_deg = nullptr;
+    int* d_rholder = nullptr;  // stop-node holders of the recompute pass
 
     bool loaded = false;
     int cap = 0;
@@ -95,6 +100,7 @@ struct sim_t {
         Veh v{};
         int* pend = nullptr;
         Counters* ctr = nullptr;
+        int* holder = nullptr;
     };
     bool tape_on = false;
     long long tape_t0 = 0;
@@ -121,6 +127,11 @@ struct sim_t {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<GraphEntry> graphs;
+    // graphs are captured and replayed on a stream of the library's own (the
+    // caller's stream may be the legacy default stream, which cannot be
+    // captured), ordered after and before the caller's work by two events
+    hipStream_t gstream = nullptr;
+    hipEvent_t gjoin[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -130,11 +141,15 @@ int fail(sim_t* S, int code, const std::string& msg) {
     return code;
 }
 
+// a failed call also clears the thread's last-error state, so that it is not
+// reported again by the caller's next, unrelated HIP call
 #define HIPCHECK(S, call)                                                                        \
     do {                                                                                         \
         hipError_t e_ = (call);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
+        if (e_ != hipSuccess) {                                                                  \
+            (void)hipGetLastError();                                                             \
             return fail((S), SIM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+        }                                                                                        \
     } while (0)
 
 void* raw_alloc(sim_t* S, size_t bytes) {
@@ -218,8 +233,16 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, co
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
     hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->P, S->tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, out, sc, ctr, 1);
+    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
     if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
+    HIPCHECK(S, hipGetLastError());
+    return SIM_OK;
+}
+
+// index the lanes of a state that did not come from the previous step
+int reindex(sim_t* S, const Veh& buf, const Scratch& sc, Counters* ctr) {
+    hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(64), 0, S->stream, S->d_epoch);
+    hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->P, S->net, buf, sc, ctr, 0);
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
@@ -230,8 +253,8 @@ bool alloc_veh(sim_t* S, Veh& V, size_t n) {
            dalloc(S, V.phin, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) && dalloc(S, V.co, n);
 }
 
-int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, const Veh& sv, const int* spend,
-               const Counters* sctr) {
+int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, const Veh& sv, const int* spend,
+               const Counters* sctr, const int* shold) {
     const size_t n = (size_t)S->cap;
     const hipMemcpyKind k = hipMemcpyDeviceToDevice;
     HIPCHECK(S, hipMemcpyAsync(dv.key, sv.key, sizeof(int) * n, k, S->stream));
@@ -248,19 +271,21 @@ int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, const Veh& s
     HIPCHECK(S, hipMemcpyAsync(dv.co, sv.co, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dpend, spend, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dctr, sctr, sizeof(Counters), k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dhold, shold, sizeof(int) * (size_t)S->nn, k, S->stream));
     return SIM_OK;
 }
 
 int take_checkpoint(sim_t* S, int p) {
     if (S->nckpt == S->ckpt_pool.size()) {
         sim_t::Ckpt ck;
-        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.pend, S->cap) || !dalloc(S, ck.ctr, 1))
+        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.pend, S->cap) || !dalloc(S, ck.ctr, 1) ||
+            !dalloc(S, ck.holder, S->nn))
             return fail(S, SIM_ENOMEM, "checkpoint allocation failed");
         S->ckpt_pool.push_back(ck);
     }
     sim_t::Ckpt& ck = S->ckpt_pool[S->nckpt++];
     ck.t = S->host_t;
-    return copy_state(S, ck.v, ck.pend, ck.ctr, S->buf[p], S->pend[p], S->ctr);
+    return copy_state(S, ck.v, ck.pend, ck.ctr, ck.holder, S->buf[p], S->pend[p], S->ctr, S->s.holder);
 }
 
 Tape slice(sim_t* S, int k) {
@@ -278,6 +303,14 @@ void drop_graphs(sim_t* S) {
     S->graphs.clear();
 }
 
+int graph_stream(sim_t* S) {
+    if (S->gstream) return SIM_OK;
+    HIPCHECK(S, hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
+    HIPCHECK(S, hipEventCreateWithFlags(&S->gjoin[0], hipEventDisableTiming));
+    HIPCHECK(S, hipEventCreateWithFlags(&S->gjoin[1], hipEventDisableTiming));
+    return SIM_OK;
+}
+
 int alloc_adjoint(sim_t* S) {
     if (S->adj_ready) return SIM_OK;
     const size_t cap = (size_t)S->cap, K = (size_t)S->tape_every, n = cap * K;
@@ -293,7 +326,7 @@ int alloc_adjoint(sim_t* S) {
               dalloc(S, S->L1v, cap) && dalloc(S, a.cgx, cap) && dalloc(S, a.cgv, cap) && dalloc(S, a.cl, cap) &&
               dalloc(S, a.accx, cap) && dalloc(S, a.accv, cap) && dalloc(S, a.maxbits, 1) &&
               dalloc(S, a.scale, 1) && dalloc(S, a.lp, cap) && dalloc(S, a.gpart, nthreads * S->ncls * 4) &&
-              dalloc(S, S->sink, 3 * (size_t)S->ne);
+              dalloc(S, S->sink, 3 * (size_t)S->ne) && dalloc(S, S->d_rholder, S->nn);
     if (!ok) return fail(S, SIM_ENOMEM, "adjoint allocation failed");
     a.ncls = S->ncls;
     S->adj_k = S->tape_every;
@@ -400,7 +433,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
               dalloc(S, S->s.lanes, (size_t)S->nlanes) &&
               dalloc(S, S->s.cells, (size_t)cells) && dalloc(S, S->s.st_cnt, ne) &&
               dalloc(S, S->s.st_steps, ne) && dalloc(S, S->s.st_us, ne) && dalloc(S, S->ctr, 1) &&
-              dalloc(S, dummy, 1);
+              dalloc(S, S->s.holder, nn) && dalloc(S, S->s.stop_req, nn) && dalloc(S, dummy, 1);
     if (!ok) {
         release_all(S);
         delete S;
@@ -432,7 +465,13 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     if (he == hipSuccess) {
         int g = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, (cells + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kBlock), 0, S->stream, S->s.cells, cells, ~0ull);
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(kBlock), 0, S->stream, S->s.stop_req, (long long)nn, ~0ull);
         he = hipGetLastError();
+    }
+    if (he == hipSuccess) {
+        const std::vector<int> none(nn, -1);
+        he = hipMemcpyAsync(S->s.holder, none.data(), sizeof(int) * nn, hipMemcpyHostToDevice, S->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(S->stream);
     }
     if (he == hipSuccess) he = hipStreamSynchronize(S->stream);
     if (he != hipSuccess) {
@@ -627,8 +666,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     S->h_rbeg = rbeg;
     S->grid = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)cap + kBlock - 1) / kBlock));
     S->grid_small = std::max(1, S->grid / 4);
-    hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
-    HIPCHECK(S, hipGetLastError());
+    if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
     HIPCHECK(S, hipStreamSynchronize(S->stream));
     S->loaded = true;
     return SIM_OK;
@@ -703,6 +741,7 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
     rs.st_cnt = S->sink;
     rs.st_steps = S->sink + S->ne;
     rs.st_us = S->sink + 2 * (size_t)S->ne;
+    rs.holder = S->d_rholder;  // stop-node admissions replay on their own copy
     AdjState a = S->adj;
     a.dLdT = dL_dmeanTT;
     a.cnt = S->s.st_cnt;
@@ -711,8 +750,9 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
         const sim_t::Ckpt& ck = S->ckpt_pool[c];
         const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
         const int K = (int)(t_end - ck.t);
-        if ((rc = copy_state(S, S->rbuf[0], S->rpend[0], S->rctr, ck.v, ck.pend, ck.ctr))) return rc;
-        hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->rbuf[0], rs, S->rctr, 0);
+        if ((rc = copy_state(S, S->rbuf[0], S->rpend[0], S->rctr, S->d_rholder, ck.v, ck.pend, ck.ctr, ck.holder)))
+            return rc;
+        if ((rc = reindex(S, S->rbuf[0], rs, S->rctr))) return rc;
         for (int k = 0; k < K; ++k) {
             if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], S->rpend[k & 1], S->rpend[(k + 1) & 1],
                                   rs, slice(S, k), S->rctr, nullptr)))
@@ -733,7 +773,7 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
         }
     }
     // the recompute pass re-indexed the lanes: index the live state again
-    hipLaunchKernelGGL(k_lanes, dim3(S->grid), b, 0, S->stream, S->buf[S->host_t & 1], S->s, S->ctr, 0);
+    if ((rc = reindex(S, S->buf[S->host_t & 1], S->s, S->ctr))) return rc;
     double* out64 = nullptr;
     hipLaunchKernelGGL(k_adj_reduce, dim3((nvals + 63) / 64), dim3(64), 0, S->stream, S->adj.gpart, (int)nthreads,
                        nvals, dL_dtheta, out64);
@@ -863,6 +903,44 @@ int sim_set_idm(sim_t* S, const float* idm) {
     return upload_idm(S, idm);
 }
 
+int sim_set_control(sim_t* S, const int32_t* node_control, int32_t signal_green_steps, float stop_dist,
+                    float stop_speed) {
+    if (!S || !node_control) return SIM_EINVAL;
+    if (signal_green_steps <= 0 || !(stop_dist > 0) || !(stop_speed >= 0) || !std::isfinite(stop_dist) ||
+        !std::isfinite(stop_speed))
+        return fail(S, SIM_EINVAL, "invalid control parameters");
+    if (S->tape_on) return fail(S, SIM_ESTATE, "control cannot change inside a differentiation window");
+    std::vector<int> ctrl(node_control, node_control + S->nn);
+    for (int u = 0; u < S->nn; ++u)
+        if (ctrl[u] < 0 || ctrl[u] > 2) return fail(S, SIM_EINVAL, "node " + std::to_string(u) + ": control not 0, 1 or 2");
+    // host sources stay alive until the stream is synchronised below
+    std::vector<int> in_rank(S->ne), in_deg(S->nn, 0);
+    if (!S->d_ctrl) {
+        for (int e = 0; e < S->ne; ++e) in_rank[e] = in_deg[S->col_idx[e]]++;
+        if (!dalloc(S, S->d_ctrl, S->nn) || !dalloc(S, S->d_in_rank, S->ne) || !dalloc(S, S->d_in_deg, S->nn))
+            return fail(S, SIM_ENOMEM, "control allocation failed");
+        int rc;
+        if ((rc = h2d(S, S->d_in_rank, in_rank.data(), S->ne)) || (rc = h2d(S, S->d_in_deg, in_deg.data(), S->nn)))
+            return rc;
+    }
+    int rc;
+    if ((rc = h2d(S, S->d_ctrl, ctrl.data(), S->nn))) return rc;
+    // every stop node starts free; requests are issued again from the current state
+    const std::vector<int> none(S->nn, -1);
+    if ((rc = h2d(S, S->s.holder, none.data(), S->nn))) return rc;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(kBlock), 0, S->stream, S->s.stop_req, (long long)S->nn, ~0ull);
+    S->P.green = signal_green_steps;
+    S->P.stop_dist = stop_dist;
+    S->P.stop_speed = stop_speed;
+    S->net.ctrl = S->d_ctrl;
+    S->net.in_rank = S->d_in_rank;
+    S->net.in_deg = S->d_in_deg;
+    drop_graphs(S);  // captured launches hold the old parameters
+    if (S->loaded && (rc = reindex(S, S->buf[S->host_t & 1], S->s, S->ctr))) return rc;
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
 int sim_set_timing(sim_t* S, int32_t every) {
     if (!S || every < 0) return SIM_EINVAL;
     S->timing_every = every;
@@ -895,6 +973,12 @@ int sim_set_stream(sim_t* S, void* hip_stream) {
 void sim_destroy(sim_t* S) {
     if (!S) return;
     drop_graphs(S);
+    if (S->gstream) {
+        (void)hipStreamSynchronize(S->gstream);
+        (void)hipStreamDestroy(S->gstream);
+        (void)hipEventDestroy(S->gjoin[0]);
+        (void)hipEventDestroy(S->gjoin[1]);
+    }
     release_all(S);
     for (auto& evs : S->ev_steps)
         for (hipEvent_t e : evs) S->ev_free.push_back(e);
@@ -1026,6 +1110,8 @@ int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
             len = std::min(chunk, to_timed);
         }
         if (num_steps - done < len || len < 2) break;
+        int rc0 = graph_stream(S);
+        if (rc0) return rc0;
         const int parity = (int)(S->host_t & 1);
         hipGraphExec_t exec = nullptr;
         for (auto& g : S->graphs)
@@ -1033,26 +1119,43 @@ int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
         if (!exec) {
             if (S->graphs.size() >= 8) drop_graphs(S);
             hipGraph_t graph;
-            HIPCHECK(S, hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal));
+            HIPCHECK(S, hipStreamBeginCapture(S->gstream, hipStreamCaptureModeThreadLocal));
             const Tape off{};
             int rc = SIM_OK;
+            hipStream_t user = S->stream;
+            S->stream = S->gstream;  // launch_step enqueues on S->stream
             for (int k = 0; k < len && rc == SIM_OK; ++k) {
                 const int p = (parity + k) & 1;
                 rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->pend[p], S->pend[p ^ 1], S->s, off, S->ctr, nullptr);
             }
-            hipError_t ce = hipStreamEndCapture(S->stream, &graph);
-            if (rc) return rc;
-            if (ce != hipSuccess) return fail(S, SIM_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+            S->stream = user;
+            hipError_t ce = hipStreamEndCapture(S->gstream, &graph);
+            if (rc) {
+                if (ce == hipSuccess) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                return rc;
+            }
+            if (ce != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(S, SIM_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+            }
             ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
-            if (ce != hipSuccess) return fail(S, SIM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+            if (ce != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(S, SIM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ce));
+            }
             sim_t::GraphEntry ge;
             ge.parity = parity;
             ge.chunk = len;
             ge.exec = exec;
             S->graphs.push_back(ge);
         }
-        HIPCHECK(S, hipGraphLaunch(exec, S->stream));
+        HIPCHECK(S, hipEventRecord(S->gjoin[0], S->stream));
+        HIPCHECK(S, hipStreamWaitEvent(S->gstream, S->gjoin[0], 0));
+        HIPCHECK(S, hipGraphLaunch(exec, S->gstream));
+        HIPCHECK(S, hipEventRecord(S->gjoin[1], S->gstream));
+        HIPCHECK(S, hipStreamWaitEvent(S->stream, S->gjoin[1], 0));
         S->host_t += len;
         done += len;
     }
@@ -1070,14 +1173,15 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     unsigned long long* st_save = nullptr;
     int* trip_save = nullptr;
     if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.pend, S->cap) || !dalloc(S, save.ctr, 1) ||
-        !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap))
+        !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap) ||
+        !dalloc(S, save.holder, S->nn))
         return fail(S, SIM_ENOMEM, "autotune allocation failed");
     const size_t tb = sizeof(int) * (size_t)S->cap;
     HIPCHECK(S, hipMemcpyAsync(trip_save, S->tr.depart_actual, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
-    int rc = copy_state(S, save.v, save.pend, save.ctr, S->buf[p], S->pend[p], S->ctr);
+    int rc = copy_state(S, save.v, save.pend, save.ctr, save.holder, S->buf[p], S->pend[p], S->ctr, S->s.holder);
     if (rc) return rc;
     const size_t eb = sizeof(unsigned long long) * (size_t)S->ne;
     HIPCHECK(S, hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
@@ -1102,8 +1206,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
             S->grid = gc;
             S->grid_small = gs;
             S->host_t = t_save;
-            if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, save.v, save.pend, save.ctr))) return rc;
-            hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
+            if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, S->s.holder, save.v, save.pend, save.ctr, save.holder))) return rc;
+            if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
             HIPCHECK(S, hipEventRecord(e0, S->stream));
             for (int k = 0; k < steps_per_trial && rc == SIM_OK; ++k) {
                 const int q = (int)(S->host_t & 1);
@@ -1129,7 +1233,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     S->grid = bg;
     S->grid_small = bs;
     drop_graphs(S);
-    if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, save.v, save.pend, save.ctr))) return rc;
+    if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, S->s.holder, save.v, save.pend, save.ctr, save.holder))) return rc;
     HIPCHECK(S, hipMemcpyAsync(S->s.st_cnt, st_save, eb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->s.st_steps, st_save + S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
@@ -1137,8 +1241,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     HIPCHECK(S, hipMemcpyAsync(S->tr.arrive_step, trip_save + S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->tr.fuel_total, trip_save + 2 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->tr.co_total, trip_save + 3 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
-    hipLaunchKernelGGL(k_lanes, dim3(S->grid), dim3(kBlock), 0, S->stream, S->buf[p], S->s, S->ctr, 0);
-    HIPCHECK(S, hipGetLastError());
+    if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
     HIPCHECK(S, hipStreamSynchronize(S->stream));
     *best_grid = bg;
     *best_small = bs;

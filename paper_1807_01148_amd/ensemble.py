@@ -158,6 +158,16 @@ class Ensemble(Sim):
         self.num_edges = self.edge_off[-1]
         self.num_trips = self.trip_off[-1]
         self.num_classes = ncls
+        if any(sc["net"].get("node_control") is not None for sc in scens):
+            # one control array over the concatenated nodes; the timing parameters are shared
+            keys = ("signal_green", "stop_dist", "stop_speed")
+            ctl = [tuple(sc["params"].get(k, d) for k, d in zip(keys, (20, 3.0, 0.5))) for sc in scens]
+            if len(set(ctl)) != 1:
+                raise ValueError("ensemble members must share signal_green, stop_dist and stop_speed")
+            ctrl = np.concatenate([np.asarray(sc["net"]["node_control"], np.int32)
+                                   if sc["net"].get("node_control") is not None
+                                   else np.zeros(sc["net"]["row_ptr"].size - 1, np.int32) for sc in scens])
+            self.set_control(ctrl, *ctl[0])
         PP = ctypes.c_void_p * n
         dem = [sc["demand"] for sc in scens]
         ntr = np.array([d["depart_step"].size for d in dem], np.int32)
