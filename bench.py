@@ -234,6 +234,99 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+# algorithmic bytes per relaxed link of the route search: its weight (8 B),
+# its head node (4 B) and the 8-byte label it lowers
+B_PER_RELAX = 20.0
+
+
+def bench_reroute(args):
+    """Iterative decaying re-routing (Sec. 6.3.1) on the workload: four
+    iterations of (plan routes on the GPU, simulate the whole horizon,
+    measured link times become the weights), re-planning all, all, half and a
+    quarter of the trips.  Reports the route search rate (relaxed links per
+    second) of the full plan, per-iteration times and the mean trip time;
+    the CPU baseline is the oracle's Dijkstra on a sample of origins."""
+    import numpy as np
+    import torch
+    import oracle.routing as OR
+    import paper_1807_01148_amd as P
+    import scenarios as S
+    from paper_1807_01148_amd.route import Router, with_routes
+    log("[reroute] generating workload", args.workload)
+    scen, desc = workload(args.workload)
+    d = scen["demand"]
+    n = int(d["depart_step"].size)
+    masks = S.reroute_masks(1813, n)
+    rt = Router(scen["net"])
+    rt.set_trips(d["src_nodes"], d["trip_src"], d["trip_dst"])
+    its = []
+    for k in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total = rt.plan(None if k == 0 else masks[k])
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        relax, nsrc = rt.last_work()
+        ptr, edges = rt.routes()
+        t0 = time.perf_counter()
+        sim = P.Sim(with_routes(scen, ptr, edges))
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sim.step(scen["steps"])
+        torch.cuda.synchronize()
+        t_sim = time.perf_counter() - t0
+        st = sim.edge_stats_device()
+        rt.weights_from_stats(st["count"], st["tt_us"])
+        tr = sim.trips()
+        done = tr["arrive_step"] >= 0
+        c = sim.counters()
+        its.append({"replanned": int(n if k == 0 else masks[k].sum()), "origins": nsrc, "plan_s": t_plan,
+                    "relaxations": relax, "route_edges": total, "load_s": t_load, "sim_s": t_sim,
+                    "arrived": int(done.sum()),
+                    "mean_trip_s": float((tr["arrive_step"][done] - tr["depart_actual"][done]).mean() *
+                                         scen["params"]["dt"]) if done.any() else None,
+                    "vehicle_updates": c["vehicle_updates"]})
+        log("[reroute] iteration %d: %s" % (k, its[-1]))
+        sim.close()
+        del ptr, edges
+    rate = its[0]["relaxations"] / its[0]["plan_s"]
+    # CPU baseline: the oracle's Dijkstra from a sample of origins, scaled
+    w0 = OR.initial_weights(scen["net"])
+    sample = d["src_nodes"][:: max(1, d["src_nodes"].size // 3)][:3]
+    t0 = time.perf_counter()
+    for s0 in sample:
+        OR.sssp(scen["net"], w0, int(s0))
+    t_cpu = (time.perf_counter() - t0) / len(sample)
+    ne = int(scen["net"]["col_idx"].size)
+    out = {"metric": "re-routing (Sec. 6.3.1): route-search relaxed links/s of a full plan, 4 decaying iterations",
+           "value": rate, "unit": "relaxations/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int64",
+           "data": "synthetic", "config": {"workload": desc, "iterations": 4, "replan_shares": [1, 1, 0.5, 0.25]},
+           "full_plan_s": its[0]["plan_s"], "work_ratio": its[0]["relaxations"] / (its[0]["origins"] * ne),
+           "roofline": {"bound": "hbm", "achieved": rate * B_PER_RELAX / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": rate * B_PER_RELAX / 1e9 / HBM_PEAK_GBS, "traffic": None},
+           "cpu_baseline": {"value": ne / t_cpu, "unit": "relaxations/s", "cores": 1, "kind": "oracle",
+                            "sample": "binary-heap Dijkstra (int64) from %d origins of the workload, each "
+                                      "relaxing every link once" % len(sample)},
+           "iterations": its}
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibration(args):
+    """A plain device-to-device copy of 1 GiB, five times: the reference
+    dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters (each copy
+    reads and writes exactly 1 GiB)."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,7 +339,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
     ap.add_argument("--tune-at", type=int, default=0,
                     help="simulate to this step, autotune the launch shape there, store it in the cache, exit")
-    ap.add_argument("--mode", default="plain", choices=["plain", "ensemble", "adjoint"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "ensemble", "adjoint", "reroute", "copycal"],
                     help="plain: the metric; ensemble / adjoint: speed-up of the batched and adjoint forms "
                          "over the plain per-scenario GPU loop")
     ap.add_argument("--scenarios", type=int, default=64)
@@ -264,6 +357,10 @@ def main():
         return bench_ensemble(args)
     if args.mode == "adjoint":
         return bench_adjoint(args)
+    if args.mode == "reroute":
+        return bench_reroute(args)
+    if args.mode == "copycal":
+        return copy_calibration(args)
 
     log("[bench] generating workload", args.workload)
     t = time.perf_counter()

@@ -24,10 +24,11 @@ FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-
 
 
 def build(force: bool = False):
-    """Compile liboracle_f32.so, liboracle_f64.so and libadjoint.so with gcc."""
+    """Compile liboracle_f32.so, liboracle_f64.so, libadjoint.so and
+    liboracle_route.so with gcc."""
     outs = []
     for prec, defs, name in (("f32", [], "oracle.c"), ("f64", ["-DORACLE_F64"], "oracle.c"),
-                             ("adj", [], "adjoint.c")):
+                             ("adj", [], "adjoint.c"), ("route", [], "routing.c")):
         src = os.path.join(_HERE, name)
         out = os.path.join(_HERE, "liboracle_%s.so" % prec if prec != "adj" else "libadjoint.so")
         if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
@@ -72,6 +73,8 @@ def _lib(prec):
         lib.or_num_active.restype = i32
         lib.or_num_pending.argtypes = [P]
         lib.or_num_pending.restype = i32
+        lib.or_set_vehicle_types.argtypes = [P, i32, P, i32, P]
+        lib.or_set_vehicle_types.restype = ctypes.c_int
         lib.or_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
         lib.or_set_control.restype = ctypes.c_int
         lib.or_get_emissions.argtypes = [P, P, P]
@@ -174,6 +177,13 @@ class Oracle:
                 raise OracleError("or_set_control failed")
         d = scen["demand"]
         self.ntrips = int(d["depart_step"].size)
+        if p.get("vehicle_types") is not None or d.get("trip_type") is not None:
+            vt = arr(p.get("vehicle_types", [[p["veh_length"], np.inf, np.inf]]), np.float32)
+            tt = None if d.get("trip_type") is None else arr(d["trip_type"], np.uint8)
+            if self.lib.or_set_vehicle_types(self.h, int(vt.size // 3), _p(vt), self.ntrips, _p(tt)) != 0:
+                self.lib.or_destroy(self.h)
+                self.h = None
+                raise OracleError("or_set_vehicle_types failed")
         ix = d.get("init_x")
         if tape:
             self.lib.or_tape_enable(self.h, 1)

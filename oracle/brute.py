@@ -46,15 +46,21 @@ class Brute:
         idm = np.asarray(p["idm"], np.float32)
         self.vscale = [float(r[0]) for r in idm]
         self.T = [float(r[1]) for r in idm]
-        self.A = [float(r[2]) for r in idm]
-        self.kab = [1.0 / (2.0 * math.sqrt(float(r[2]) * float(r[3]))) for r in idm]
-        self.inv_v0 = [1.0 / (self.vscale[self.cls[e]] * _f(net["speed"][e])) for e in range(ne)]
+        # vehicle types (Sec. 6.3.5): (length, acceleration cap, speed cap)
+        vt = p.get("vehicle_types")
+        self.types = ([(_f(p["veh_length"]), math.inf, math.inf)] if vt is None else
+                      [(_f(r[0]), _f(r[1]), _f(r[2])) for r in np.asarray(vt, np.float32)])
+        self.A = [[min(float(r[2]), ty[1]) for ty in self.types] for r in idm]
+        self.kab = [[1.0 / (2.0 * math.sqrt(min(float(r[2]), ty[1]) * float(r[3]))) for ty in self.types]
+                    for r in idm]
+        self.inv_v0 = [[1.0 / min(self.vscale[self.cls[e]] * _f(net["speed"][e]), ty[2]) for ty in self.types]
+                       for e in range(ne)]
         self.ncell = [int(math.floor(self.len[e])) + 1 for e in range(ne)]
         self.dt = _f(p["dt"])
         self.h = 0.5 * self.dt * self.dt
         self.lveh = _f(p["veh_length"])
         self.s0 = _f(p["s0"])
-        self.claim_len = self.lveh + self.s0
+        self.claim_len = [ty[0] + self.s0 for ty in self.types]
         self.s_eps = _f(p["s_eps"])
         self.b_max = _f(p["b_max"])
         self.pol = _f(p["mobil_p"])
@@ -75,10 +81,12 @@ class Brute:
         rp = np.asarray(d["route_ptr"], np.int64)
         re = [int(a) for a in d["route_edges"]]
         tr = np.asarray(d["trip_route"], np.int64)
+        ttype = d.get("trip_type")
         self.trips = []
         for vid, i in enumerate(order):
             r = int(tr[i])
-            self.trips.append({"dep": int(dep[i]), "route": re[rp[r]:rp[r + 1]], "orig": int(i)})
+            self.trips.append({"dep": int(dep[i]), "route": re[rp[r]:rp[r + 1]], "orig": int(i),
+                               "ty": 0 if ttype is None else int(ttype[i])})
         self.t = 0
         self.active = []
         self.pending = []
@@ -100,7 +108,10 @@ class Brute:
     def _new(self, vid, lane, x, v, kin, phin):
         route = self.trips[vid]["route"]
         return {"vid": vid, "cur": 0, "edge": route[0], "lane": lane, "x": x, "v": v,
-                "lc": LC_NONE, "kin": kin, "phin": phin}
+                "lc": LC_NONE, "kin": kin, "phin": phin, "ty": self.trips[vid]["ty"]}
+
+    def _len(self, q):
+        return self.types[q["ty"]][0]
 
     def _next(self, q):
         route = self.trips[q["vid"]]["route"]
@@ -109,17 +120,17 @@ class Brute:
     def _on(self, e, l):
         return [q for q in self.active if q["edge"] == e and q["lane"] == l]
 
-    def _idm(self, e, v, lead):
+    def _idm(self, e, v, lead, ty):
         c = self.cls[e]
-        r = v * self.inv_v0[e]
+        r = v * self.inv_v0[e][ty]
         fr = 1.0 - (r * r) * (r * r)
         if lead is None:
-            acc = self.A[c] * fr
+            acc = self.A[c][ty] * fr
         else:
             s, vl = lead
-            dyn = v * self.T[c] + (v * (v - vl)) * self.kab[c]
+            dyn = v * self.T[c] + (v * (v - vl)) * self.kab[c][ty]
             q = (self.s0 + max(0.0, dyn)) / max(s, self.s_eps)
-            acc = self.A[c] * (fr - q * q)
+            acc = self.A[c][ty] * (fr - q * q)
         return max(acc, -self.b_max)
 
     def _move(self, v, acc):
@@ -155,45 +166,46 @@ class Brute:
         ahead = [q for q in self._on(e, l) if q["x"] > x]
         if ahead:
             q = min(ahead, key=lambda q: (q["x"], q["vid"]))
-            return (1, q["x"], q["v"])
+            return (1, q["x"], q["v"], self._len(q))
         if held:
-            return (3, self.len[e], 0.0)
+            return (3, self.len[e], 0.0, 0.0)
         if nxt >= 0:
             q = self._rearmost(nxt, min(l, self.lanes[nxt] - 1))
             if q is not None:
-                return (2, q["x"], q["v"])
+                return (2, q["x"], q["v"], self._len(q))
         return None
 
     def _gap(self, e, ah, x):
         if ah is None:
             return None
-        kind, xl, vl = ah
+        kind, xl, vl, ll = ah
         if kind == 3:
             return (self.len[e] - x, 0.0)
-        s = (xl - self.lveh) - x if kind == 1 else (self.len[e] - x) + (xl - self.lveh)
+        s = (xl - ll) - x if kind == 1 else (self.len[e] - x) + (xl - ll)
         return (s, vl)
 
-    def _cells(self, e, X):
-        return max(0, math.floor(X - self.claim_len)), min(self.ncell[e] - 1, math.floor(X))
+    def _cells(self, e, X, ty):
+        return max(0, math.floor(X - self.claim_len[ty])), min(self.ncell[e] - 1, math.floor(X))
 
     # -- one step ----------------------------------------------------------
     def _decide(self, q):
-        e, l, x, v = q["edge"], q["lane"], q["x"], q["v"]
+        e, l, x, v, ty = q["edge"], q["lane"], q["x"], q["v"], q["ty"]
+        lme = self._len(q)
         nxt = self._next(q)
         held = self._held(e, nxt, q["vid"])
         same = [w for w in self._on(e, l) if (w["x"], w["vid"]) > (x, q["vid"])]
         if same:
             w = min(same, key=lambda w: (w["x"], w["vid"]))
-            own = (1, w["x"], w["v"])
+            own = (1, w["x"], w["v"], self._len(w))
         elif held:
-            own = (3, self.len[e], 0.0)
+            own = (3, self.len[e], 0.0, 0.0)
         elif nxt >= 0:
             w = self._rearmost(nxt, min(l, self.lanes[nxt] - 1))
-            own = None if w is None else (2, w["x"], w["v"])
+            own = None if w is None else (2, w["x"], w["v"], self._len(w))
         else:
             own = None
         L = self._gap(e, own, x)
-        ac = self._idm(e, v, L)
+        ac = self._idm(e, v, L, ty)
         dx, vn = self._move(v, ac)
         dx, vn, clamped = self._clamp(L, dx, vn)
         xs = x + dx
@@ -206,11 +218,11 @@ class Brute:
             tl = min(l, self.lanes[nxt] - 1)
             X = xs - self.len[e]
             out.update(kind="cross", f=f, tedge=nxt, tlane=tl, X=X, vc=vn, xs=self.len[e], vs=0.0,
-                       cells=self._cells(nxt, X))
+                       cells=self._cells(nxt, X, ty))
             return out
         out.update(kind="stay", xs=xs, vs=vn)
         n = self.lanes[e]
-        if n < 2 or self.t - q["lc"] < self.cool or x < self.lveh:
+        if n < 2 or self.t - q["lc"] < self.cool or x < lme:
             return out
         if nxt >= 0:
             hn = self.head[e]
@@ -238,9 +250,9 @@ class Brute:
             Ft = max(lag, key=lambda w: (w["x"], w["vid"])) if lag else None
             if Lt is not None and Lt[0] < self.s0:
                 continue
-            if Ft is not None and (x - self.lveh) - Ft["x"] < self.s0:
+            if Ft is not None and (x - lme) - Ft["x"] < self.s0:
                 continue
-            at = self._idm(e, v, Lt)
+            at = self._idm(e, v, Lt, ty)
             if at < -self.bsafe:
                 continue
             dxt, vt = self._move(v, at)
@@ -250,20 +262,21 @@ class Brute:
                 continue
             an = ant = 0.0
             if Ft is not None:
-                an = self._idm(e, Ft["v"], self._gap(e, ah, Ft["x"]))
-                ant = self._idm(e, Ft["v"], ((x - self.lveh) - Ft["x"], v))
+                tf = Ft["ty"]
+                an = self._idm(e, Ft["v"], self._gap(e, ah, Ft["x"]), tf)
+                ant = self._idm(e, Ft["v"], ((x - lme) - Ft["x"], v), tf)
                 if ant < -self.bsafe:
                     continue
-                dxF, _ = self._move(Ft["v"], self._idm(e, Ft["v"], None))
-                if (Xt - self.lveh) - Ft["x"] < dxF:
+                dxF, _ = self._move(Ft["v"], self._idm(e, Ft["v"], None, tf))
+                if (Xt - lme) - Ft["x"] < dxF:
                     continue
             inc = 0.0
             if not mand:
                 d2 = (ant - an) if Ft is not None else 0.0
                 d3 = 0.0
                 if F is not None:
-                    ao = self._idm(e, F["v"], ((x - self.lveh) - F["x"], v))
-                    aot = self._idm(e, F["v"], self._gap(e, own, F["x"]))
+                    ao = self._idm(e, F["v"], ((x - lme) - F["x"], v), F["ty"])
+                    aot = self._idm(e, F["v"], self._gap(e, own, F["x"]), F["ty"])
                     d3 = aot - ao
                 inc = (at - ac) + self.pol * (d2 + d3)
                 if not inc > self.athr:
@@ -272,7 +285,7 @@ class Brute:
                 best = (inc, lt, Xt, vt)
         if best is not None:
             out.update(kind="change", tedge=e, tlane=best[1], X=best[2], vc=best[3],
-                       cells=self._cells(e, best[2]))
+                       cells=self._cells(e, best[2], ty))
         return out
 
     def _exit(self, q, f):
@@ -311,12 +324,13 @@ class Brute:
             best, bsp = -1, 0.0
             for l in range(self.lanes[e0]):
                 r = self._rearmost(e0, l)
-                sp = (r["x"] - self.lveh) if r is not None else self.len[e0]
+                sp = (r["x"] - self._len(r)) if r is not None else self.len[e0]
                 if best < 0 or sp > bsp:
                     best, bsp = l, sp
-            if bsp >= self.claim_len:
+            ty = self.trips[v]["ty"]
+            if bsp >= self.claim_len[ty]:
                 ins_lane[v] = best
-                lo, hi = self._cells(e0, self.lveh)
+                lo, hi = self._cells(e0, self.types[ty][0], ty)
                 claims.append((e0, best, lo, hi, v, ("ins", v)))
         won = set()
         for a in claims:
@@ -344,7 +358,7 @@ class Brute:
         pend = []
         for v in cands:
             if ("ins", v) in won:
-                new.append(self._new(v, ins_lane[v], self.lveh, 0.0, t + 1, 1.0))
+                new.append(self._new(v, ins_lane[v], self.types[self.trips[v]["ty"]][0], 0.0, t + 1, 1.0))
                 self.depart_actual[v] = t + 1
             else:
                 pend.append(v)

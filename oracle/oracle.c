@@ -56,6 +56,7 @@ enum { TM_STAY = 0, TM_CHANGE = 1, TM_YIELD = 2, TM_ARRIVE = 3, TM_CROSS = 4, TM
 
 typedef struct {
     int32_t vid, edge, lane, rcur, next, lc, kin;
+    int32_t ty; /* vehicle type (0 car; Sec. 6.3.5 adds trucks) */
     real x, v, phin;
     real fuel, co; /* accumulated fuel (mL) and CO (g) */
 } veh_t;
@@ -68,12 +69,20 @@ typedef struct {
     int32_t green;
     real stop_dist, stop_speed;
     int32_t *row_ptr, *col_idx, *lanes, *cls, *lane_base, *ncell;
-    real *len, *inv_v0;
+    real *len, *inv_v0; /* inv_v0[e * nt + type] */
     /* parameters */
     int32_t ncls, lc_cool;
     real dt, h, lveh, s0, claim_len, s_eps, b_max, p, athr, bsafe, dmand, dt_us_f;
     int64_t dt_us;
-    real *T, *A, *kab;
+    real *T, *A, *kab; /* A, kab: [class * nt + type] */
+    /* vehicle types (Sec. 6.3.5): length, acceleration cap, speed cap */
+    int32_t nt;
+    real tlen[4], tclaim[4];
+    double tamax[4], tvmax[4];
+    float *idm_in, *speed_in; /* inputs the per-type constants are derived from */
+    uint8_t* trip_type; /* per trip (input order), set before loading */
+    int32_t ntyped;
+    int32_t* vtype;     /* per vehicle id */
     real mph; /* miles per hour per m/s */
     /* demand, indexed by vehicle id */
     int32_t ntrips, loaded;
@@ -119,6 +128,62 @@ static void tape_push(osim* S, int32_t step, int32_t vid, int32_t mode, int32_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Per (class, type) and (link, type) car-following constants: a type caps the
+ * class's maximum acceleration and the link's desired speed (Sec. 6.3.5:
+ * trucks differ in size, acceleration and maximum speed).  In double, rounded
+ * once; with no cap (infinite) they are the class's own values. */
+static void derive_type_constants(osim* S) {
+    const int nt = S->nt;
+    free(S->A); free(S->kab); free(S->inv_v0);
+    S->A = (real*)malloc(sizeof(real) * S->ncls * nt);
+    S->kab = (real*)malloc(sizeof(real) * S->ncls * nt);
+    S->inv_v0 = (real*)malloc(sizeof(real) * S->ne * nt);
+    for (int c = 0; c < S->ncls; ++c) {
+        double a = S->idm_in[4 * c + 2], b = S->idm_in[4 * c + 3];
+        S->T[c] = (real)S->idm_in[4 * c + 1];
+        for (int k = 0; k < nt; ++k) {
+            double ak = a < S->tamax[k] ? a : S->tamax[k];
+            S->A[c * nt + k] = (real)ak;
+            S->kab[c * nt + k] = (real)(1.0 / (2.0 * sqrt(ak * b)));
+        }
+    }
+    for (int32_t e = 0; e < S->ne; ++e) {
+        double v0 = (double)S->idm_in[4 * S->cls[e] + 0] * (double)S->speed_in[e];
+        for (int k = 0; k < nt; ++k) S->inv_v0[e * nt + k] = (real)(1.0 / (v0 < S->tvmax[k] ? v0 : S->tvmax[k]));
+    }
+}
+
+/* Vehicle types (Sec. 6.3.5), before or_load_demand: types[nt][3] = (length,
+ * acceleration cap, speed cap; caps may be +inf), trip_type[ntrips] in input
+ * order (NULL: all type 0).  Every link must hold the longest type. */
+int or_set_vehicle_types(osim* S, int32_t nt, const float* types, int32_t ntrips, const uint8_t* trip_type) {
+    if (S->loaded) return OR_ESTATE;
+    if (nt < 1 || nt > 4 || ntrips < 0) return OR_EINVAL;
+    for (int k = 0; k < nt; ++k) {
+        if (!(types[3 * k] > 0) || !(types[3 * k + 1] > 0) || !(types[3 * k + 2] > 0)) return OR_EINVAL;
+        for (int32_t e = 0; e < S->ne; ++e)
+            if (!((double)S->len[e] >= (double)types[3 * k] + (double)S->s0)) return OR_EINVAL;
+    }
+    for (int32_t i = 0; i < ntrips; ++i)
+        if (trip_type && trip_type[i] >= nt) return OR_EINVAL;
+    S->nt = nt;
+    for (int k = 0; k < nt; ++k) {
+        S->tlen[k] = (real)types[3 * k];
+        S->tclaim[k] = (real)((double)types[3 * k] + (double)S->s0);
+        S->tamax[k] = (double)types[3 * k + 1];
+        S->tvmax[k] = (double)types[3 * k + 2];
+    }
+    free(S->trip_type);
+    S->trip_type = NULL;
+    S->ntyped = ntrips;
+    if (trip_type) {
+        S->trip_type = (uint8_t*)malloc(ntrips + 1);
+        memcpy(S->trip_type, trip_type, ntrips);
+    }
+    derive_type_constants(S);
+    return OR_OK;
+}
+
 /* creation: derived constants are computed once in double from the inputs
  * and rounded once to `real`. */
 osim* or_create(int32_t nn, int32_t ne, const int32_t* row_ptr, const int32_t* col_idx,
@@ -156,12 +221,18 @@ osim* or_create(int32_t nn, int32_t ne, const int32_t* row_ptr, const int32_t* c
     S->dt_us = llround((double)fp[0] * 1e6);
     S->dt_us_f = (real)((double)fp[0] * 1e6);
     S->mph = (real)(1.0 / 0.44704);
+    S->nt = 1;
+    S->tamax[0] = INFINITY;
+    S->tvmax[0] = INFINITY;
+    S->tlen[0] = S->lveh;
+    S->tclaim[0] = S->claim_len;
+    S->idm_in = (float*)malloc(sizeof(float) * 4 * ncls);
+    S->speed_in = (float*)malloc(sizeof(float) * ne);
+    memcpy(S->idm_in, idm, sizeof(float) * 4 * ncls);
+    memcpy(S->speed_in, speed, sizeof(float) * ne);
     for (int c = 0; c < ncls; ++c) {
         double a = idm[4 * c + 2], b = idm[4 * c + 3];
         if (!(a > 0) || !(b > 0) || !(idm[4 * c + 0] > 0) || !(idm[4 * c + 1] >= 0)) goto bad;
-        S->T[c] = (real)idm[4 * c + 1];
-        S->A[c] = (real)a;
-        S->kab[c] = (real)(1.0 / (2.0 * sqrt(a * b)));
     }
     S->lane_base[0] = 0;
     for (int32_t e = 0; e < ne; ++e) {
@@ -173,17 +244,18 @@ osim* or_create(int32_t nn, int32_t ne, const int32_t* row_ptr, const int32_t* c
         S->lanes[e] = lanes[e];
         S->cls[e] = c;
         S->len[e] = (real)length[e];
-        S->inv_v0[e] = (real)(1.0 / ((double)idm[4 * c + 0] * (double)speed[e]));
         S->ncell[e] = (int32_t)floor((double)length[e]) + 1;
         S->lane_base[e + 1] = S->lane_base[e] + lanes[e];
     }
     S->nlanes = S->lane_base[ne];
+    derive_type_constants(S);
     *err = OR_OK;
     return S;
 bad:
     *err = OR_EINVAL;
     free(S->row_ptr); free(S->col_idx); free(S->lanes); free(S->cls); free(S->lane_base);
-    free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab); free(S);
+    free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab);
+    free(S->idm_in); free(S->speed_in); free(S);
     return NULL;
 }
 
@@ -216,6 +288,7 @@ void or_destroy(osim* S) {
     free(S->ctrl); free(S->holder); free(S->in_rank); free(S->in_deg);
     free(S->row_ptr); free(S->col_idx); free(S->lanes); free(S->cls); free(S->lane_base);
     free(S->ncell); free(S->len); free(S->inv_v0); free(S->T); free(S->A); free(S->kab);
+    free(S->idm_in); free(S->speed_in); free(S->trip_type); free(S->vtype);
     free(S->dep); free(S->rbeg); free(S->rend); free(S->route_edges);
     free(S->depart_actual); free(S->arrive_step); free(S->act); free(S->pend);
     free(S->st_cnt); free(S->st_steps); free(S->st_us);
@@ -293,8 +366,14 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
     S->nroute_edges = nre;
     S->route_edges = (int32_t*)malloc(sizeof(int32_t) * (nre + 1));
     memcpy(S->route_edges, route_edges, sizeof(int32_t) * nre);
+    if (S->trip_type && S->ntyped != ntrips) {
+        free(ord);
+        return OR_EINVAL;
+    }
+    S->vtype = (int32_t*)malloc(sizeof(int32_t) * (ntrips + 1));
     for (int32_t v = 0; v < ntrips; ++v) {
         int32_t i = ord[v];
+        S->vtype[v] = S->trip_type ? (int32_t)S->trip_type[i] : 0;
         S->dep[v] = depart_step[i];
         S->rbeg[v] = (int32_t)route_ptr[trip_route[i]];
         S->rend[v] = (int32_t)route_ptr[trip_route[i] + 1];
@@ -314,6 +393,7 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
             int32_t i = ord[v];
             veh_t* q = &S->act[v];
             q->vid = v;
+            q->ty = S->vtype[v];
             q->rcur = S->rbeg[v];
             q->edge = S->route_edges[q->rcur];
             q->next = (q->rcur + 1 < S->rend[v]) ? S->route_edges[q->rcur + 1] : -1;
@@ -339,7 +419,7 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
         qsort(o, ntrips, sizeof(int32_t), cmp_order);
         for (int32_t k = 0; k + 1 < ntrips; ++k) {
             const veh_t *a = &S->act[o[k]], *b = &S->act[o[k + 1]];
-            if (a->edge == b->edge && a->lane == b->lane && ((b->x - S->lveh) - a->x) < 0) {
+            if (a->edge == b->edge && a->lane == b->lane && ((b->x - S->tlen[b->ty]) - a->x) < 0) {
                 free(o); free(ord);
                 S->nact = 0;
                 return OR_EINVAL;
@@ -365,6 +445,7 @@ typedef struct {
     real vl;    /* speed of the vehicle ahead */
     real xl;    /* its front position on its own link */
     int32_t vid;
+    real ll;    /* its length */
 } lead_t;
 
 /* branch flags of one applied motion (recorded in the event tape) */
@@ -381,7 +462,8 @@ static int lead_flags(lead_t L) {
 /* IDM acceleration (Sec. 6.3.2, car-following equation), with the dynamic
  * part of the desired gap floored at 0, the gap floored at s_eps and the
  * result floored at -b_max. */
-static real idm_fl(const osim* S, int32_t c, real inv_v0, real v, lead_t L, int* fl) {
+static real idm_fl(const osim* S, int32_t c, int32_t ty, real inv_v0, real v, lead_t L, int* fl) {
+    const real A = S->A[c * S->nt + ty], kab = S->kab[c * S->nt + ty];
     real r = v * inv_v0;
     real r2 = r * r;
     real r4 = r2 * r2;
@@ -389,23 +471,23 @@ static real idm_fl(const osim* S, int32_t c, real inv_v0, real v, lead_t L, int*
     real acc;
     int f = 0;
     if (L.kind == 0) {
-        acc = S->A[c] * fr;
+        acc = A * fr;
     } else {
         real dv = v - L.vl;
-        real dyn = v * S->T[c] + (v * dv) * S->kab[c];
+        real dyn = v * S->T[c] + (v * dv) * kab;
         if ((real)0 > dyn) f |= TF_DYN_FLOOR;
         real ss = S->s0 + RMAX((real)0, dyn);
         if (!(L.s > S->s_eps)) f |= TF_S_FLOOR;
         real q = ss / RMAX(L.s, S->s_eps);
-        acc = S->A[c] * (fr - q * q);
+        acc = A * (fr - q * q);
     }
     if (!(acc > -S->b_max)) f |= TF_ACC_FLOOR;
     if (fl) *fl |= f;
     return RMAX(acc, -S->b_max);
 }
 
-static real idm(const osim* S, int32_t c, real inv_v0, real v, lead_t L) {
-    return idm_fl(S, c, inv_v0, v, L, NULL);
+static real idm(const osim* S, int32_t c, int32_t ty, real inv_v0, real v, lead_t L) {
+    return idm_fl(S, c, ty, inv_v0, v, L, NULL);
 }
 
 /* Ballistic update over dt; when the speed would turn negative the vehicle
@@ -469,8 +551,8 @@ static int cmp_claim(const void* a, const void* b) {
     return (u->vid > w->vid) - (u->vid < w->vid);
 }
 
-static void claim_cells(const osim* S, int32_t edge, real X, int32_t* lo, int32_t* hi) {
-    int32_t a = (int32_t)RFLOOR(X - S->claim_len);
+static void claim_cells(const osim* S, int32_t edge, int32_t ty, real X, int32_t* lo, int32_t* hi) {
+    int32_t a = (int32_t)RFLOOR(X - S->tclaim[ty]);
     int32_t b = (int32_t)RFLOOR(X);
     *lo = a < 0 ? 0 : a;
     *hi = b > S->ncell[edge] - 1 ? S->ncell[edge] - 1 : b;
@@ -501,7 +583,7 @@ static int blocked(const osim* S, int32_t e, int32_t next, int32_t vid) {
 
 /* a stopped virtual vehicle whose rear is at the link end */
 static lead_t stop_line(const osim* S, int32_t e, real x) {
-    lead_t L = {3, S->len[e] - x, (real)0, S->len[e], -1};
+    lead_t L = {3, S->len[e] - x, (real)0, S->len[e], -1, (real)0};
     return L;
 }
 
@@ -510,12 +592,12 @@ static lead_t stop_line(const osim* S, int32_t e, real x) {
  * vehicle of lane min(l, lanes-1) of the next link. */
 static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_t next, int32_t l, int held) {
     const osim* S = W->S;
-    lead_t L = {0, 0, 0, 0, -1};
+    lead_t L = {0, 0, 0, 0, -1, 0};
     int32_t f = W->first[k], n = W->cnt[k];
     for (int32_t j = 0; j < n; ++j) {
         const veh_t* q = at(W, f + j);
         if (q->x > x) {
-            L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x; L.vid = q->vid;
+            L.kind = 1; L.xl = q->x; L.vl = q->v; L.ll = S->tlen[q->ty]; L.s = (q->x - L.ll) - x; L.vid = q->vid;
             return L;
         }
     }
@@ -525,7 +607,8 @@ static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_
         int32_t k2 = lane_key(S, next, l2);
         if (W->cnt[k2] > 0) {
             const veh_t* q = at(W, W->first[k2]);
-            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (S->len[e] - x) + (q->x - S->lveh); L.vid = q->vid;
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.ll = S->tlen[q->ty];
+            L.s = (S->len[e] - x) + (q->x - L.ll); L.vid = q->vid;
         }
     }
     return L;
@@ -534,8 +617,8 @@ static lead_t lead_in_lane(const view_t* W, int32_t e, int32_t k, real x, int32_
 /* the same vehicle ahead, seen from another vehicle at xf on the same link */
 static lead_t relead(const osim* S, int32_t e, lead_t L, real xf) {
     lead_t R = L;
-    if (L.kind == 1) R.s = (L.xl - S->lveh) - xf;
-    else if (L.kind == 2) R.s = (S->len[e] - xf) + (L.xl - S->lveh);
+    if (L.kind == 1) R.s = (L.xl - L.ll) - xf;
+    else if (L.kind == 2) R.s = (S->len[e] - xf) + (L.xl - L.ll);
     else if (L.kind == 3) R.s = S->len[e] - xf;
     return R;
 }
@@ -543,17 +626,18 @@ static lead_t relead(const osim* S, int32_t e, lead_t L, real xf) {
 static dec_t decide(const view_t* W, int32_t o) {
     const osim* S = W->S;
     const veh_t* me = at(W, o);
-    int32_t e = me->edge, l = me->lane, c = S->cls[e], k = lane_key(S, e, l);
-    real len = S->len[e], iv = S->inv_v0[e], x = me->x, v = me->v;
+    int32_t e = me->edge, l = me->lane, c = S->cls[e], k = lane_key(S, e, l), ty = me->ty;
+    real len = S->len[e], iv = S->inv_v0[e * S->nt + ty], x = me->x, v = me->v;
+    real lme = S->tlen[ty]; /* own length */
     dec_t D;
     memset(&D, 0, sizeof(D));
 
     /* own leader: the next vehicle of this lane, else look ahead one link */
     const int held = blocked(S, e, me->next, me->vid);
-    lead_t L = {0, 0, 0, 0, -1};
+    lead_t L = {0, 0, 0, 0, -1, 0};
     if (o + 1 < S->nact && lane_key(S, at(W, o + 1)->edge, at(W, o + 1)->lane) == k) {
         const veh_t* q = at(W, o + 1);
-        L.kind = 1; L.xl = q->x; L.vl = q->v; L.s = (q->x - S->lveh) - x; L.vid = q->vid;
+        L.kind = 1; L.xl = q->x; L.vl = q->v; L.ll = S->tlen[q->ty]; L.s = (q->x - L.ll) - x; L.vid = q->vid;
     } else if (held) {
         L = stop_line(S, e, x);
     } else if (me->next >= 0) {
@@ -562,13 +646,14 @@ static dec_t decide(const view_t* W, int32_t o) {
         int32_t k2 = lane_key(S, n2, l2);
         if (W->cnt[k2] > 0) {
             const veh_t* q = at(W, W->first[k2]);
-            L.kind = 2; L.xl = q->x; L.vl = q->v; L.s = (len - x) + (q->x - S->lveh); L.vid = q->vid;
+            L.kind = 2; L.xl = q->x; L.vl = q->v; L.ll = S->tlen[q->ty];
+            L.s = (len - x) + (q->x - L.ll); L.vid = q->vid;
         }
     }
     D.own_fl = lead_flags(L);
     D.own_lead = L.kind ? L.vid : -1;
     D.chg_lead = -1;
-    real ac = idm_fl(S, c, iv, v, L, &D.own_fl);
+    real ac = idm_fl(S, c, ty, iv, v, L, &D.own_fl);
     real dx, vn;
     move_fl(S, v, ac, &dx, &vn, &D.own_fl);
     D.clamped = clampmv_fl(L, &dx, &vn, &D.own_fl);
@@ -591,7 +676,7 @@ static dec_t decide(const view_t* W, int32_t o) {
         D.vc = vn;
         D.xs = len;
         D.vs = (real)0;
-        claim_cells(S, n2, D.X, &D.lo, &D.hi);
+        claim_cells(S, n2, ty, D.X, &D.lo, &D.hi);
         return D;
     }
     D.kind = K_STAY;
@@ -600,7 +685,7 @@ static dec_t decide(const view_t* W, int32_t o) {
 
     /* lane change (Sec. 6.3.2): eligibility */
     int32_t n = S->lanes[e];
-    if (n < 2 || (S->t - me->lc) < S->lc_cool || x < S->lveh) return D;
+    if (n < 2 || (S->t - me->lc) < S->lc_cool || x < lme) return D;
     int32_t lo = 0, hi = n - 1;
     if (me->next >= 0) {
         int32_t hn = S->col_idx[e];
@@ -642,9 +727,9 @@ static dec_t decide(const view_t* W, int32_t o) {
         }
         /* gap acceptance */
         if (Lt.kind != 0 && Lt.s < S->s0) continue;
-        if (Ft && ((x - S->lveh) - Ft->x) < S->s0) continue;
+        if (Ft && ((x - lme) - Ft->x) < S->s0) continue;
         int tfl = lead_flags(Lt);
-        real at_ = idm_fl(S, c, iv, v, Lt, &tfl);
+        real at_ = idm_fl(S, c, ty, iv, v, Lt, &tfl);
         if (at_ < -S->bsafe) continue;
         real dxt, vt;
         move_fl(S, v, at_, &dxt, &vt, &tfl);
@@ -653,15 +738,17 @@ static dec_t decide(const view_t* W, int32_t o) {
         if (Xt >= len) continue;
         real an = 0, ant = 0;
         if (Ft) {
-            an = idm(S, c, iv, Ft->v, relead(S, e, Lt, Ft->x));
-            lead_t Li = {1, (x - S->lveh) - Ft->x, v, x, me->vid};
-            ant = idm(S, c, iv, Ft->v, Li);
+            const int32_t tf = Ft->ty; /* the lag follows with its own type's constants */
+            const real ivf = S->inv_v0[e * S->nt + tf];
+            an = idm(S, c, tf, ivf, Ft->v, relead(S, e, Lt, Ft->x));
+            lead_t Li = {1, (x - lme) - Ft->x, v, x, me->vid, lme};
+            ant = idm(S, c, tf, ivf, Ft->v, Li);
             if (ant < -S->bsafe) continue;
-            lead_t none = {0, 0, 0, 0, -1};
-            real afree = idm(S, c, iv, Ft->v, none);
+            lead_t none = {0, 0, 0, 0, -1, 0};
+            real afree = idm(S, c, tf, ivf, Ft->v, none);
             real dxF, vF;
             move(S, Ft->v, afree, &dxF, &vF);
-            if (((Xt - S->lveh) - Ft->x) < dxF) continue;
+            if (((Xt - lme) - Ft->x) < dxF) continue;
         }
         real inc = 0;
         if (!mand) {
@@ -669,9 +756,11 @@ static dec_t decide(const view_t* W, int32_t o) {
             real d2 = Ft ? (ant - an) : (real)0;
             real d3 = (real)0;
             if (F) {
-                lead_t Lo = {1, (x - S->lveh) - F->x, v, x, me->vid};
-                real ao = idm(S, c, iv, F->v, Lo);
-                real aot = idm(S, c, iv, F->v, relead(S, e, L, F->x));
+                const int32_t tf = F->ty;
+                const real ivf = S->inv_v0[e * S->nt + tf];
+                lead_t Lo = {1, (x - lme) - F->x, v, x, me->vid, lme};
+                real ao = idm(S, c, tf, ivf, F->v, Lo);
+                real aot = idm(S, c, tf, ivf, F->v, relead(S, e, L, F->x));
                 d3 = aot - ao;
             }
             inc = d1 + S->p * (d2 + d3);
@@ -691,7 +780,7 @@ static dec_t decide(const view_t* W, int32_t o) {
         D.vc = best_v;
         D.chg_fl = best_fl;
         D.chg_lead = best_lead;
-        claim_cells(S, e, best_X, &D.lo, &D.hi);
+        claim_cells(S, e, ty, best_X, &D.lo, &D.hi);
     }
     return D;
 }
@@ -796,15 +885,15 @@ static int step_once(osim* S) {
         real bsp = 0;
         for (int32_t l = 0; l < S->lanes[e0]; ++l) {
             int32_t k = lane_key(S, e0, l);
-            real sp = cnt[k] > 0 ? (at(&W, first[k])->x - S->lveh) : S->len[e0];
+            real sp = cnt[k] > 0 ? (at(&W, first[k])->x - S->tlen[at(&W, first[k])->ty]) : S->len[e0];
             if (best < 0 || sp > bsp) { best = l; bsp = sp; }
         }
         clane[i] = -1;
-        if (bsp >= S->claim_len) {
+        if (bsp >= S->tclaim[S->vtype[v]]) {
             clane[i] = best;
             claim_t c;
             c.key = lane_key(S, e0, best);
-            claim_cells(S, e0, S->lveh, &c.lo, &c.hi);
+            claim_cells(S, e0, S->vtype[v], S->tlen[S->vtype[v]], &c.lo, &c.hi);
             c.vid = v; c.src = -1 - i; c.win = 0;
             C[nclaim++] = c;
         }
@@ -890,7 +979,8 @@ static int step_once(osim* S) {
             q.edge = S->route_edges[q.rcur];
             q.lane = clane[i];
             q.next = (q.rcur + 1 < S->rend[v]) ? S->route_edges[q.rcur + 1] : -1;
-            q.x = S->lveh;
+            q.ty = S->vtype[v];
+            q.x = S->tlen[q.ty];
             q.v = (real)0;
             q.lc = LC_NONE;
             q.kin = t + 1;

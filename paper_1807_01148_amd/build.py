@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = [os.path.join(HERE, "csrc", "trafficsim.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "trafficsim.hip"), os.path.join(HERE, "csrc", "route.hip")]
 LIB = os.path.join(HERE, "libtrafficsim.so")
 
 FLAGS = [

@@ -317,12 +317,31 @@ def uniform_od(rng, n_nodes, n_trips):
 
 def make_demand(net, orig, dest, depart_s, dt):
     trip_route, route_ptr, route_edges = routes_for_pairs(net, orig, dest)
+    src_nodes, trip_src = np.unique(np.asarray(orig, np.int64), return_inverse=True)
     return {
         "depart_step": np.floor(np.asarray(depart_s) / dt).astype(np.int32),
         "trip_route": trip_route,
         "route_ptr": route_ptr,
         "route_edges": route_edges,
+        # the O/D pairs, for planning routes again: distinct origins, and per
+        # trip the index of its origin and its destination node
+        "src_nodes": src_nodes.astype(np.int32),
+        "trip_src": trip_src.astype(np.int32),
+        "trip_dst": np.asarray(dest, np.int32),
     }
+
+
+def reroute_masks(seed: int, n_trips: int, shares=(1.0, 1.0, 0.5, 0.25)):
+    """Per iteration, which trips plan their route again: a uniform random
+    subset of exactly round(share * n) trips (all of them for share 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for sh in shares:
+        m = np.zeros(n_trips, bool)
+        k = int(round(sh * n_trips))
+        m[rng.choice(n_trips, k, replace=False)] = True
+        out.append(m)
+    return out
 
 
 # ---------------------------------------------------------------------------

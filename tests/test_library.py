@@ -1,5 +1,5 @@
 """CPU-side checks of the C-ABI library: it loads, and it exports every entry
-point that include/trafficsim.h declares.  No compute calls (no GPU here)."""
+point that the headers under include/ declare.  No compute calls (no GPU here)."""
 import os
 import re
 import subprocess
@@ -7,19 +7,22 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "trafficsim.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(sim_[a-z_]+)\s*\(", text)
-    return sorted(set(n for n in names if not n.endswith("_fn")))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b((?:sim|rt)_[a-z_]+)\s*\(", text))
+    return sorted(n for n in names if not n.endswith("_fn"))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ("sim_create", "sim_load_demand", "sim_step", "sim_stats"):
+    for n in ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_set_control", "rt_create", "rt_plan",
+              "rt_weights_from_stats"):
         assert n in names
 
 
@@ -29,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(lib_path):
         pytest.fail("libtrafficsim.so is not built")
     out = subprocess.check_output(["nm", "-D", "--defined-only", lib_path]).decode()
-    exported = set(re.findall(r" T (sim_\w+)", out))
+    exported = set(re.findall(r" T ((?:sim|rt)_\w+)", out))
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     lib = P.library()
