@@ -70,7 +70,7 @@ def cpu_baseline(seconds_budget=20.0):
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds_budget or steps >= 200:
+        if el > seconds_budget or steps >= 5000:
             break
     upd = o.counters()["vehicle_updates"]
     return {"value": upd / el, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",

@@ -167,6 +167,20 @@ int sim_read_samples(sim_t* sim, int64_t* count, int64_t* speed_um);
  * constants are recomputed as in sim_create.  Errors: SIM_EINVAL. */
 int sim_set_idm(sim_t* sim, const float* idm);
 
+/* Vehicle types (Sec. 6.3.5: trucks differ from cars in size, acceleration
+ * and maximum speed).  types: HOST float [num_types][3] = (length in m,
+ * acceleration cap in m/s^2, speed cap in m/s); a cap may be +inf.  A vehicle
+ * of type k has length types[k][0] (gaps to it, its claim cells, its entry
+ * point x = length); its car-following uses a = min(a_class, cap_a) and
+ * v0 = min(v0_scale * speed limit, cap_v).  trip_type: HOST uint8 [num_trips]
+ * in the trip order of sim_load_demand (NULL: every trip type 0).  Without
+ * this call there is one type: (veh_length, +inf, +inf).  1 <= num_types <= 4;
+ * every link must be at least as long as every type plus s0.  Must precede
+ * sim_load_demand (for ensembles: the concatenated trips, scenario order).
+ * Errors: SIM_EINVAL, SIM_ESTATE (demand already loaded). */
+int sim_set_vehicle_types(sim_t* sim, int32_t num_types, const float* types, int32_t num_trips,
+                          const uint8_t* trip_type);
+
 /* Intersection control (Sec. 6.3.2, stop signs and traffic signals).
  * node_control: HOST int32[num_nodes] (copied), 0 = uncontrolled, 1 = stop
  * sign, 2 = signal.  A vehicle whose next movement (link e -> link e') is held

@@ -45,7 +45,7 @@ def _adjlib():
         lib = ctypes.CDLL(os.path.join(_HERE, "libadjoint.so"))
         P = ctypes.c_void_p
         lib.adj_eval.argtypes = [ctypes.c_int64] + [P] * 8 + [ctypes.c_int32, ctypes.c_int32, P, P, P,
-                                                            ctypes.c_int32] + [P] * 9 + [ctypes.c_int32]
+                                                            ctypes.c_int32] + [P] * 9 + [ctypes.c_int32] * 2 + [P] * 2
         lib.adj_eval.restype = ctypes.c_int
         _LIBS["adj"] = lib
     return _LIBS["adj"]
@@ -135,9 +135,19 @@ def replay(tape, scen, theta, target, mask, grad=True, at_tape_states=False):
     xf = np.zeros(max(nveh, 1), np.float64)
     vf = np.zeros(max(nveh, 1), np.float64)
     tp = {k: np.ascontiguousarray(tape[k]) for k in TAPE_INT + TAPE_F64}
+    # vehicle types (Sec. 6.3.5): the table as float32 inputs, the type of each vehicle id
+    types = np.ascontiguousarray(np.asarray(p.get("vehicle_types", [[p["veh_length"], np.inf, np.inf]]),
+                                            np.float32).astype(np.float64).reshape(-1, 3))
+    tt = scen["demand"].get("trip_type")
+    dep = np.asarray(scen["demand"]["depart_step"])
+    order = np.lexsort((np.arange(dep.size), dep))  # vehicle id -> trip
+    vtype = np.zeros(max(nveh, 1), np.int32)
+    if tt is not None:
+        vtype[:nveh] = np.asarray(tt, np.int32)[order]
     rc = lib.adj_eval(int(tp["step"].size), *[_p(tp[k]) for k in TAPE_INT + TAPE_F64], nveh, ne,
                       _p(length), _p(speed), _p(cls), int(th.shape[0]), _p(th), _p(fp), _p(tgt), _p(msk),
-                      ctypes.byref(loss), _p(g), _p(tbar), _p(xf), _p(vf), 1 if at_tape_states else 0)
+                      ctypes.byref(loss), _p(g), _p(tbar), _p(xf), _p(vf), 1 if at_tape_states else 0,
+                      int(types.shape[0]), _p(types), _p(vtype))
     if rc != 0:
         raise OracleError("adj_eval failed: %d" % rc)
     return loss.value, (None if g is None else g.reshape(th.shape)), tbar, xf[:nveh], vf[:nveh]

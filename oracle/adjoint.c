@@ -49,15 +49,16 @@ typedef struct {
 } cst_t;
 
 typedef struct {
-    double a, T, kab, iv; /* per record: class parameters and 1/v0 of its link */
+    double a, T, kab, iv; /* per (link, vehicle type): class parameters and 1/v0 */
+    int capa, capv;       /* the type's acceleration / speed cap replaces a / v0_scale */
 } par_t;
 
 /* one motion, forward: returns dx, vn (before the crossing shift) and f */
 static void motion(const cst_t* K, const par_t* P, int fl, double len, double x, double v, double xL,
-                   double vL, double* dxo, double* vno, double* fo) {
+                   double vL, double lL, double* dxo, double* vno, double* fo) {
     double s = 0.0;
     if (fl & TF_HAS_LEAD)
-        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
+        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - lL) : (xL - lL) - x;
     double r = v * P->iv;
     double r2 = r * r;
     double fr = 1.0 - r2 * r2;
@@ -93,12 +94,12 @@ static void motion(const cst_t* K, const par_t* P, int fl, double len, double x,
 /* one motion, reverse: given adjoints of dx (gdx), vn (gvn) and f (gf),
  * accumulate adjoints of x, v, xL, vL and of (a, T, kab, iv). */
 static void motion_rev(const cst_t* K, const par_t* P, int fl, double len, double x, double v, double xL,
-                       double vL, double gdx, double gvn, double gf, double* gx, double* gv, double* gxL,
-                       double* gvL, double* ga, double* gT, double* gkab, double* giv) {
+                       double vL, double lL, double gdx, double gvn, double gf, double* gx, double* gv,
+                       double* gxL, double* gvL, double* ga, double* gT, double* gkab, double* giv) {
     /* recompute the forward intermediates */
     double s = 0.0;
     if (fl & TF_HAS_LEAD)
-        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - K->lveh) : (xL - K->lveh) - x;
+        s = (fl & TF_VIRTUAL) ? len - x : (fl & TF_LEAD_CROSS) ? (len - x) + (xL - lL) : (xL - lL) - x;
     double r = v * P->iv;
     double r2 = r * r;
     double fr = 1.0 - r2 * r2;
@@ -182,7 +183,8 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
              const int32_t* flags, const int32_t* edge, const double* x0, const double* v0, int32_t nveh,
              int32_t ne, const double* len, const double* speed, const int32_t* cls, int32_t ncls,
              const double* theta, const double* fp, const double* target, const uint8_t* mask, double* loss,
-             double* grad, double* tbar, double* xfin, double* vfin, int32_t at_tape_states) {
+             double* grad, double* tbar, double* xfin, double* vfin, int32_t at_tape_states, int32_t nt,
+             const double* types, const int32_t* vtype) {
     cst_t K;
     K.dt = fp[0];
     K.h = 0.5 * fp[0] * fp[0];
@@ -209,14 +211,23 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
     double* tr_T = (double*)malloc(sizeof(double) * (nrec + 1));
     for (int32_t i = 0; i < nveh; ++i) { where[i] = -1; phsrc[i] = -1; }
 
-    par_t* P = (par_t*)malloc(sizeof(par_t) * (ne + 1));
+    /* per (link, type): a vehicle type (Sec. 6.3.5) caps a and v0 = v0_scale * speed */
+    par_t* P = (par_t*)malloc(sizeof(par_t) * ((size_t)ne * nt + 1));
     for (int32_t e = 0; e < ne; ++e) {
         const double* th = theta + 4 * cls[e];
-        P[e].a = th[2];
-        P[e].T = th[1];
-        P[e].kab = 1.0 / (2.0 * sqrt(th[2] * th[3]));
-        P[e].iv = 1.0 / (th[0] * speed[e]);
+        for (int32_t k = 0; k < nt; ++k) {
+            par_t* q = &P[(size_t)e * nt + k];
+            const double amax = types[3 * k + 1], vmax = types[3 * k + 2], v0 = th[0] * speed[e];
+            q->capa = !(th[2] < amax);
+            q->capv = !(v0 < vmax);
+            q->a = q->capa ? amax : th[2];
+            q->T = th[1];
+            q->kab = 1.0 / (2.0 * sqrt(q->a * th[3]));
+            q->iv = 1.0 / (q->capv ? vmax : v0);
+        }
     }
+#define PAR(e, i) (&P[(size_t)(e) * nt + vtype[i]])
+#define LLEN(k) (rlead[k] >= 0 ? types[3 * vtype[lead[k]]] : 0.0)
 
     /* ---------------- forward replay ---------------- */
     int64_t r = 0;
@@ -253,7 +264,7 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
             double xL = 0.0, vL = 0.0;
             if (rlead[k] >= 0) { xL = rx[rlead[k]]; vL = rv[rlead[k]]; }
             double dx, vn, f;
-            motion(&K, &P[e], flags[k], len[e], rx[k], rv[k], xL, vL, &dx, &vn, &f);
+            motion(&K, PAR(e, i), flags[k], len[e], rx[k], rv[k], xL, vL, LLEN(k), &dx, &vn, &f);
             nx[k] = rx[k] + dx;
             nv[k] = vn;
             if (mode[k] == TM_CROSS || mode[k] == TM_ARRIVE) {
@@ -314,10 +325,11 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
         double* gfsrc = (double*)calloc(nrec + 1, sizeof(double)); /* adjoint of f at each crossing record */
         double* ngx = (double*)calloc(nrec + 1, sizeof(double));
         double* ngv = (double*)calloc(nrec + 1, sizeof(double));
-        double* ga = (double*)calloc(ne + 1, sizeof(double));
-        double* gTT = (double*)calloc(ne + 1, sizeof(double));
-        double* gkab = (double*)calloc(ne + 1, sizeof(double));
-        double* giv = (double*)calloc(ne + 1, sizeof(double));
+        const size_t npar = (size_t)ne * nt + 1;
+        double* ga = (double*)calloc(npar, sizeof(double));
+        double* gTT = (double*)calloc(npar, sizeof(double));
+        double* gkab = (double*)calloc(npar, sizeof(double));
+        double* giv = (double*)calloc(npar, sizeof(double));
         /* traversal adjoints: dT/df = dt, dT/dphin = -dt */
         int64_t e1 = nrec;
         while (e1 > 0) {
@@ -349,8 +361,9 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
                 double gxs = 0.0, gvs = 0.0, gxL = 0.0, gvL = 0.0;
                 /* x' = x + dx (- len): both x and dx get gxp */
                 gxs += gxp;
-                motion_rev(&K, &P[e], flags[k], len[e], rx[k], rv[k], xL, vL, gxp, gvp, gf, &gxs, &gvs, &gxL, &gvL,
-                           &ga[e], &gTT[e], &gkab[e], &giv[e]);
+                const size_t pe = (size_t)e * nt + vtype[i];
+                motion_rev(&K, &P[pe], flags[k], len[e], rx[k], rv[k], xL, vL, LLEN(k), gxp, gvp, gf, &gxs, &gvs,
+                           &gxL, &gvL, &ga[pe], &gTT[pe], &gkab[pe], &giv[pe]);
                 ngx[k] += gxs;
                 ngv[k] += gvs;
                 if (rlead[k] >= 0) {
@@ -369,11 +382,14 @@ int adj_eval(int64_t nrec, const int32_t* step, const int32_t* vid, const int32_
         for (int32_t e = 0; e < ne; ++e) {
             int32_t c = cls[e];
             const double* th = theta + 4 * c;
-            double kab = P[e].kab;
-            grad[4 * c + 0] += giv[e] * (-P[e].iv / th[0]);
-            grad[4 * c + 1] += gTT[e];
-            grad[4 * c + 2] += ga[e] + gkab[e] * (-kab / (2.0 * th[2]));
-            grad[4 * c + 3] += gkab[e] * (-kab / (2.0 * th[3]));
+            for (int32_t k = 0; k < nt; ++k) {
+                const size_t pe = (size_t)e * nt + k;
+                double kab = P[pe].kab;
+                if (!P[pe].capv) grad[4 * c + 0] += giv[pe] * (-P[pe].iv / th[0]);
+                grad[4 * c + 1] += gTT[pe];
+                if (!P[pe].capa) grad[4 * c + 2] += ga[pe] + gkab[pe] * (-kab / (2.0 * th[2]));
+                grad[4 * c + 3] += gkab[pe] * (-kab / (2.0 * th[3]));
+            }
         }
         free(gx); free(gv); free(gfsrc); free(ngx); free(ngv); free(ga); free(gTT); free(gkab); free(giv);
     }

@@ -23,7 +23,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
-            "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_set_vehicle_types", "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -97,6 +97,8 @@ def library(path: str = LIB_PATH):
         lib.sim_tape_begin.restype = ctypes.c_int
         lib.sim_grad.argtypes = [P, P, P]
         lib.sim_grad.restype = ctypes.c_int
+        lib.sim_set_vehicle_types.argtypes = [P, i32, P, i32, P]
+        lib.sim_set_vehicle_types.restype = ctypes.c_int
         lib.sim_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
         lib.sim_set_control.restype = ctypes.c_int
         lib.sim_set_stream.argtypes = [P, P]
@@ -185,6 +187,8 @@ class Sim:
                              p.get("stop_speed", 0.5))
         d = scen["demand"]
         self.num_trips = int(d["depart_step"].size)
+        if p.get("vehicle_types") is not None or d.get("trip_type") is not None:
+            self.set_vehicle_types(p.get("vehicle_types", [[p["veh_length"], np.inf, np.inf]]), d.get("trip_type"))
         ix = d.get("init_x")
         with torch.cuda.device(device):
             rc = self.lib.sim_load_demand(
@@ -194,6 +198,14 @@ class Sim:
                 None if d.get("init_v") is None else arr(d["init_v"], np.float32),
                 None if d.get("init_lane") is None else arr(d["init_lane"], np.int32))
         self._check(rc)
+
+    def set_vehicle_types(self, types, trip_type=None):
+        """types: [[length, accel cap, speed cap], ...]; trip_type: per trip (input order)."""
+        import torch
+        vt = np.ascontiguousarray(types, np.float32).reshape(-1, 3)
+        tt = None if trip_type is None else np.ascontiguousarray(trip_type, np.uint8)
+        with torch.cuda.device(self.device):
+            self._check(self.lib.sim_set_vehicle_types(self.h, int(vt.shape[0]), _p(vt), self.num_trips, _p(tt)))
 
     def set_control(self, node_control, signal_green=20, stop_dist=3.0, stop_speed=0.5):
         """Stop signs (1) and signals (2) per node, 0 = uncontrolled."""

@@ -32,15 +32,16 @@ struct AdjState {
     const unsigned long long* cnt;  // traversals per link
     double* gpart;     // per-thread partial sums of dLoss/dtheta [threads][ncls*4]
     int ncls;
+    const unsigned char* vtype;  // vehicle type by vehicle id
 };
 
 // reverse of one applied motion (see the forward in step_kernels.h)
 __device__ void motion_rev(const Params& P, float A, float T, float kab, float iv, int fl, float len, float x,
-                           float v, float xL, float vL, float gdx, float gvn, float gf, float& gx, float& gv,
-                           float& gxL, float& gvL, float& ga, float& gT, float& gkab, float& giv) {
+                           float v, float xL, float vL, float lL, float gdx, float gvn, float gf, float& gx,
+                           float& gv, float& gxL, float& gvL, float& ga, float& gT, float& gkab, float& giv) {
     const bool lead = fl & kFHasLead;
     float s = 0.0f;
-    if (lead) s = (fl & kFVirtual) ? len - x : (fl & kFLeadCross) ? (len - x) + (xL - P.lveh) : (xL - P.lveh) - x;
+    if (lead) s = (fl & kFVirtual) ? len - x : (fl & kFLeadCross) ? (len - x) + (xL - lL) : (xL - lL) - x;
     float r = v * iv;
     float r2 = r * r;
     float fr = 1.0f - r2 * r2;
@@ -134,17 +135,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_own(Params P, Net net, Tape tp, 
             lead = mode == kModeChange ? tp.clead[i] : tp.lead[i];
             const float xL = lead >= 0 ? tp.x[lead] : 0.0f;
             const float vL = lead >= 0 ? tp.v[lead] : 0.0f;
+            const float lL = lead >= 0 ? P.tlen[a.vtype[tp.vid[lead]]] : 0.0f;
             const int c = net.cls[e];
-            const float A = net.cA[c], T = net.cT[c], kab = net.cKab[c], iv = net.inv_v0[e];
+            const int ty = a.vtype[vid], nt = P.nt;
+            const float A = net.cA[c * nt + ty], T = net.cT[c], kab = net.cKab[c * nt + ty];
+            const float iv = net.inv_v0[e * nt + ty];
             float ga = 0.0f, gT = 0.0f, gkab = 0.0f, giv = 0.0f;
             gx = gxp;  // x' = x + dx (- len)
-            motion_rev(P, A, T, kab, iv, fl, net.len[e], tp.x[i], tp.v[i], xL, vL, gxp, gvp, gf, gx, gv, gxL,
+            motion_rev(P, A, T, kab, iv, fl, net.len[e], tp.x[i], tp.v[i], xL, vL, lL, gxp, gvp, gf, gx, gv, gxL,
                        gvL, ga, gT, gkab, giv);
-            // theta = (v0_scale, T, a, b): iv = 1/(v0_scale*speed), kab = 1/(2 sqrt(ab))
+            // theta = (v0_scale, T, a, b): iv = 1/(v0_scale*speed), kab = 1/(2 sqrt(ab)); where the
+            // vehicle's type caps the speed or the acceleration, that parameter drops out
             const double vs = net.cVs[c], aa = A, bb = net.cB[c];
-            gp[4 * c + 0] += (double)giv * (-(double)iv / vs);
+            const bool capv = net.capV[e * nt + ty], capa = net.capA[c * nt + ty];
+            if (!capv) gp[4 * c + 0] += (double)giv * (-(double)iv / vs);
             gp[4 * c + 1] += (double)gT;
-            gp[4 * c + 2] += (double)ga + (double)gkab * (-(double)kab / (2.0 * aa));
+            if (!capa) gp[4 * c + 2] += (double)ga + (double)gkab * (-(double)kab / (2.0 * aa));
             gp[4 * c + 3] += (double)gkab * (-(double)kab / (2.0 * bb));
             if (lead < 0) {
                 gxL = 0.0f;

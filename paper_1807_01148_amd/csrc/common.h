@@ -41,6 +41,9 @@ struct Params {
     float stop_dist, stop_speed;  // a vehicle within stop_dist of a stop line at <= stop_speed is waiting
     long long dt_us;
     int lc_cool;
+    // vehicle types (Sec. 6.3.5): length and claim length (length + s0)
+    int nt;
+    float tlen[4], tclaim[4];
 };
 
 struct Net {
@@ -62,6 +65,11 @@ struct Net {
     const float* cKab;
     const float* cVs;  // v0 scale per class (adjoint chain rule)
     const float* cB;   // comfortable deceleration per class (adjoint chain rule)
+    // cA, cKab are [class * nt + type], inv_v0 [edge * nt + type]; a type's
+    // acceleration cap (capA) or speed cap (capV) cuts the dependence on the
+    // class parameter it replaces
+    const unsigned char* capA;
+    const unsigned char* capV;
 };
 
 struct Trips {
@@ -71,6 +79,7 @@ struct Trips {
     const int* rel_off;  // rel_off[t] = first vehicle id due at step >= t
     int rel_len;         // rel_off has rel_len + 1 entries
     const unsigned char* placed;
+    const unsigned char* vtype;  // per vehicle id
     int* depart_actual;
     int* arrive_step;
     float* fuel_total;  // per vehicle id, at arrival
@@ -90,6 +99,7 @@ struct Veh {
     int* vid;
     float* fuel;  // accumulated fuel (mL)
     float* co;    // accumulated CO (g)
+    unsigned char* ty;  // vehicle type
 };
 
 // Entries [lo, hi] of the sorted arrays are the vehicles of one lane, valid
@@ -176,6 +186,7 @@ struct Lead {
     float vl;  // speed of the vehicle ahead
     float xl;  // its position on its own link
     int idx;   // its entry index in the sorted arrays
+    float ll;  // its length
 };
 
 __device__ __forceinline__ int lead_flags(const Lead& L) {
@@ -259,8 +270,8 @@ __device__ __forceinline__ int clamp_to_leader(const Lead& L, float& dx, float& 
 
 __device__ __forceinline__ Lead relead(const Params& P, float len, const Lead& L, float xf) {
     Lead R = L;
-    if (L.kind == 1) R.s = (L.xl - P.lveh) - xf;
-    else if (L.kind == 2) R.s = (len - xf) + (L.xl - P.lveh);
+    if (L.kind == 1) R.s = (L.xl - L.ll) - xf;
+    else if (L.kind == 2) R.s = (len - xf) + (L.xl - L.ll);
     else if (L.kind == 3) R.s = len - xf;
     return R;
 }
@@ -344,7 +355,7 @@ __device__ __forceinline__ bool movement_held(const Params& P, const Net& net, c
 }
 
 __device__ __forceinline__ Lead stop_line_lead(float len, float x) {
-    Lead L = {3, len - x, 0.0f, len, -1};
+    Lead L = {3, len - x, 0.0f, len, -1, 0.0f};
     return L;
 }
 
@@ -353,9 +364,9 @@ __device__ __forceinline__ unsigned long long epoch_tag(unsigned epoch) {
     return (unsigned long long)(0xFFFFFFFFu - epoch) << 32;
 }
 
-__device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, float X, int& lo,
+__device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, int ty, float X, int& lo,
                                             int& hi) {
-    int a = (int)floorf(X - P.claim_len);
+    int a = (int)floorf(X - P.tclaim[ty]);
     int b = (int)floorf(X);
     int nc = net.ncell[edge];
     lo = a < 0 ? 0 : a;

@@ -37,9 +37,12 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const int e = in.edge[i];
     const int nx = in.next[i];
     const float len = net.len[e];
-    const float iv = net.inv_v0[e];
+    const int ty = in.ty[i];
+    const float lme = P.tlen[ty];  // own length
+    const int nt = P.nt;
+    const float iv = net.inv_v0[e * nt + ty];
     const int c = net.cls[e];
-    const float A = net.cA[c], T = net.cT[c], kab = net.cKab[c];
+    const float A = net.cA[c * nt + ty], T = net.cT[c], kab = net.cKab[c * nt + ty];
     const int lb = net.lane_base[e];
     const int l = k - lb;
 
@@ -47,10 +50,10 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // mapped lane of the next link of the route
     const int vid = in.vid[i];
     const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
-    Lead L = {0, 0.0f, 0.0f, 0.0f, -1};
+    Lead L = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
     if (i + 1 < N && in.key[i + 1] == k) {
         float xl = in.x[i + 1];
-        L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.s = (xl - P.lveh) - x; L.idx = i + 1;
+        L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.ll = P.tlen[in.ty[i + 1]]; L.s = (xl - L.ll) - x; L.idx = i + 1;
     } else if (held) {
         L = stop_line_lead(len, x);
     } else if (nx >= 0) {
@@ -59,7 +62,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         int j, jh;
         if (lane_range(s.lanes, k2, ep, j, jh)) {
             float xl = in.x[j];
-            L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.s = (len - x) + (xl - P.lveh); L.idx = j;
+            L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.ll = P.tlen[in.ty[j]]; L.s = (len - x) + (xl - L.ll); L.idx = j;
         }
     }
     int own_fl = lead_flags(L);
@@ -112,7 +115,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         int tl = l < nl2 - 1 ? l : nl2 - 1;
         float X = xs - len;
         int lo, hi;
-        claim_cells(P, net, nx, X, lo, hi);
+        claim_cells(P, net, nx, ty, X, lo, hi);
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
@@ -126,7 +129,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 
     // lane change: eligibility
     const int n = net.lanes[e];
-    if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < P.lveh) return;
+    if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
         int hn = net.head[e];
@@ -154,6 +157,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const bool hasF = i > 0 && in.key[i - 1] == k;
     const float xF = hasF ? in.x[i - 1] : 0.0f;
     const float vF = hasF ? in.v[i - 1] : 0.0f;
+    const int tyF = hasF ? in.ty[i - 1] : 0;
 
     int best = -1, best_fl = 0, best_lead = -1;
     float best_inc = 0.0f, best_X = 0.0f, best_v = 0.0f;
@@ -165,10 +169,10 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         int tlo, thi;
         const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
         int j = occ ? ub_x(in.x, tlo, thi + 1, x) : -1;
-        Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1};
+        Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
         if (occ && j <= thi) {
             float xl = in.x[j];
-            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.s = (xl - P.lveh) - x; Lt.idx = j;
+            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.ll = P.tlen[in.ty[j]]; Lt.s = (xl - Lt.ll) - x; Lt.idx = j;
         } else if (held) {
             Lt = stop_line_lead(len, x);
         } else if (nx >= 0) {
@@ -177,15 +181,17 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             int j2, j2h;
             if (lane_range(s.lanes, k2, ep, j2, j2h)) {
                 float xl = in.x[j2];
-                Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.s = (len - x) + (xl - P.lveh); Lt.idx = j2;
+                Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.ll = P.tlen[in.ty[j2]];
+                Lt.s = (len - x) + (xl - Lt.ll); Lt.idx = j2;
             }
         }
         const bool hasFt = occ && j - 1 >= tlo;
         const float xFt = hasFt ? in.x[j - 1] : 0.0f;
         const float vFt = hasFt ? in.v[j - 1] : 0.0f;
+        const int tyFt = hasFt ? in.ty[j - 1] : 0;
         // gap acceptance (Sec. 6.3.2)
         if (Lt.kind != 0 && Lt.s < P.s0) continue;
-        if (hasFt && ((x - P.lveh) - xFt) < P.s0) continue;
+        if (hasFt && ((x - lme) - xFt) < P.s0) continue;
         int tfl = lead_flags(Lt);
         const float at = idm_acc_fl(P, A, T, kab, iv, v, Lt, tfl);
         if (at < -P.bsafe) continue;
@@ -195,16 +201,17 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         const float Xt = x + dxt;
         if (Xt >= len) continue;
         float an = 0.0f, ant = 0.0f;
-        if (hasFt) {
-            an = idm_acc(P, A, T, kab, iv, vFt, relead(P, len, Lt, xFt));
-            Lead Li = {1, (x - P.lveh) - xFt, v, x, i};
-            ant = idm_acc(P, A, T, kab, iv, vFt, Li);
+        if (hasFt) {  // the lag follows with its own type's constants
+            const float Af = net.cA[c * nt + tyFt], kf = net.cKab[c * nt + tyFt], ivf = net.inv_v0[e * nt + tyFt];
+            an = idm_acc(P, Af, T, kf, ivf, vFt, relead(P, len, Lt, xFt));
+            Lead Li = {1, (x - lme) - xFt, v, x, i, lme};
+            ant = idm_acc(P, Af, T, kf, ivf, vFt, Li);
             if (ant < -P.bsafe) continue;
-            Lead none = {0, 0.0f, 0.0f, 0.0f, -1};
-            float afree = idm_acc(P, A, T, kab, iv, vFt, none);
+            Lead none = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
+            float afree = idm_acc(P, Af, T, kf, ivf, vFt, none);
             float dxF, vF2;
             kin_move(P, vFt, afree, dxF, vF2);
-            if (((Xt - P.lveh) - xFt) < dxF) continue;
+            if (((Xt - lme) - xFt) < dxF) continue;
         }
         float inc = 0.0f;
         if (!mand) {
@@ -212,9 +219,10 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             float d2 = hasFt ? (ant - an) : 0.0f;
             float d3 = 0.0f;
             if (hasF) {
-                Lead Lo = {1, (x - P.lveh) - xF, v, x, i};
-                float ao = idm_acc(P, A, T, kab, iv, vF, Lo);
-                float aot = idm_acc(P, A, T, kab, iv, vF, relead(P, len, L, xF));
+                const float Af = net.cA[c * nt + tyF], kf = net.cKab[c * nt + tyF], ivf = net.inv_v0[e * nt + tyF];
+                Lead Lo = {1, (x - lme) - xF, v, x, i, lme};
+                float ao = idm_acc(P, Af, T, kf, ivf, vF, Lo);
+                float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(P, len, L, xF));
                 d3 = aot - ao;
             }
             inc = d1 + P.pol * (d2 + d3);
@@ -232,7 +240,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             tp.clead[i] = best_lead;
         }
         int lo, hi;
-        claim_cells(P, net, e, best_X, lo, hi);
+        claim_cells(P, net, e, ty, best_X, lo, hi);
         push_claim(s, net, ctr, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
     }
 }
@@ -249,13 +257,14 @@ __device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, 
     float bsp = 0.0f;
     for (int l = 0; l < n0; ++l) {
         int jl, jh;
-        float sp = lane_range(s.lanes, lb + l, ep, jl, jh) ? (in.x[jl] - P.lveh) : len0;
+        float sp = lane_range(s.lanes, lb + l, ep, jl, jh) ? (in.x[jl] - P.tlen[in.ty[jl]]) : len0;
         if (best < 0 || sp > bsp) { best = l; bsp = sp; }
     }
-    if (bsp >= P.claim_len) {
+    const int ty = tr.vtype[vid];
+    if (bsp >= P.tclaim[ty]) {
         int lo, hi;
-        claim_cells(P, net, e0, P.lveh, lo, hi);
-        push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.lveh, 0.0f, 1.0f, lo, hi);
+        claim_cells(P, net, e0, ty, P.tlen[ty], lo, hi);
+        push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.tlen[ty], 0.0f, 1.0f, lo, hi);
     } else {
         pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
     }
@@ -492,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, S
             out.kin[j] = in.kin[i];
             out.phin[j] = in.phin[i];
             out.vid[j] = in.vid[i];
+            out.ty[j] = in.ty[i];
             float fu = in.fuel[i], co = in.co[i];
             emissions(P, in.v[i], s.vs[i], fu, co);
             out.fuel[j] = fu;
@@ -539,6 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
         out.v[j] = s.cl_v[ci];
         out.edge[j] = s.cl_tedge[ci];
         out.vid[j] = vid;
+        out.ty[j] = tr.vtype[vid];
         if (src >= 0) {
             float fu = in.fuel[src], co = in.co[src];
             emissions(P, in.v[src], s.cl_v[ci], fu, co);

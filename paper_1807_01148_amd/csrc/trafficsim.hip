@@ -59,7 +59,16 @@ struct sim_t {
     std::vector<void*> allocs;
 
     int nn = 0, ne = 0, nlanes = 0, ncls = 0;
-    std::vector<int> row_ptr, col_idx, lanes, cls, lane_base, ncell;
+    std::vector<int> row_ptr, col_idx, lanes, cls, lane_base, ncell, tail;
+    // vehicle types (Sec. 6.3.5): acceleration and speed caps per type, the
+    // car-following inputs the per-type constants derive from, trip types
+    std::vector<double> tamax{INFINITY}, tvmax{INFINITY};
+    std::vector<float> idm_in;
+    std::vector<unsigned char> trip_type;
+    bool typed = false;
+    unsigned char* d_capA = nullptr;
+    unsigned char* d_capV = nullptr;
+    unsigned char* d_vtype = nullptr;
     std::vector<float> len, speed;
     long long ncells = 0;
 
@@ -181,24 +190,42 @@ void release_all(sim_t* S) {
     S->allocs.clear();
 }
 
+// Per (class, type) and (link, type) constants in double, rounded once: a
+// type caps the class's maximum acceleration and the link's desired speed
+// (Sec. 6.3.5); with no cap (infinite) they are the class's own values.
 int upload_idm(sim_t* S, const float* idm) {
-    std::vector<float> T(S->ncls), A(S->ncls), K(S->ncls), VS(S->ncls), B(S->ncls), inv(S->ne);
-    for (int c = 0; c < S->ncls; ++c) {
+    const int nt = S->P.nt, nc = S->ncls;
+    std::vector<float> T(nc), A((size_t)nc * nt), K((size_t)nc * nt), VS(nc), B(nc), inv((size_t)S->ne * nt);
+    std::vector<unsigned char> capA((size_t)nc * nt), capV((size_t)S->ne * nt);
+    for (int c = 0; c < nc; ++c) {
         double s0 = idm[4 * c + 0], t = idm[4 * c + 1], a = idm[4 * c + 2], b = idm[4 * c + 3];
         if (!(s0 > 0) || !(t >= 0) || !(a > 0) || !(b > 0) || !std::isfinite(s0 * t * a * b))
             return fail(S, SIM_EINVAL, "idm parameters of class " + std::to_string(c) + " out of range");
         T[c] = (float)t;
-        A[c] = (float)a;
-        K[c] = (float)(1.0 / (2.0 * std::sqrt(a * b)));
         VS[c] = (float)s0;
         B[c] = (float)b;
+        for (int k = 0; k < nt; ++k) {
+            const double ak = a < S->tamax[k] ? a : S->tamax[k];
+            A[(size_t)c * nt + k] = (float)ak;
+            K[(size_t)c * nt + k] = (float)(1.0 / (2.0 * std::sqrt(ak * b)));
+            capA[(size_t)c * nt + k] = !(a < S->tamax[k]);
+        }
     }
-    for (int e = 0; e < S->ne; ++e)
-        inv[e] = (float)(1.0 / ((double)idm[4 * S->cls[e] + 0] * (double)S->speed[e]));
-    HIPCHECK(S, hipMemcpyAsync(S->d_cT, T.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->d_cA, A.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->d_cKab, K.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->d_inv_v0, inv.data(), sizeof(float) * S->ne, hipMemcpyHostToDevice, S->stream));
+    for (int e = 0; e < S->ne; ++e) {
+        const double v0 = (double)idm[4 * S->cls[e] + 0] * (double)S->speed[e];
+        for (int k = 0; k < nt; ++k) {
+            inv[(size_t)e * nt + k] = (float)(1.0 / (v0 < S->tvmax[k] ? v0 : S->tvmax[k]));
+            capV[(size_t)e * nt + k] = !(v0 < S->tvmax[k]);
+        }
+    }
+    S->idm_in.assign(idm, idm + 4 * (size_t)nc);
+    const hipMemcpyKind h = hipMemcpyHostToDevice;
+    HIPCHECK(S, hipMemcpyAsync(S->d_cT, T.data(), sizeof(float) * nc, h, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_cA, A.data(), sizeof(float) * A.size(), h, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_cKab, K.data(), sizeof(float) * K.size(), h, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_inv_v0, inv.data(), sizeof(float) * inv.size(), h, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_capA, capA.data(), capA.size(), h, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_capV, capV.data(), capV.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_cVs, VS.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_cB, B.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipStreamSynchronize(S->stream));
@@ -212,11 +239,7 @@ int h2d(sim_t* S, T* dst, const T* src, size_t n) {
     return SIM_OK;
 }
 
-int32_t tail_node(const sim_t* S, int32_t e) {
-    // largest u with row_ptr[u] <= e
-    auto it = std::upper_bound(S->row_ptr.begin(), S->row_ptr.end(), e);
-    return (int32_t)(it - S->row_ptr.begin()) - 1;
-}
+int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
 
 
 int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, const Scratch& sc, const Tape& tp,
@@ -250,7 +273,8 @@ int reindex(sim_t* S, const Veh& buf, const Scratch& sc, Counters* ctr) {
 bool alloc_veh(sim_t* S, Veh& V, size_t n) {
     return dalloc(S, V.key, n) && dalloc(S, V.x, n) && dalloc(S, V.v, n) && dalloc(S, V.edge, n) &&
            dalloc(S, V.rcur, n) && dalloc(S, V.next, n) && dalloc(S, V.lc, n) && dalloc(S, V.kin, n) &&
-           dalloc(S, V.phin, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) && dalloc(S, V.co, n);
+           dalloc(S, V.phin, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) && dalloc(S, V.co, n) &&
+           dalloc(S, V.ty, n);
 }
 
 int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, const Veh& sv, const int* spend,
@@ -269,6 +293,7 @@ int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, 
     HIPCHECK(S, hipMemcpyAsync(dv.vid, sv.vid, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.fuel, sv.fuel, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.co, sv.co, sizeof(float) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dv.ty, sv.ty, n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dpend, spend, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dctr, sctr, sizeof(Counters), k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dhold, shold, sizeof(int) * (size_t)S->nn, k, S->stream));
@@ -385,6 +410,9 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     if (net->link_class) S->cls.assign(net->link_class, net->link_class + ne);
     S->lane_base.resize(ne + 1);
     S->ncell.resize(ne);
+    S->tail.resize(ne);
+    for (int u = 0; u < nn; ++u)
+        for (int e = S->row_ptr[u]; e < S->row_ptr[u + 1]; ++e) S->tail[e] = u;
     std::vector<long long> cbase(ne);
     S->lane_base[0] = 0;
     long long cells = 0;
@@ -421,14 +449,19 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     P.dt_us_f = (float)((double)prm->dt * 1e6);
     P.lc_cool = prm->lc_cooldown_steps;
     P.mph = (float)(1.0 / 0.44704);
+    P.nt = 1;
+    P.tlen[0] = P.lveh;
+    P.tclaim[0] = P.claim_len;
 
     float *d_len, *dummy;
     int *d_lane_base, *d_lanes, *d_cls, *d_head, *d_row_ptr, *d_ncell;
     long long* d_cbase;
-    bool ok = dalloc(S, d_len, ne) && dalloc(S, S->d_inv_v0, ne) && dalloc(S, d_lane_base, ne + 1) &&
+    // per-type constants are sized for the largest number of vehicle types (4)
+    bool ok = dalloc(S, d_len, ne) && dalloc(S, S->d_inv_v0, 4 * (size_t)ne) && dalloc(S, d_lane_base, ne + 1) &&
               dalloc(S, d_lanes, ne) && dalloc(S, d_cls, ne) && dalloc(S, d_head, ne) &&
               dalloc(S, d_row_ptr, nn + 1) && dalloc(S, d_cbase, ne) && dalloc(S, d_ncell, ne) &&
-              dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, ncls) && dalloc(S, S->d_cKab, ncls) &&
+              dalloc(S, S->d_capA, 4 * (size_t)ncls) && dalloc(S, S->d_capV, 4 * (size_t)ne) &&
+              dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, 4 * (size_t)ncls) && dalloc(S, S->d_cKab, 4 * (size_t)ncls) &&
               dalloc(S, S->d_cVs, ncls) && dalloc(S, S->d_cB, ncls) && dalloc(S, S->d_epoch, 1) &&
               dalloc(S, S->s.lanes, (size_t)S->nlanes) &&
               dalloc(S, S->s.cells, (size_t)cells) && dalloc(S, S->s.st_cnt, ne) &&
@@ -494,6 +527,8 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     N.cKab = S->d_cKab;
     N.cVs = S->d_cVs;
     N.cB = S->d_cB;
+    N.capA = S->d_capA;
+    N.capV = S->d_capV;
     N.ne = ne;
     S->s.epoch = S->d_epoch;
     *out = S;
@@ -534,9 +569,13 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<int> ord(ntrips);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return depart_step[a] < depart_step[b]; });
+    if (S->typed && !S->trip_type.empty() && (int)S->trip_type.size() != ntrips)
+        return fail(S, SIM_EINVAL, "vehicle types were given for a different number of trips");
     std::vector<int> rbeg(ntrips), rend(ntrips), dep(ntrips);
+    std::vector<unsigned char> vtype(std::max(ntrips, 1), 0);
     for (int v = 0; v < ntrips; ++v) {
         int i = ord[v];
+        if (!S->trip_type.empty()) vtype[v] = S->trip_type[i];
         rbeg[v] = (int)route_ptr[trip_route[i]];
         rend[v] = (int)route_ptr[trip_route[i] + 1];
         dep[v] = depart_step[i];
@@ -553,6 +592,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<unsigned char> placed(ntrips, init_x ? 1 : 0);
     // placed vehicles: validated, then sorted by (lane, position)
     std::vector<int> pkey, pedge, prcur, pnext, plc, pkin, pvid;
+    std::vector<unsigned char> pty;
     std::vector<float> px, pv, pphin;
     if (init_x) {
         std::vector<int> idx(ntrips);
@@ -575,7 +615,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
         });
         for (int q = 0; q + 1 < ntrips; ++q) {
             int a = idx[q], b = idx[q + 1];
-            if (key[a] == key[b] && ((init_x[ord[b]] - S->P.lveh) - init_x[ord[a]]) < 0.0f)
+            if (key[a] == key[b] && ((init_x[ord[b]] - S->P.tlen[vtype[b]]) - init_x[ord[a]]) < 0.0f)
                 return fail(S, SIM_EINVAL, "placed vehicles overlap");
         }
         for (int q = 0; q < ntrips; ++q) {
@@ -590,6 +630,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
             pkin.push_back(t0);
             pphin.push_back(1.0f);
             pvid.push_back(v);
+            pty.push_back(vtype[v]);
         }
     }
 
@@ -604,13 +645,13 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
               dalloc(S, d_rel, rel_len + 1) && dalloc(S, d_placed, cap) &&
               dalloc(S, S->tr.depart_actual, cap) && dalloc(S, S->tr.arrive_step, cap) &&
               dalloc(S, S->tr.fuel_total, cap) && dalloc(S, S->tr.co_total, cap) &&
-              dalloc(S, S->pend[0], cap) && dalloc(S, S->pend[1], cap);
+              dalloc(S, S->pend[0], cap) && dalloc(S, S->pend[1], cap) && dalloc(S, S->d_vtype, cap);
     for (int b = 0; b < 2 && ok; ++b) {
         Veh& V = S->buf[b];
         ok = dalloc(S, V.key, cap) && dalloc(S, V.x, cap) && dalloc(S, V.v, cap) && dalloc(S, V.edge, cap) &&
              dalloc(S, V.rcur, cap) && dalloc(S, V.next, cap) && dalloc(S, V.lc, cap) &&
              dalloc(S, V.kin, cap) && dalloc(S, V.phin, cap) && dalloc(S, V.vid, cap) &&
-             dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap);
+             dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap) && dalloc(S, V.ty, cap);
     }
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
     ok = ok && dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
@@ -626,7 +667,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<int> minus1(cap, -1);
     if ((rc = h2d(S, d_re, route_edges, (size_t)nre)) || (rc = h2d(S, d_rbeg, rbeg.data(), ntrips)) ||
         (rc = h2d(S, d_rend, rend.data(), ntrips)) || (rc = h2d(S, d_rel, rel.data(), rel_len + 1)) ||
-        (rc = h2d(S, d_placed, placed.data(), ntrips)) ||
+        (rc = h2d(S, d_placed, placed.data(), ntrips)) || (rc = h2d(S, S->d_vtype, vtype.data(), ntrips)) ||
         (rc = h2d(S, S->tr.arrive_step, minus1.data(), cap)))
         return rc;
     std::vector<int> da(cap, init_x ? t0 : -1);
@@ -648,7 +689,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
             (rc = h2d(S, V.v, pv.data(), np)) || (rc = h2d(S, V.edge, pedge.data(), np)) ||
             (rc = h2d(S, V.rcur, prcur.data(), np)) || (rc = h2d(S, V.next, pnext.data(), np)) ||
             (rc = h2d(S, V.lc, plc.data(), np)) || (rc = h2d(S, V.kin, pkin.data(), np)) ||
-            (rc = h2d(S, V.phin, pphin.data(), np)) || (rc = h2d(S, V.vid, pvid.data(), np)))
+            (rc = h2d(S, V.phin, pphin.data(), np)) || (rc = h2d(S, V.vid, pvid.data(), np)) ||
+            (rc = h2d(S, V.ty, pty.data(), np)))
             return rc;
     }
     Counters c0{};
@@ -663,6 +705,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     S->tr.rel_off = d_rel;
     S->tr.rel_len = rel_len;
     S->tr.placed = d_placed;
+    S->tr.vtype = S->d_vtype;
     S->h_rbeg = rbeg;
     S->grid = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)cap + kBlock - 1) / kBlock));
     S->grid_small = std::max(1, S->grid / 4);
@@ -743,6 +786,7 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
     rs.st_us = S->sink + 2 * (size_t)S->ne;
     rs.holder = S->d_rholder;  // stop-node admissions replay on their own copy
     AdjState a = S->adj;
+    a.vtype = S->tr.vtype;
     a.dLdT = dL_dmeanTT;
     a.cnt = S->s.st_cnt;
     float *L0x = S->L0x, *L0v = S->L0v, *L1x = S->L1x, *L1v = S->L1v;
@@ -901,6 +945,38 @@ int sim_read_samples(sim_t* S, int64_t* count, int64_t* speed_um) {
 int sim_set_idm(sim_t* S, const float* idm) {
     if (!S || !idm) return SIM_EINVAL;
     return upload_idm(S, idm);
+}
+
+int sim_set_vehicle_types(sim_t* S, int32_t num_types, const float* types, int32_t num_trips,
+                          const uint8_t* trip_type) {
+    if (!S || !types || num_types < 1 || num_types > 4 || num_trips < 0) return SIM_EINVAL;
+    if (S->loaded) return fail(S, SIM_ESTATE, "vehicle types are set before the demand is loaded");
+    for (int k = 0; k < num_types; ++k) {
+        const float len = types[3 * k], am = types[3 * k + 1], vm = types[3 * k + 2];
+        if (!(len > 0) || !std::isfinite(len) || !(am > 0) || !(vm > 0))
+            return fail(S, SIM_EINVAL, "vehicle type " + std::to_string(k) + " out of range");
+        for (int e = 0; e < S->ne; ++e)
+            if (!((double)S->len[e] >= (double)len + (double)S->P.s0))
+                return fail(S, SIM_EINVAL, "link " + std::to_string(e) + " is shorter than type " +
+                                               std::to_string(k) + " plus the minimum gap");
+    }
+    for (int i = 0; i < num_trips; ++i)
+        if (trip_type && trip_type[i] >= num_types) return fail(S, SIM_EINVAL, "trip type out of range");
+    S->P.nt = num_types;
+    S->tamax.assign(num_types, 0.0);
+    S->tvmax.assign(num_types, 0.0);
+    for (int k = 0; k < num_types; ++k) {
+        S->P.tlen[k] = types[3 * k];
+        S->P.tclaim[k] = (float)((double)types[3 * k] + (double)S->P.s0);
+        S->tamax[k] = (double)types[3 * k + 1];
+        S->tvmax[k] = (double)types[3 * k + 2];
+    }
+    S->trip_type.clear();
+    if (trip_type) S->trip_type.assign(trip_type, trip_type + num_trips);
+    S->typed = true;
+    drop_graphs(S);
+    const std::vector<float> idm = S->idm_in;
+    return upload_idm(S, idm.data());
 }
 
 int sim_set_control(sim_t* S, const int32_t* node_control, int32_t signal_green_steps, float stop_dist,

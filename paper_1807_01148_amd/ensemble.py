@@ -168,6 +168,17 @@ class Ensemble(Sim):
                                    if sc["net"].get("node_control") is not None
                                    else np.zeros(sc["net"]["row_ptr"].size - 1, np.int32) for sc in scens])
             self.set_control(ctrl, *ctl[0])
+        if any(sc["params"].get("vehicle_types") is not None or sc["demand"].get("trip_type") is not None
+               for sc in scens):
+            # one type table for the batch; trip types concatenated in scenario order
+            tabs = [np.asarray(sc["params"].get("vehicle_types", [[sc["params"]["veh_length"], np.inf, np.inf]]),
+                               np.float32) for sc in scens]
+            if any(t.shape != tabs[0].shape or not np.array_equal(t, tabs[0]) for t in tabs):
+                raise ValueError("ensemble members must share their vehicle types")
+            tt = np.concatenate([np.asarray(sc["demand"]["trip_type"], np.uint8)
+                                 if sc["demand"].get("trip_type") is not None
+                                 else np.zeros(sc["demand"]["depart_step"].size, np.uint8) for sc in scens])
+            self.set_vehicle_types(tabs[0], tt)
         PP = ctypes.c_void_p * n
         dem = [sc["demand"] for sc in scens]
         ntr = np.array([d["depart_step"].size for d in dem], np.int32)
