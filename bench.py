@@ -62,7 +62,7 @@ def cpu_baseline(seconds_budget=20.0):
     import scenarios as S
     net = S.metro()
     net.pop("xy", None)
-    scen = S.placed_snapshot(net, 1_000_000, seed=11)
+    scen = S.placed_snapshot(net, 1_000_000, seed=11, route_len=40)
     o = oracle.Oracle(scen, "f32")
     steps = 0
     t0 = time.perf_counter()
@@ -70,7 +70,7 @@ def cpu_baseline(seconds_budget=20.0):
         o.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds_budget or steps >= 5000:
+        if el > seconds_budget or steps >= 2000:
             break
     upd = o.counters()["vehicle_updates"]
     return {"value": upd / el, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",

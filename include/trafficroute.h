@@ -88,8 +88,14 @@ int rt_tree(rt_t* rt, int32_t src_node, int64_t* dist, int32_t* pred);
 int rt_last_work(rt_t* rt, int64_t* relaxations, int32_t* sources);
 
 /* Largest number of origins searched at once (default: as many as fit in
- * 12 bytes x nodes x count <= 4 GiB).  Errors: SIM_EINVAL. */
+ * 32 bytes x nodes x count <= 4 GiB).  Errors: SIM_EINVAL. */
 int rt_set_batch(rt_t* rt, int32_t sources_per_batch);
+
+/* Band width of the search in ms (the search relaxes labels below a threshold
+ * first and raises the threshold by this much when none are left; the
+ * result does not depend on it, the work does).  0 = three times the mean
+ * weight (default).  Errors: SIM_EINVAL. */
+int rt_set_delta(rt_t* rt, int64_t delta_ms);
 
 int rt_set_stream(rt_t* rt, void* hip_stream);
 const char* rt_last_error(const rt_t* rt);

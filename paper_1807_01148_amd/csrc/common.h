@@ -373,11 +373,25 @@ __device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int
     hi = b > nc - 1 ? nc - 1 : b;
 }
 
+// A slot in a list filled through one shared counter: the lanes of a wave
+// that reach this point together take consecutive slots with a single atomic
+// (the order of the slots carries no meaning anywhere in the step).
+__device__ __forceinline__ int wave_slot(int* counter) {
+    const unsigned long long mask = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, kWave);
+    return base + rank;
+}
+
 __device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Counters* ctr,
                                            unsigned long long tag, int vid, int kind, int src,
                                            int tedge, int tlane, float X, float vc, float f, int lo,
                                            int hi) {
-    int ci = atomicAdd(&ctr->nclaim, 1);
+    const int ci = wave_slot(&ctr->nclaim);
     s.cl_vid[ci] = vid;
     s.cl_key[ci] = net.lane_base[tedge] + tlane;
     s.cl_lo[ci] = lo;

@@ -12,6 +12,13 @@
 // round before (a per-label round stamp keeps each label at most once in a
 // frontier).  Integer weights make the result exact and order-free.
 //
+// To keep the work near that of Dijkstra the rounds are banded (a near/far
+// split of delta-stepping): a label that drops below the current threshold T
+// joins the next round's frontier, one that drops to T or more waits in a far
+// list; when the frontier runs dry T grows by delta and the far labels below
+// it form the next frontier.  Any order of relaxations ends at the same
+// labels, so the banding changes the work, never the result.
+//
 // Routes of the selected trips are read back from the predecessor arrays of
 // their origins (count, scan, write from the destination backwards); the
 // other trips' routes are copied.
@@ -34,17 +41,31 @@ constexpr unsigned long long kEdgeMask = (1ull << kEdgeBits) - 1ull;  // also "n
 constexpr unsigned long long kUnreached = ~0ull;
 constexpr int kMaxGrid = 8192;
 constexpr int kScanTile = 2048;  // entries per block in the route-length scan
-constexpr int kRoundsPerCheck = 16;
+constexpr int kRoundsPerCheck = 4;
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
 
-__global__ void k_fill_keys(unsigned long long* key, unsigned* stamp, long long n) {
+// consecutive slots for the lanes of a wave that reach this point together,
+// with one atomic on the shared counter
+__device__ __forceinline__ unsigned wave_slot(unsigned* counter) {
+    const unsigned long long mask = __ballot(1);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    const unsigned rank = (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(mask));
+    base = __shfl(base, leader, kWave);
+    return base + rank;
+}
+
+__global__ void k_fill_keys(unsigned long long* key, unsigned* stamp, unsigned* fstamp, long long n) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
         key[i] = kUnreached;
         stamp[i] = 0u;
+        fstamp[i] = 0u;
     }
 }
 
@@ -68,10 +89,14 @@ __global__ void k_seed(unsigned long long* key, const int* origins, int B, long 
 // labels that drop join fout (count cnt[(r + 1) % 3]), each at most once per
 // round by its stamp r + 1; cnt[(r + 2) % 3], the input count of round
 // r - 1, is cleared for round r + 1
+// Labels that drop to thr or more go to the far list instead (each at most
+// once per band, by its far stamp = the band number).
 __global__ __launch_bounds__(kBlock) void k_relax(const int* __restrict__ row_ptr, const int* __restrict__ col,
                                                   const long long* __restrict__ w, unsigned long long* key,
                                                   unsigned* stamp, long long nn, const unsigned* __restrict__ fin,
-                                                  unsigned* fout, unsigned* cnt, int r, unsigned long long* work) {
+                                                  unsigned* fout, unsigned* cnt, int r, unsigned long long* work,
+                                                  unsigned long long thr, unsigned* fstamp, unsigned band,
+                                                  unsigned* far, unsigned* nfar) {
     const unsigned nin = cnt[r % 3];
     unsigned* nout = cnt + (r + 1) % 3;
     const unsigned mark = (unsigned)r + 1u;
@@ -87,13 +112,36 @@ __global__ __launch_bounds__(kBlock) void k_relax(const int* __restrict__ row_pt
             const unsigned long long x = base + (unsigned long long)col[e];
             const unsigned long long nd = d + (unsigned long long)w[e];
             const unsigned long long old = atomicMin(key + x, (nd << kEdgeBits) | (unsigned long long)e);
-            if (nd < (old >> kEdgeBits) && atomicExch(stamp + x, mark) != mark)
-                fout[atomicAdd(nout, 1u)] = (unsigned)x;
+            if (nd < (old >> kEdgeBits)) {
+                if (nd < thr) {
+                    if (atomicExch(stamp + x, mark) != mark) fout[wave_slot(nout)] = (unsigned)x;
+                } else if (atomicExch(fstamp + x, band) != band) {
+                    far[wave_slot(nfar)] = (unsigned)x;
+                }
+            }
         }
         done += (unsigned long long)(e1 - row_ptr[u]);
     }
     done = wave_sum(done);
     if ((threadIdx.x & (kWave - 1)) == 0 && done) atomicAdd(work, done);
+}
+
+// A new band [.., thr): far labels below thr form the frontier of round r
+// (stamp r, as if pushed by round r - 1); the others stay far, stamped with
+// the new band.  Stale entries (labels that dropped again since) are harmless.
+__global__ void k_split(const unsigned long long* key, unsigned* stamp, unsigned* fstamp, const unsigned* far_in,
+                        const unsigned* nfar_in, unsigned long long thr, unsigned band, unsigned* fr, unsigned* cnt,
+                        int r, unsigned* far_out, unsigned* nfar_out) {
+    const unsigned n = *nfar_in;
+    unsigned* nnear = cnt + r % 3;
+    for (unsigned q = blockIdx.x * kBlock + threadIdx.x; q < n; q += gridDim.x * kBlock) {
+        const unsigned i = far_in[q];
+        if ((key[i] >> kEdgeBits) < thr) {
+            if (atomicExch(stamp + i, (unsigned)r) != (unsigned)r) fr[wave_slot(nnear)] = i;
+        } else if (atomicExch(fstamp + i, band) != band) {
+            far_out[wave_slot(nfar_out)] = i;
+        }
+    }
 }
 
 // predecessor edge per node of each origin of the batch (-1: origin, unreached)
@@ -279,7 +327,7 @@ struct rt_t {
     long long* d_w = nullptr;
     unsigned long long* d_u64 = nullptr;  // [0] relaxations, [1] weight sum
     unsigned* d_err = nullptr;
-    unsigned* d_cnt = nullptr;  // three frontier counters
+    unsigned* d_cnt = nullptr;  // three rotating frontier counters, two far-list counters
 
     // trips
     int nsrc = 0, ntrips = 0;
@@ -303,7 +351,11 @@ struct rt_t {
     int batch_alloc = 0;
     unsigned long long* d_key = nullptr;
     unsigned* d_stamp = nullptr;
+    unsigned* d_fstamp = nullptr;
     unsigned* d_fr[2] = {nullptr, nullptr};
+    unsigned* d_far[2] = {nullptr, nullptr};
+    long long delta = 0;  // band width in ms; 0 = three times the mean weight
+    long long wsum = 0;   // sum of the weights (checked before every search)
     int* d_origins = nullptr;
 
     long long last_relax = 0;
@@ -367,8 +419,8 @@ int grid_for(long long n) {
 }
 
 int auto_batch(const rt_t* R) {
-    // key (8 B) + stamp (4 B) + two frontier entries (8 B) per (origin, node)
-    const long long per = 20ll * R->nn;
+    // key (8 B) + two stamps (8 B) + two frontier and two far entries (16 B) per (origin, node)
+    const long long per = 32ll * R->nn;
     long long b = (4ll << 30) / std::max<long long>(per, 1);
     b = std::min<long long>(b, (long long)(UINT32_MAX / (unsigned long long)R->nn));
     return (int)std::max<long long>(1, std::min<long long>(b, 1024));
@@ -376,19 +428,18 @@ int auto_batch(const rt_t* R) {
 
 int ensure_batch(rt_t* R, int B) {
     if (B <= R->batch_alloc) return SIM_OK;
-    rfree(R, R->d_key);
-    rfree(R, R->d_stamp);
-    rfree(R, R->d_fr[0]);
-    rfree(R, R->d_fr[1]);
+    for (void* p : {(void*)R->d_key, (void*)R->d_stamp, (void*)R->d_fstamp, (void*)R->d_fr[0], (void*)R->d_fr[1],
+                    (void*)R->d_far[0], (void*)R->d_far[1]})
+        rfree(R, p);
     rfree(R, R->d_origins);
     R->d_key = nullptr;
-    R->d_stamp = nullptr;
-    R->d_fr[0] = R->d_fr[1] = nullptr;
+    R->d_stamp = R->d_fstamp = nullptr;
+    R->d_fr[0] = R->d_fr[1] = R->d_far[0] = R->d_far[1] = nullptr;
     R->d_origins = nullptr;
     R->batch_alloc = 0;
     const size_t n = (size_t)B * (size_t)R->nn;
-    if (!ra(R, R->d_key, n) || !ra(R, R->d_stamp, n) || !ra(R, R->d_fr[0], n) || !ra(R, R->d_fr[1], n) ||
-        !ra(R, R->d_origins, (size_t)B))
+    if (!ra(R, R->d_key, n) || !ra(R, R->d_stamp, n) || !ra(R, R->d_fstamp, n) || !ra(R, R->d_fr[0], n) ||
+        !ra(R, R->d_fr[1], n) || !ra(R, R->d_far[0], n) || !ra(R, R->d_far[1], n) || !ra(R, R->d_origins, (size_t)B))
         return rfail(R, SIM_ENOMEM, "search batch of " + std::to_string(B) + " origins does not fit");
     R->batch_alloc = B;
     return SIM_OK;
@@ -400,27 +451,45 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
     if (rc) return rc;
     const long long n = (long long)B * R->nn;
     if ((rc = rh2d(R, R->d_origins, origins, (size_t)B))) return rc;
-    hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n)), dim3(kBlock), 0, R->stream, R->d_key, R->d_stamp, n);
+    hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n)), dim3(kBlock), 0, R->stream, R->d_key, R->d_stamp,
+                       R->d_fstamp, n);
+    RCHECK(R, hipMemsetAsync(R->d_cnt, 0, 5 * sizeof(unsigned), R->stream));
     hipLaunchKernelGGL(k_seed, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, R->stream, R->d_key, R->d_origins,
                        B, (long long)R->nn, R->d_fr[0], R->d_cnt);
     RCHECK(R, hipMemsetAsync(R->d_u64, 0, sizeof(unsigned long long), R->stream));
     RCHECK(R, hipGetLastError());
-    // frontiers shrink to nothing within nn rounds (each round that leaves a
-    // label lower extends a simple path by one edge)
+    const long long delta = R->delta > 0 ? R->delta : std::max<long long>(1, 3 * R->wsum / std::max(R->ne, 1));
+    unsigned long long thr = (unsigned long long)delta;
+    unsigned band = 1;
     const int g = grid_for(n);
     int r = 0;
+    long long launched = 0;
     for (;;) {
-        for (int k = 0; k < kRoundsPerCheck; ++k, ++r) {
-            hipLaunchKernelGGL(k_relax, dim3(g), dim3(kBlock), 0, R->stream, R->d_row_ptr, R->d_col, R->d_w,
-                               R->d_key, R->d_stamp, (long long)R->nn, R->d_fr[r & 1], R->d_fr[(r + 1) & 1],
-                               R->d_cnt, r, R->d_u64);
+        // rounds of the current band until its frontier runs dry
+        unsigned c[5];
+        for (;;) {
+            for (int k = 0; k < kRoundsPerCheck; ++k, ++r) {
+                hipLaunchKernelGGL(k_relax, dim3(g), dim3(kBlock), 0, R->stream, R->d_row_ptr, R->d_col, R->d_w,
+                                   R->d_key, R->d_stamp, (long long)R->nn, R->d_fr[r & 1], R->d_fr[(r + 1) & 1],
+                                   R->d_cnt, r, R->d_u64, thr, R->d_fstamp, band, R->d_far[band & 1],
+                                   R->d_cnt + 3 + (band & 1));
+            }
+            RCHECK(R, hipGetLastError());
+            RCHECK(R, hipMemcpyAsync(c, R->d_cnt, sizeof(c), hipMemcpyDeviceToHost, R->stream));
+            RCHECK(R, hipStreamSynchronize(R->stream));
+            launched += kRoundsPerCheck;
+            if (c[r % 3] == 0) break;  // the frontier the next round would read
+            if (launched > 64ll * R->nn + 1024) return rfail(R, SIM_EHIP, "search did not converge");
         }
+        if (c[3 + (band & 1)] == 0) break;  // nothing waits: every label is final
+        // next band: far labels below the new threshold start the next round
+        RCHECK(R, hipMemsetAsync(R->d_cnt + 3 + ((band + 1) & 1), 0, sizeof(unsigned), R->stream));
+        thr += (unsigned long long)delta;
+        hipLaunchKernelGGL(k_split, dim3(grid_for(c[3 + (band & 1)])), dim3(kBlock), 0, R->stream, R->d_key,
+                           R->d_stamp, R->d_fstamp, R->d_far[band & 1], R->d_cnt + 3 + (band & 1), thr, band + 1,
+                           R->d_fr[r & 1], R->d_cnt, r, R->d_far[(band + 1) & 1], R->d_cnt + 3 + ((band + 1) & 1));
         RCHECK(R, hipGetLastError());
-        unsigned c[3];
-        RCHECK(R, hipMemcpyAsync(c, R->d_cnt, sizeof(c), hipMemcpyDeviceToHost, R->stream));
-        RCHECK(R, hipStreamSynchronize(R->stream));
-        if (c[r % 3] == 0) break;  // the frontier the next round would read
-        if (r > R->nn + kRoundsPerCheck) return rfail(R, SIM_EHIP, "search did not converge");
+        ++band;
     }
     unsigned long long w = 0;
     RCHECK(R, hipMemcpyAsync(&w, R->d_u64, sizeof(w), hipMemcpyDeviceToHost, R->stream));
@@ -437,6 +506,7 @@ int check_weight_sum(rt_t* R) {
     RCHECK(R, hipMemcpyAsync(&s, R->d_u64 + 1, sizeof(s), hipMemcpyDeviceToHost, R->stream));
     RCHECK(R, hipStreamSynchronize(R->stream));
     if (s >= (1ull << (64 - kEdgeBits))) return rfail(R, SIM_EINVAL, "weights sum to 2^40 ms or more");
+    R->wsum = (long long)s;
     return SIM_OK;
 }
 
@@ -476,7 +546,7 @@ int rt_create(const sim_network* net, void* hip_stream, sim_alloc_fn alloc, sim_
         for (int e = R->row_ptr[u]; e < R->row_ptr[u + 1]; ++e) tail[e] = u;
     int rc = SIM_OK;
     if (!ra(R, R->d_row_ptr, nn + 1) || !ra(R, R->d_col, ne) || !ra(R, R->d_tail, ne) || !ra(R, R->d_w, ne) ||
-        !ra(R, R->d_u64, 2) || !ra(R, R->d_err, 1) || !ra(R, R->d_cnt, 3))
+        !ra(R, R->d_u64, 2) || !ra(R, R->d_err, 1) || !ra(R, R->d_cnt, 5))
         rc = SIM_ENOMEM;
     if (rc == SIM_OK && ((rc = rh2d(R, R->d_row_ptr, R->row_ptr.data(), nn + 1)) ||
                          (rc = rh2d(R, R->d_col, R->col_idx.data(), ne)) || (rc = rh2d(R, R->d_tail, tail.data(), ne))))
@@ -698,6 +768,12 @@ int rt_set_batch(rt_t* R, int32_t sources_per_batch) {
     if (sources_per_batch > 0 && (unsigned long long)sources_per_batch * (unsigned long long)R->nn > UINT32_MAX)
         return rfail(R, SIM_EINVAL, "batch x nodes must stay below 2^32");
     R->batch = sources_per_batch;
+    return SIM_OK;
+}
+
+int rt_set_delta(rt_t* R, int64_t delta_ms) {
+    if (!R || delta_ms < 0) return SIM_EINVAL;
+    R->delta = delta_ms;
     return SIM_OK;
 }
 

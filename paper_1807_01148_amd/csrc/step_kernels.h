@@ -266,7 +266,7 @@ __device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, 
         claim_cells(P, net, e0, ty, P.tlen[ty], lo, hi);
         push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.tlen[ty], 0.0f, 1.0f, lo, hi);
     } else {
-        pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
+        pend_out[wave_slot(&ctr->npend_next)] = vid;
     }
 }
 
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
         }
         if (win) {
             if (src >= 0) s.stay[src] = 0;
-            int m = atomicAdd(&ctr->nmove, 1);
+            const int m = wave_slot(&ctr->nmove);
             s.mv_claim[m] = ci;
             // its gap in the sorted order: inside its lane's run if the lane is
             // occupied, else before the first entry of a later lane
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
             }
         } else {
             lost += 1;
-            if (kind == kInsert) pend_out[atomicAdd(&ctr->npend_next, 1)] = vid;
+            if (kind == kInsert) pend_out[wave_slot(&ctr->npend_next)] = vid;
         }
     }
     unsigned long long lw = wave_sum_u64((unsigned long long)lost);

@@ -47,6 +47,8 @@ def _bind(lib):
     lib.rt_last_work.restype = ctypes.c_int
     lib.rt_set_batch.argtypes = [P, i32]
     lib.rt_set_batch.restype = ctypes.c_int
+    lib.rt_set_delta.argtypes = [P, ctypes.c_int64]
+    lib.rt_set_delta.restype = ctypes.c_int
     lib.rt_set_stream.argtypes = [P, P]
     lib.rt_set_stream.restype = ctypes.c_int
     lib.rt_last_error.argtypes = [P]
@@ -150,6 +152,9 @@ class Router:
         r, s = ctypes.c_int64(0), ctypes.c_int32(0)
         self._check(self.lib.rt_last_work(self.h, ctypes.byref(r), ctypes.byref(s)))
         return int(r.value), int(s.value)
+
+    def set_delta(self, delta_ms: int):
+        self._check(self.lib.rt_set_delta(self.h, int(delta_ms)))
 
     def set_batch(self, n: int):
         self._check(self.lib.rt_set_batch(self.h, int(n)))

@@ -160,3 +160,23 @@ def test_errors():
         rt.set_weights(np.zeros(net["col_idx"].size, np.int64))
     assert e.value.code == P.SIM_EINVAL
     assert rt.plan() == 2 * d["trip_src"].size
+
+
+@pytest.mark.parametrize("delta", [500, 20000, 10 ** 9])
+def test_band_width_changes_work_not_result(delta):
+    scen = S.small_grid()
+    net, d = scen["net"], scen["demand"]
+    rng = np.random.default_rng(12)
+    w = rng.integers(1000, 60000, net["col_idx"].size).astype(np.int64)
+    rt = router(net)
+    rt.set_weights(w)
+    rt.set_delta(delta)
+    rt.set_trips(d["src_nodes"], d["trip_src"], d["trip_dst"])
+    rt.plan()
+    ptr, edges = rt.routes()
+    optr, oedges = R.plan(net, w, d["src_nodes"], d["trip_src"], d["trip_dst"])
+    assert np.array_equal(ptr, optr) and np.array_equal(edges, oedges)
+    for s in (0, 42):
+        dg, pg = rt.tree(s)
+        do, po = R.sssp(net, w, s)
+        assert np.array_equal(dg, do) and np.array_equal(pg, po)
