@@ -457,6 +457,7 @@ def main():
     sim.set_timing(0)
     upd = c1["vehicle_updates"] - c0["vehicle_updates"]
     claims = c1["claims"] - c0["claims"]
+    claims_veh = claims - (c1["claims_departure"] - c0["claims_departure"])
     secs = ev_ms / 1000.0
     value = upd / secs
     log("[bench] %d steps in %.3f s (wall %.3f s), %d vehicle-updates, final en_route %d arrived %d"
@@ -465,7 +466,8 @@ def main():
     avg = {k: (v / samples if samples else 0.0) for k, v in kms.items()}
     dom = max(avg, key=avg.get)
     per_launch_units = upd / args.steps
-    per_launch_claims = claims / args.steps
+    # k_decide advances the vehicles; its events are their crossing and lane-change claims
+    per_launch_claims = claims_veh / args.steps
     alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
     achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     step_achieved = (B_PER_VEH * upd + B_PER_EVENT * claims) / secs / 1e9

@@ -86,7 +86,11 @@ typedef struct {
 typedef struct {
     int64_t step, loaded, waiting, en_route, arrived, departed;
     int64_t vehicle_updates, claims_lost, clamps;
-    int64_t claims; /* claims issued (crossings, lane changes, insertions) */
+    int64_t claims; /* claims issued (crossings, lane changes, departures) */
+    int64_t claims_departure; /* of which departures: of several trips waiting to
+                               * enter one link by the same lane, only the one with
+                               * the lowest id can win; the others are counted
+                               * (here and in claims_lost) without a claim record */
 } sim_stats_t;
 
 /* Create a simulation of `net` with `params` on `hip_stream` (a hipStream_t,
@@ -204,9 +208,9 @@ int sim_set_control(sim_t* sim, const int32_t* node_control, int32_t signal_gree
 
 /* Per-kernel timing with HIP events on the handle's stream: when every > 0,
  * every `every`-th subsequent step records an event before and after each of
- * its SIM_NUM_KERNELS kernel launches (decide, resolve, scan, scatter, place, lanes);
- * 0 disables.  Timing adds no synchronisation to sim_step. */
-#define SIM_NUM_KERNELS 6
+ * its SIM_NUM_KERNELS kernel launches (decide, insert, resolve, scan, scatter,
+ * place, lanes); 0 disables.  Timing adds no synchronisation to sim_step. */
+#define SIM_NUM_KERNELS 7
 int sim_set_timing(sim_t* sim, int32_t every);
 
 /* Synchronise, then add the elapsed milliseconds of every sampled launch to

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtrafficsim.so")
+# the in-tree build; TRAFFICSIM_LIB names another build of the same library
+LIB_PATH = os.environ.get("TRAFFICSIM_LIB") or os.path.join(_HERE, "libtrafficsim.so")
 _LIB = None
 
 SIM_OK, SIM_EINVAL, SIM_EROUTE, SIM_ENOMEM, SIM_EHIP, SIM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -24,7 +25,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
-KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
+KERNELS = ("k_decide", "k_insert", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 class SimError(RuntimeError):
@@ -53,7 +54,8 @@ class SimParams(ctypes.Structure):
 
 class SimStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("step", "loaded", "waiting", "en_route", "arrived", "departed",
-                                              "vehicle_updates", "claims_lost", "clamps", "claims")]
+                                              "vehicle_updates", "claims_lost", "clamps", "claims",
+                                              "claims_departure")]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)

@@ -23,15 +23,16 @@ enum : int { kCross = 1, kChange = 2, kInsert = 3 };
 struct Counters {
     int t;           // current step
     int n;           // vehicles on the road (entries of the current buffer)
-    int npend;       // carried insertion candidates (current pending buffer)
+    int nghost;      // departure claims that lose for certain, counted without an entry
     int nclaim;      // claims this step
     int nmove;       // winning claims this step
-    int npend_next;  // candidates carried to the next step
+    int pad1;
     int n_next;      // entries of the next buffer
     unsigned scan_tile;
     unsigned epoch_next;  // epoch of the next step (set during the step, committed at its end)
     int pad;
     unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
+    unsigned long long claims_dep;  // of which departures (those counted without an entry included)
 };
 
 struct Params {
@@ -46,7 +47,28 @@ struct Params {
     float tlen[4], tclaim[4];
 };
 
+// Packed per-link records for the step's hot path (one 16-byte load each
+// instead of a chain of dependent gathers); the plain arrays below hold the
+// same values for the other kernels.
+struct __align__(16) EdgeRec {
+    float len;
+    int lane_base;
+    int lanes;
+    int r0;  // first out-link of the head node
+};
+struct __align__(16) DrvRec {  // per (link, vehicle type)
+    float iv, A, T, kab;       // 1/v0, acceleration, time gap, 1/(2 sqrt(ab))
+};
+struct __align__(16) ClaimRec {
+    long long cbase;  // first claim cell of lane 0
+    int ncell;        // cells per lane
+    int m;            // out-degree of the head node
+};
+
 struct Net {
+    const EdgeRec* er;
+    const DrvRec* drv;
+    const ClaimRec* cr;
     const float* len;
     const float* inv_v0;
     const int* lane_base;
@@ -78,8 +100,19 @@ struct Trips {
     const int* rend;
     const int* rel_off;  // rel_off[t] = first vehicle id due at step >= t
     int rel_len;         // rel_off has rel_len + 1 entries
-    const unsigned char* placed;
     const unsigned char* vtype;  // per vehicle id
+    // Departure queues: the trips of one (first link, type), by vehicle id,
+    // which is also their order of departure steps.  Queue q holds entries
+    // [qoff[q], qoff[q+1]) of qvid / qdep; qtail[q] of them are due so far and
+    // the first qhead[q] have entered the road.
+    int nq;
+    const int* qoff;
+    const int* qvid;
+    const int* qdep;
+    const int* qedge;
+    const unsigned char* qtype;
+    int* qhead;
+    int* qtail;
     int* depart_actual;
     int* arrive_step;
     float* fuel_total;  // per vehicle id, at arrival
@@ -104,17 +137,33 @@ struct Veh {
 
 // Entries [lo, hi] of the sorted arrays are the vehicles of one lane, valid
 // when ep equals the current step's epoch (so the table is never cleared).
-struct LaneIx {
+// The rearmost vehicle's type, position and speed ride along, so a vehicle
+// that looks ahead into the next link reads one record instead of four.
+struct __align__(32) LaneIx {
     unsigned ep;
     int lo;
     int hi;
-    int pad;
+    int ty;   // rearmost vehicle (entry lo): type,
+    float x;  // position
+    float v;  // and speed
+    int pad0, pad1;
 };
 
 __device__ __forceinline__ bool lane_range(const LaneIx* __restrict__ lanes, int key, unsigned ep, int& lo, int& hi) {
     const int4 w = *reinterpret_cast<const int4*>(lanes + key);
     lo = w.y;
     hi = w.z;
+    return (unsigned)w.x == ep;
+}
+
+__device__ __forceinline__ bool lane_rear(const LaneIx* __restrict__ lanes, int key, unsigned ep, int& lo,
+                                          float& x, float& v, int& ty) {
+    const int4 w = *reinterpret_cast<const int4*>(lanes + key);
+    const float4 r = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(lanes + key) + 16);
+    lo = w.y;
+    ty = w.w;
+    x = r.x;
+    v = r.y;
     return (unsigned)w.x == ep;
 }
 
@@ -368,7 +417,7 @@ __device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int
                                             int& hi) {
     int a = (int)floorf(X - P.tclaim[ty]);
     int b = (int)floorf(X);
-    int nc = net.ncell[edge];
+    int nc = net.cr[edge].ncell;
     lo = a < 0 ? 0 : a;
     hi = b > nc - 1 ? nc - 1 : b;
 }
@@ -393,7 +442,8 @@ __device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Cou
                                            int hi) {
     const int ci = wave_slot(&ctr->nclaim);
     s.cl_vid[ci] = vid;
-    s.cl_key[ci] = net.lane_base[tedge] + tlane;
+    const ClaimRec C = net.cr[tedge];
+    s.cl_key[ci] = net.er[tedge].lane_base + tlane;
     s.cl_lo[ci] = lo;
     s.cl_hi[ci] = hi;
     s.cl_src[ci] = src;
@@ -402,7 +452,7 @@ __device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Cou
     s.cl_X[ci] = X;
     s.cl_v[ci] = vc;
     s.cl_f[ci] = f;
-    unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tlane * net.ncell[tedge];
+    unsigned long long* cell = s.cells + C.cbase + (long long)tlane * C.ncell;
     unsigned long long mine = tag | (unsigned)vid;
     for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
 }

@@ -36,14 +36,14 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const float v = in.v[i];
     const int e = in.edge[i];
     const int nx = in.next[i];
-    const float len = net.len[e];
+    const EdgeRec E = net.er[e];
+    const float len = E.len;
     const int ty = in.ty[i];
     const float lme = P.tlen[ty];  // own length
     const int nt = P.nt;
-    const float iv = net.inv_v0[e * nt + ty];
-    const int c = net.cls[e];
-    const float A = net.cA[c * nt + ty], T = net.cT[c], kab = net.cKab[c * nt + ty];
-    const int lb = net.lane_base[e];
+    const DrvRec D = net.drv[e * nt + ty];
+    const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
+    const int lb = E.lane_base;
     const int l = k - lb;
 
     // own leader: next element of the lane, else the rearmost vehicle of the
@@ -57,12 +57,13 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     } else if (held) {
         L = stop_line_lead(len, x);
     } else if (nx >= 0) {
-        int nl2 = net.lanes[nx];
-        int k2 = net.lane_base[nx] + (l < nl2 - 1 ? l : nl2 - 1);
-        int j, jh;
-        if (lane_range(s.lanes, k2, ep, j, jh)) {
-            float xl = in.x[j];
-            L.kind = 2; L.xl = xl; L.vl = in.v[j]; L.ll = P.tlen[in.ty[j]]; L.s = (len - x) + (xl - L.ll); L.idx = j;
+        const EdgeRec E2 = net.er[nx];
+        int nl2 = E2.lanes;
+        int k2 = E2.lane_base + (l < nl2 - 1 ? l : nl2 - 1);
+        int j, tyr;
+        float xl, vr;
+        if (lane_rear(s.lanes, k2, ep, j, xl, vr, tyr)) {
+            L.kind = 2; L.xl = xl; L.vl = vr; L.ll = P.tlen[tyr]; L.s = (len - x) + (xl - L.ll); L.idx = j;
         }
     }
     int own_fl = lead_flags(L);
@@ -111,7 +112,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             arrivals += 1;
             return;
         }
-        int nl2 = net.lanes[nx];
+        int nl2 = net.er[nx].lanes;
         int tl = l < nl2 - 1 ? l : nl2 - 1;
         float X = xs - len;
         int lo, hi;
@@ -128,13 +129,12 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     if (tp.on) tp.flags[i] = (unsigned short)own_fl;
 
     // lane change: eligibility
-    const int n = net.lanes[e];
+    const int n = E.lanes;
     if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
-        int hn = net.head[e];
-        int r0 = net.row_ptr[hn];
-        int m = net.row_ptr[hn + 1] - r0;
+        const int r0 = E.r0;
+        const int m = net.cr[e].m;
         int j = nx - r0;
         blo = (j * n) / m;
         bhi = ((j + 1) * n + m - 1) / m - 1;
@@ -176,12 +176,13 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         } else if (held) {
             Lt = stop_line_lead(len, x);
         } else if (nx >= 0) {
-            int nl2 = net.lanes[nx];
-            int k2 = net.lane_base[nx] + (lt < nl2 - 1 ? lt : nl2 - 1);
-            int j2, j2h;
-            if (lane_range(s.lanes, k2, ep, j2, j2h)) {
-                float xl = in.x[j2];
-                Lt.kind = 2; Lt.xl = xl; Lt.vl = in.v[j2]; Lt.ll = P.tlen[in.ty[j2]];
+            const EdgeRec E2 = net.er[nx];
+            int nl2 = E2.lanes;
+            int k2 = E2.lane_base + (lt < nl2 - 1 ? lt : nl2 - 1);
+            int j2, tyr;
+            float xl, vr;
+            if (lane_rear(s.lanes, k2, ep, j2, xl, vr, tyr)) {
+                Lt.kind = 2; Lt.xl = xl; Lt.vl = vr; Lt.ll = P.tlen[tyr];
                 Lt.s = (len - x) + (xl - Lt.ll); Lt.idx = j2;
             }
         }
@@ -202,7 +203,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         if (Xt >= len) continue;
         float an = 0.0f, ant = 0.0f;
         if (hasFt) {  // the lag follows with its own type's constants
-            const float Af = net.cA[c * nt + tyFt], kf = net.cKab[c * nt + tyFt], ivf = net.inv_v0[e * nt + tyFt];
+            const DrvRec Df = net.drv[e * nt + tyFt];
+            const float Af = Df.A, kf = Df.kab, ivf = Df.iv;
             an = idm_acc(P, Af, T, kf, ivf, vFt, relead(P, len, Lt, xFt));
             Lead Li = {1, (x - lme) - xFt, v, x, i, lme};
             ant = idm_acc(P, Af, T, kf, ivf, vFt, Li);
@@ -219,7 +221,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             float d2 = hasFt ? (ant - an) : 0.0f;
             float d3 = 0.0f;
             if (hasF) {
-                const float Af = net.cA[c * nt + tyF], kf = net.cKab[c * nt + tyF], ivf = net.inv_v0[e * nt + tyF];
+                const DrvRec Df = net.drv[e * nt + tyF];
+                const float Af = Df.A, kf = Df.kab, ivf = Df.iv;
                 Lead Lo = {1, (x - lme) - xF, v, x, i, lme};
                 float ao = idm_acc(P, Af, T, kf, ivf, vF, Lo);
                 float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(P, len, L, xF));
@@ -245,56 +248,52 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     }
 }
 
-__device__ void decide_insert(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                              const Scratch& s, Counters* ctr, int* pend_out, unsigned ep,
-                              unsigned long long tag, int vid) {
-    if (tr.placed[vid]) return;
-    const int e0 = tr.route_edges[tr.rbeg[vid]];
-    const int n0 = net.lanes[e0];
-    const int lb = net.lane_base[e0];
-    const float len0 = net.len[e0];
+// Departures (Sec. 6.2.2): a due trip enters the first link of its route in
+// the lane with the most entry space, if that space holds its length plus s0,
+// by claiming the entry cells; losers wait and try again every step.  Every
+// trip of one queue (same first link, same type) sees the same lane and the
+// same space, and all their claims cover cell 0 of that lane, so only the
+// queue's head (its lowest vehicle id) can win, and its claim blocks every
+// third claim any other member's would.  The head claims; the others are
+// counted as claims that lost.
+__device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, const Scratch& s, Counters* ctr,
+                             unsigned ep, unsigned long long tag, int t, int q, int& ghost, int& issued) {
+    const int q0 = tr.qoff[q], qn = tr.qoff[q + 1] - q0;
+    const int h = tr.qhead[q];
+    int tl = tr.qtail[q];
+    while (tl < qn && tr.qdep[q0 + tl] <= t) ++tl;  // release the trips due now
+    tr.qtail[q] = tl;
+    if (h == tl) return;  // nobody waiting
+    const int e0 = tr.qedge[q];
+    const int ty = tr.qtype[q];
+    const EdgeRec E0 = net.er[e0];
     int best = -1;
     float bsp = 0.0f;
-    for (int l = 0; l < n0; ++l) {
-        int jl, jh;
-        float sp = lane_range(s.lanes, lb + l, ep, jl, jh) ? (in.x[jl] - P.tlen[in.ty[jl]]) : len0;
+    for (int l = 0; l < E0.lanes; ++l) {
+        int jl, tyr;
+        float xr, vr;
+        float sp = lane_rear(s.lanes, E0.lane_base + l, ep, jl, xr, vr, tyr) ? (xr - P.tlen[tyr]) : E0.len;
         if (best < 0 || sp > bsp) { best = l; bsp = sp; }
     }
-    const int ty = tr.vtype[vid];
     if (bsp >= P.tclaim[ty]) {
         int lo, hi;
         claim_cells(P, net, e0, ty, P.tlen[ty], lo, hi);
-        push_claim(s, net, ctr, tag, vid, kInsert, -1, e0, best, P.tlen[ty], 0.0f, 1.0f, lo, hi);
-    } else {
-        pend_out[wave_slot(&ctr->npend_next)] = vid;
+        push_claim(s, net, ctr, tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best, P.tlen[ty], 0.0f, 1.0f, lo, hi);
+        ghost += tl - h - 1;
+        issued += tl - h;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                                   const int* __restrict__ pend_in, int* pend_out,
                                                    Counters* ctr) {
     const int t = ctr->t;
     const int N = ctr->n;
-    const int np = ctr->npend;
-    int rlo = 0, rhi = 0;
-    if (t < tr.rel_len) {
-        rlo = tr.rel_off[t];
-        rhi = tr.rel_off[t + 1];
-    }
-    const int total = N + np + (rhi - rlo);
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
     int clamps = 0, arrivals = 0;
     if (tp.on && blockIdx.x == 0 && threadIdx.x == 0) *tp.n = N;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-        if (i < N) {
-            decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals);
-        } else {
-            int cidx = i - N;
-            int vid = cidx < np ? pend_in[cidx] : rlo + (cidx - np);
-            decide_insert(P, net, tr, in, s, ctr, pend_out, ep, tag, vid);
-        }
-    }
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
+        decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals);
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
@@ -304,11 +303,30 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
     }
 }
 
+// departures: one thread per queue
+__global__ __launch_bounds__(kBlock) void k_insert(Params P, Net net, Trips tr, Scratch s, Counters* ctr) {
+    const int t = ctr->t;
+    const unsigned ep = *s.epoch;
+    const unsigned long long tag = epoch_tag(ep);
+    int ghost = 0, issued = 0;
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < tr.nq; q += gridDim.x * kBlock)
+        decide_queue(P, net, tr, s, ctr, ep, tag, t, q, ghost, issued);
+    const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
+    const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (gw) {
+            atomicAdd(&ctr->nghost, (int)gw);
+            atomicAdd(&ctr->claims_lost, gw);
+        }
+        if (iw) atomicAdd(&ctr->claims_dep, iw);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_resolve
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                                    int* pend_out, Counters* ctr) {
+                                                    Counters* ctr) {
     const int t = ctr->t;
     const int N = ctr->n;
     const int C = ctr->nclaim;
@@ -323,8 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
         const int vid = s.cl_vid[ci];
         const int tedge = s.cl_tedge[ci];
         const int key = s.cl_key[ci];
-        const int tl = key - net.lane_base[tedge];
-        const unsigned long long* cell = s.cells + net.cbase[tedge] + (long long)tl * net.ncell[tedge];
+        const int tl = key - net.er[tedge].lane_base;
+        const ClaimRec C = net.cr[tedge];
+        const unsigned long long* cell = s.cells + C.cbase + (long long)tl * C.ncell;
         const unsigned long long mine = tag | (unsigned)vid;
         bool win = true;
         for (int c = s.cl_lo[ci]; c <= s.cl_hi[ci]; ++c) {
@@ -356,11 +375,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
             }
             if (kind == kInsert) {
                 tr.depart_actual[vid] = t + 1;
+                tr.qhead[-2 - src] += 1;  // the queue's head has left (one winner per queue)
                 departed += 1;
             }
         } else {
-            lost += 1;
-            if (kind == kInsert) pend_out[wave_slot(&ctr->npend_next)] = vid;
+            lost += 1;  // a losing departure simply stays at its queue's head
         }
     }
     unsigned long long lw = wave_sum_u64((unsigned long long)lost);
@@ -605,6 +624,9 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
         }
         if (j == 0 || buf.key[j - 1] != k) {
             s.lanes[k].lo = j;
+            s.lanes[k].ty = buf.ty[j];
+            s.lanes[k].x = buf.x[j];
+            s.lanes[k].v = buf.v[j];
             s.lanes[k].ep = ep;
         }
         if (j == N - 1 || buf.key[j + 1] != k) s.lanes[k].hi = j;
@@ -613,8 +635,8 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
         ctr->updates += (unsigned long long)ctr->n;
         ctr->claims += (unsigned long long)ctr->nclaim;
         ctr->n = ctr->n_next;
-        ctr->npend = ctr->npend_next;
-        ctr->npend_next = 0;
+        ctr->claims += (unsigned long long)ctr->nghost;
+        ctr->nghost = 0;
         ctr->nclaim = 0;
         ctr->nmove = 0;
         ctr->t = ctr->t + 1;

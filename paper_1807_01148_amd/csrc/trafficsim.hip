@@ -66,6 +66,7 @@ struct sim_t {
     std::vector<float> idm_in;
     std::vector<unsigned char> trip_type;
     bool typed = false;
+    DrvRec* d_drv = nullptr;
     unsigned char* d_capA = nullptr;
     unsigned char* d_capV = nullptr;
     unsigned char* d_vtype = nullptr;
@@ -77,7 +78,7 @@ struct sim_t {
     Trips tr{};
     Veh buf[2]{};
     Scratch s{};
-    int* pend[2]{nullptr, nullptr};
+    int* qstate = nullptr;  // departure queues: heads [0, nq), then tails [nq, 2 nq)
     Counters* ctr = nullptr;
     float* d_inv_v0 = nullptr;
     float* d_cT = nullptr;
@@ -98,6 +99,7 @@ struct sim_t {
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
     int grid_small = 1;  // kernels that work on claims and movers (a few % of the vehicles)
+    int grid_q = 1;      // the departure kernel: one thread per queue
     std::vector<int> h_rbeg;
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
@@ -107,7 +109,7 @@ struct sim_t {
     struct Ckpt {
         long long t = 0;
         Veh v{};
-        int* pend = nullptr;
+        int* qstate = nullptr;
         Counters* ctr = nullptr;
         int* holder = nullptr;
     };
@@ -119,7 +121,7 @@ struct sim_t {
     // recompute state and adjoint work arrays (allocated at the first sim_grad)
     bool adj_ready = false;
     Veh rbuf[2]{};
-    int* rpend[2]{nullptr, nullptr};
+    int* rqstate = nullptr;  // queue heads and tails of the recompute pass
     Counters* rctr = nullptr;
     Tape slab{};  // tape_every slices of cap entries
     AdjState adj{};
@@ -225,6 +227,13 @@ int upload_idm(sim_t* S, const float* idm) {
     HIPCHECK(S, hipMemcpyAsync(S->d_cKab, K.data(), sizeof(float) * K.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_inv_v0, inv.data(), sizeof(float) * inv.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_capA, capA.data(), capA.size(), h, S->stream));
+    std::vector<DrvRec> drv((size_t)S->ne * nt);
+    for (int e = 0; e < S->ne; ++e)
+        for (int k = 0; k < nt; ++k) {
+            const size_t ck = (size_t)S->cls[e] * nt + k;
+            drv[(size_t)e * nt + k] = DrvRec{inv[(size_t)e * nt + k], A[ck], T[S->cls[e]], K[ck]};
+        }
+    HIPCHECK(S, hipMemcpyAsync(S->d_drv, drv.data(), sizeof(DrvRec) * drv.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_capV, capV.data(), capV.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_cVs, VS.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_cB, B.data(), sizeof(float) * S->ncls, hipMemcpyHostToDevice, S->stream));
@@ -242,22 +251,24 @@ int h2d(sim_t* S, T* dst, const T* src, size_t n) {
 int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
 
 
-int launch_step(sim_t* S, const Veh& in, const Veh& out, int* pin, int* pout, const Scratch& sc, const Tape& tp,
+int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
-    hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pin, pout, ctr);
+    hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
-    hipLaunchKernelGGL(k_resolve, gs, b, 0, S->stream, S->P, S->net, S->tr, in, sc, tp, pout, ctr);
+    hipLaunchKernelGGL(k_insert, dim3(S->grid_q), b, 0, S->stream, S->P, S->net, tr, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-    hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
+    hipLaunchKernelGGL(k_resolve, gs, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
-    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
+    hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
-    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->P, S->tr, in, out, sc, tp, kLcNone, ctr);
+    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
+    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
+    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
+    if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
@@ -277,7 +288,7 @@ bool alloc_veh(sim_t* S, Veh& V, size_t n) {
            dalloc(S, V.ty, n);
 }
 
-int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, const Veh& sv, const int* spend,
+int copy_state(sim_t* S, const Veh& dv, int* dq, Counters* dctr, int* dhold, const Veh& sv, const int* sq,
                const Counters* sctr, const int* shold) {
     const size_t n = (size_t)S->cap;
     const hipMemcpyKind k = hipMemcpyDeviceToDevice;
@@ -294,7 +305,7 @@ int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, 
     HIPCHECK(S, hipMemcpyAsync(dv.fuel, sv.fuel, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.co, sv.co, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.ty, sv.ty, n, k, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(dpend, spend, sizeof(int) * n, k, S->stream));
+    if (S->tr.nq) HIPCHECK(S, hipMemcpyAsync(dq, sq, sizeof(int) * 2 * (size_t)S->tr.nq, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dctr, sctr, sizeof(Counters), k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dhold, shold, sizeof(int) * (size_t)S->nn, k, S->stream));
     return SIM_OK;
@@ -303,14 +314,14 @@ int copy_state(sim_t* S, const Veh& dv, int* dpend, Counters* dctr, int* dhold, 
 int take_checkpoint(sim_t* S, int p) {
     if (S->nckpt == S->ckpt_pool.size()) {
         sim_t::Ckpt ck;
-        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.pend, S->cap) || !dalloc(S, ck.ctr, 1) ||
+        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.qstate, 2 * (size_t)S->tr.nq) || !dalloc(S, ck.ctr, 1) ||
             !dalloc(S, ck.holder, S->nn))
             return fail(S, SIM_ENOMEM, "checkpoint allocation failed");
         S->ckpt_pool.push_back(ck);
     }
     sim_t::Ckpt& ck = S->ckpt_pool[S->nckpt++];
     ck.t = S->host_t;
-    return copy_state(S, ck.v, ck.pend, ck.ctr, ck.holder, S->buf[p], S->pend[p], S->ctr, S->s.holder);
+    return copy_state(S, ck.v, ck.qstate, ck.ctr, ck.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
 }
 
 Tape slice(sim_t* S, int k) {
@@ -343,8 +354,8 @@ int alloc_adjoint(sim_t* S) {
     AdjState& a = S->adj;
     S->adj_grid = S->grid;
     const size_t nthreads = (size_t)S->adj_grid * kBlock;
-    bool ok = alloc_veh(S, S->rbuf[0], cap) && alloc_veh(S, S->rbuf[1], cap) && dalloc(S, S->rpend[0], cap) &&
-              dalloc(S, S->rpend[1], cap) && dalloc(S, S->rctr, 1) && dalloc(S, t.x, n) && dalloc(S, t.v, n) &&
+    bool ok = alloc_veh(S, S->rbuf[0], cap) && alloc_veh(S, S->rbuf[1], cap) &&
+              dalloc(S, S->rqstate, 2 * (size_t)S->tr.nq) && dalloc(S, S->rctr, 1) && dalloc(S, t.x, n) && dalloc(S, t.v, n) &&
               dalloc(S, t.vid, n) && dalloc(S, t.edge, n) && dalloc(S, t.lead, n) && dalloc(S, t.clead, n) &&
               dalloc(S, t.next, n) && dalloc(S, t.mode, n) && dalloc(S, t.flags, n) && dalloc(S, t.cflags, n) &&
               dalloc(S, t.n, K) && dalloc(S, S->L0x, cap) && dalloc(S, S->L0v, cap) && dalloc(S, S->L1x, cap) &&
@@ -384,7 +395,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
         return SIM_EINVAL;
     if ((alloc == nullptr) != (free_fn == nullptr)) return SIM_EINVAL;
     const int nn = net->num_nodes, ne = net->num_edges, ncls = prm->num_classes;
-    if (nn <= 0 || ne <= 0 || ncls <= 0 || ncls > 4096) return SIM_EINVAL;
+    if (nn <= 0 || ne <= 0 || ncls <= 0 || ncls > 4096 || ne >= (1 << 28)) return SIM_EINVAL;
     if (net->row_ptr[0] != 0 || net->row_ptr[nn] != ne) return SIM_EINVAL;
     for (int u = 0; u < nn; ++u)
         if (net->row_ptr[u + 1] < net->row_ptr[u]) return SIM_EINVAL;
@@ -454,6 +465,8 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     P.tclaim[0] = P.claim_len;
 
     float *d_len, *dummy;
+    EdgeRec* d_er;
+    ClaimRec* d_cr;
     int *d_lane_base, *d_lanes, *d_cls, *d_head, *d_row_ptr, *d_ncell;
     long long* d_cbase;
     // per-type constants are sized for the largest number of vehicle types (4)
@@ -461,6 +474,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
               dalloc(S, d_lanes, ne) && dalloc(S, d_cls, ne) && dalloc(S, d_head, ne) &&
               dalloc(S, d_row_ptr, nn + 1) && dalloc(S, d_cbase, ne) && dalloc(S, d_ncell, ne) &&
               dalloc(S, S->d_capA, 4 * (size_t)ncls) && dalloc(S, S->d_capV, 4 * (size_t)ne) &&
+              dalloc(S, S->d_drv, 4 * (size_t)ne) && dalloc(S, d_er, ne) && dalloc(S, d_cr, ne) &&
               dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, 4 * (size_t)ncls) && dalloc(S, S->d_cKab, 4 * (size_t)ncls) &&
               dalloc(S, S->d_cVs, ncls) && dalloc(S, S->d_cB, ncls) && dalloc(S, S->d_epoch, 1) &&
               dalloc(S, S->s.lanes, (size_t)S->nlanes) &&
@@ -477,6 +491,19 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
         (rc = h2d(S, d_lanes, S->lanes.data(), ne)) || (rc = h2d(S, d_cls, S->cls.data(), ne)) ||
         (rc = h2d(S, d_head, S->col_idx.data(), ne)) || (rc = h2d(S, d_row_ptr, S->row_ptr.data(), nn + 1)) ||
         (rc = h2d(S, d_cbase, cbase.data(), ne)) || (rc = h2d(S, d_ncell, S->ncell.data(), ne))) {
+        release_all(S);
+        delete S;
+        return rc;
+    }
+    std::vector<EdgeRec> er(ne);
+    std::vector<ClaimRec> cr(ne);
+    for (int e = 0; e < ne; ++e) {
+        const int h = S->col_idx[e];
+        er[e] = EdgeRec{S->len[e], S->lane_base[e], S->lanes[e], S->row_ptr[h]};
+        cr[e] = ClaimRec{cbase[e], S->ncell[e], S->row_ptr[h + 1] - S->row_ptr[h]};
+    }
+    if ((rc = h2d(S, d_er, er.data(), ne)) || (rc = h2d(S, d_cr, cr.data(), ne)) ||
+        (rc = (hipStreamSynchronize(S->stream) == hipSuccess ? SIM_OK : SIM_EHIP))) {
         release_all(S);
         delete S;
         return rc;
@@ -528,6 +555,9 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     N.cVs = S->d_cVs;
     N.cB = S->d_cB;
     N.capA = S->d_capA;
+    N.er = d_er;
+    N.cr = d_cr;
+    N.drv = S->d_drv;
     N.capV = S->d_capV;
     N.ne = ne;
     S->s.epoch = S->d_epoch;
@@ -589,7 +619,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
             rel[t] = v;
         }
     }
-    std::vector<unsigned char> placed(ntrips, init_x ? 1 : 0);
+    std::vector<int> first_edge(std::max(ntrips, 1), -1);
+    for (int v = 0; v < ntrips && !init_x; ++v) first_edge[v] = route_edges[rbeg[v]];
     // placed vehicles: validated, then sorted by (lane, position)
     std::vector<int> pkey, pedge, prcur, pnext, plc, pkin, pvid;
     std::vector<unsigned char> pty;
@@ -634,18 +665,46 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
         }
     }
 
+    // departure queues: the trips that are not placed, by (first link, type),
+    // each queue by vehicle id (= by departure step)
+    std::vector<int> qmem;
+    qmem.reserve(ntrips);
+    for (int v = 0; v < ntrips; ++v)
+        if (first_edge[v] >= 0) qmem.push_back(v);
+    std::stable_sort(qmem.begin(), qmem.end(), [&](int a, int b) {
+        const long long ka = 4ll * first_edge[a] + vtype[a], kb = 4ll * first_edge[b] + vtype[b];
+        return ka < kb;
+    });
+    std::vector<int> qoff(1, 0), qedge, qdep(qmem.size());
+    std::vector<unsigned char> qtype;
+    for (size_t m = 0; m < qmem.size(); ++m) {
+        const int v = qmem[m];
+        if (m == 0 || first_edge[v] != first_edge[qmem[m - 1]] || vtype[v] != vtype[qmem[m - 1]]) {
+            if (m) qoff.push_back((int)m);
+            qedge.push_back(first_edge[v]);
+            qtype.push_back(vtype[v]);
+        }
+        qdep[m] = dep[v];
+    }
+    qoff.push_back((int)qmem.size());
+    if (qmem.empty()) qoff.assign(1, 0);
+    const int nq = (int)qedge.size();
+
     const int cap = std::max(ntrips, 1);
     S->cap = cap;
     S->ntrips = ntrips;
     int* d_re;
     int *d_rbeg, *d_rend, *d_rel;
-    unsigned char* d_placed;
+    int *d_qoff, *d_qvid, *d_qdep, *d_qedge;
+    unsigned char* d_qtype;
     Scratch& s = S->s;
     bool ok = dalloc(S, d_re, (size_t)nre) && dalloc(S, d_rbeg, cap) && dalloc(S, d_rend, cap) &&
-              dalloc(S, d_rel, rel_len + 1) && dalloc(S, d_placed, cap) &&
+              dalloc(S, d_rel, rel_len + 1) &&
               dalloc(S, S->tr.depart_actual, cap) && dalloc(S, S->tr.arrive_step, cap) &&
               dalloc(S, S->tr.fuel_total, cap) && dalloc(S, S->tr.co_total, cap) &&
-              dalloc(S, S->pend[0], cap) && dalloc(S, S->pend[1], cap) && dalloc(S, S->d_vtype, cap);
+              dalloc(S, S->d_vtype, cap) && dalloc(S, d_qoff, (size_t)nq + 1) &&
+              dalloc(S, d_qvid, qmem.size()) && dalloc(S, d_qdep, qmem.size()) && dalloc(S, d_qedge, (size_t)nq) &&
+              dalloc(S, d_qtype, (size_t)nq) && dalloc(S, S->qstate, 2 * (size_t)nq);
     for (int b = 0; b < 2 && ok; ++b) {
         Veh& V = S->buf[b];
         ok = dalloc(S, V.key, cap) && dalloc(S, V.x, cap) && dalloc(S, V.v, cap) && dalloc(S, V.edge, cap) &&
@@ -667,12 +726,15 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<int> minus1(cap, -1);
     if ((rc = h2d(S, d_re, route_edges, (size_t)nre)) || (rc = h2d(S, d_rbeg, rbeg.data(), ntrips)) ||
         (rc = h2d(S, d_rend, rend.data(), ntrips)) || (rc = h2d(S, d_rel, rel.data(), rel_len + 1)) ||
-        (rc = h2d(S, d_placed, placed.data(), ntrips)) || (rc = h2d(S, S->d_vtype, vtype.data(), ntrips)) ||
+        (rc = h2d(S, S->d_vtype, vtype.data(), ntrips)) || (rc = h2d(S, d_qoff, qoff.data(), qoff.size())) ||
+        (rc = h2d(S, d_qvid, qmem.data(), qmem.size())) || (rc = h2d(S, d_qdep, qdep.data(), qdep.size())) ||
+        (rc = h2d(S, d_qedge, qedge.data(), qedge.size())) || (rc = h2d(S, d_qtype, qtype.data(), qtype.size())) ||
         (rc = h2d(S, S->tr.arrive_step, minus1.data(), cap)))
         return rc;
     std::vector<int> da(cap, init_x ? t0 : -1);
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
     HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
+    if (nq) HIPCHECK(S, hipMemsetAsync(S->qstate, 0, sizeof(int) * 2 * (size_t)nq, S->stream));
     HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));
     HIPCHECK(S, hipMemsetAsync(S->tr.co_total, 0, sizeof(float) * cap, S->stream));
     for (int b = 0; b < 2; ++b) {
@@ -704,11 +766,19 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     S->tr.rend = d_rend;
     S->tr.rel_off = d_rel;
     S->tr.rel_len = rel_len;
-    S->tr.placed = d_placed;
     S->tr.vtype = S->d_vtype;
+    S->tr.nq = nq;
+    S->tr.qoff = d_qoff;
+    S->tr.qvid = d_qvid;
+    S->tr.qdep = d_qdep;
+    S->tr.qedge = d_qedge;
+    S->tr.qtype = d_qtype;
+    S->tr.qhead = S->qstate;
+    S->tr.qtail = S->qstate + nq;
     S->h_rbeg = rbeg;
     S->grid = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)cap + kBlock - 1) / kBlock));
     S->grid_small = std::max(1, S->grid / 4);
+    S->grid_q = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)nq + kBlock - 1) / kBlock));
     if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
     HIPCHECK(S, hipStreamSynchronize(S->stream));
     S->loaded = true;
@@ -739,7 +809,7 @@ int sim_step(sim_t* S, int32_t num_steps) {
                 S->ev_free.pop_back();
             }
         }
-        int rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->pend[p], S->pend[p ^ 1], S->s, off, S->ctr,
+        int rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->tr, S->s, off, S->ctr,
                              timed ? ev : nullptr);
         if (rc) return rc;
         if (timed) S->ev_steps.emplace_back(ev, ev + SIM_NUM_KERNELS + 1);
@@ -785,6 +855,9 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
     rs.st_steps = S->sink + S->ne;
     rs.st_us = S->sink + 2 * (size_t)S->ne;
     rs.holder = S->d_rholder;  // stop-node admissions replay on their own copy
+    Trips rtr = S->tr;         // and so do the departure queues
+    rtr.qhead = S->rqstate;
+    rtr.qtail = S->rqstate + S->tr.nq;
     AdjState a = S->adj;
     a.vtype = S->tr.vtype;
     a.dLdT = dL_dmeanTT;
@@ -794,11 +867,11 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
         const sim_t::Ckpt& ck = S->ckpt_pool[c];
         const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
         const int K = (int)(t_end - ck.t);
-        if ((rc = copy_state(S, S->rbuf[0], S->rpend[0], S->rctr, S->d_rholder, ck.v, ck.pend, ck.ctr, ck.holder)))
+        if ((rc = copy_state(S, S->rbuf[0], S->rqstate, S->rctr, S->d_rholder, ck.v, ck.qstate, ck.ctr, ck.holder)))
             return rc;
         if ((rc = reindex(S, S->rbuf[0], rs, S->rctr))) return rc;
         for (int k = 0; k < K; ++k) {
-            if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], S->rpend[k & 1], S->rpend[(k + 1) & 1],
+            if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], rtr,
                                   rs, slice(S, k), S->rctr, nullptr)))
                 return rc;
         }
@@ -849,6 +922,7 @@ int sim_stats(sim_t* S, sim_stats_t* host_out, int64_t* edge_count, int64_t* edg
         host_out->claims_lost = (int64_t)c.claims_lost;
         host_out->clamps = (int64_t)c.clamps;
         host_out->claims = (int64_t)c.claims;
+        host_out->claims_departure = (int64_t)c.claims_dep;
     }
     return SIM_OK;
 }
@@ -1202,7 +1276,7 @@ int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
             S->stream = S->gstream;  // launch_step enqueues on S->stream
             for (int k = 0; k < len && rc == SIM_OK; ++k) {
                 const int p = (parity + k) & 1;
-                rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->pend[p], S->pend[p ^ 1], S->s, off, S->ctr, nullptr);
+                rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->tr, S->s, off, S->ctr, nullptr);
             }
             S->stream = user;
             hipError_t ce = hipStreamEndCapture(S->gstream, &graph);
@@ -1248,7 +1322,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     const int p = (int)(S->host_t & 1);
     unsigned long long* st_save = nullptr;
     int* trip_save = nullptr;
-    if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.pend, S->cap) || !dalloc(S, save.ctr, 1) ||
+    if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.qstate, 2 * (size_t)S->tr.nq) || !dalloc(S, save.ctr, 1) ||
         !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap) ||
         !dalloc(S, save.holder, S->nn))
         return fail(S, SIM_ENOMEM, "autotune allocation failed");
@@ -1257,7 +1331,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     HIPCHECK(S, hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
-    int rc = copy_state(S, save.v, save.pend, save.ctr, save.holder, S->buf[p], S->pend[p], S->ctr, S->s.holder);
+    int rc = copy_state(S, save.v, save.qstate, save.ctr, save.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
     if (rc) return rc;
     const size_t eb = sizeof(unsigned long long) * (size_t)S->ne;
     HIPCHECK(S, hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
@@ -1282,12 +1356,12 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
             S->grid = gc;
             S->grid_small = gs;
             S->host_t = t_save;
-            if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, S->s.holder, save.v, save.pend, save.ctr, save.holder))) return rc;
+            if ((rc = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder))) return rc;
             if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
             HIPCHECK(S, hipEventRecord(e0, S->stream));
             for (int k = 0; k < steps_per_trial && rc == SIM_OK; ++k) {
                 const int q = (int)(S->host_t & 1);
-                rc = launch_step(S, S->buf[q], S->buf[q ^ 1], S->pend[q], S->pend[q ^ 1], S->s, off, S->ctr, nullptr);
+                rc = launch_step(S, S->buf[q], S->buf[q ^ 1], S->tr, S->s, off, S->ctr, nullptr);
                 S->host_t += 1;
             }
             if (rc) return rc;
@@ -1309,7 +1383,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     S->grid = bg;
     S->grid_small = bs;
     drop_graphs(S);
-    if ((rc = copy_state(S, S->buf[p], S->pend[p], S->ctr, S->s.holder, save.v, save.pend, save.ctr, save.holder))) return rc;
+    if ((rc = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder))) return rc;
     HIPCHECK(S, hipMemcpyAsync(S->s.st_cnt, st_save, eb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->s.st_steps, st_save + S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
