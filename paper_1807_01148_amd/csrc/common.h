@@ -14,6 +14,20 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kLcNone = -(1 << 30);
 constexpr int kMaxGrid = 2048;
+// A list that every wave of a step may append to (lane-change candidates,
+// claims) is split into kSeg segments with one counter each, in lines of their
+// own: the entries of 256-vehicle (or 256-queue) chunk c go to segment
+// c % kSeg.  With a grid that is a multiple of kSeg, chunk c is handled by a
+// block on XCD c % kSeg, so the appends of one XCD meet one counter and stay
+// in that XCD's L2; one counter for the whole chip would serialise every
+// wave's append.
+constexpr int kSeg = 8;
+constexpr int kSegStride = 32;  // ints from one segment counter to the next
+// The step's statistics are summed the same way: one line of kStatStride
+// counters per XCD (block b adds to line b % kSeg), folded into the Counters
+// when the step ends.
+enum : int { kStClamps = 0, kStArrived, kStGhost, kStLost, kStDepClaims, kStDeparted };
+constexpr int kStatStride = 16;
 
 enum : int { kCross = 1, kChange = 2, kInsert = 3 };
 
@@ -23,14 +37,10 @@ enum : int { kCross = 1, kChange = 2, kInsert = 3 };
 struct Counters {
     int t;           // current step
     int n;           // vehicles on the road (entries of the current buffer)
-    int nghost;      // departure claims that lose for certain, counted without an entry
-    int nclaim;      // claims this step
     int nmove;       // winning claims this step
-    int pad1;
     int n_next;      // entries of the next buffer
     unsigned scan_tile;
     unsigned epoch_next;  // epoch of the next step (set during the step, committed at its end)
-    int pad;
     unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
     unsigned long long claims_dep;  // of which departures (those counted without an entry included)
 };
@@ -167,7 +177,23 @@ __device__ __forceinline__ bool lane_rear(const LaneIx* __restrict__ lanes, int 
     return (unsigned)w.x == ep;
 }
 
+// A vehicle that may change lanes this step, listed by k_decide for k_change:
+// its entry index, its own-lane acceleration and its own leader (kind in bits
+// 0-1 of meta, bit 2 set when its movement at the link end is held).
+struct __align__(16) LcRec {
+    int i, meta;
+    float ac;
+    int lidx;
+    float ls, lxl, lvl, lll;
+};
+
 struct Scratch {
+    LcRec* lc;    // kSeg segments of lc_seg records
+    int* lcnt;    // their counters, kSegStride ints apart
+    int lc_seg;
+    int* ccnt;    // counters of the kSeg segments of the claim list (cl_*)
+    int cl_seg;   // entries per claim segment
+    unsigned long long* sstat;  // kSeg lines of per-XCD statistics
     float* xs;
     float* vs;
     unsigned char* stay;
@@ -436,11 +462,16 @@ __device__ __forceinline__ int wave_slot(int* counter) {
     return base + rank;
 }
 
-__device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, Counters* ctr,
-                                           unsigned long long tag, int vid, int kind, int src,
-                                           int tedge, int tlane, float X, float vc, float f, int lo,
-                                           int hi) {
-    const int ci = wave_slot(&ctr->nclaim);
+// adds v to statistic `what` of the calling block's line
+__device__ __forceinline__ void seg_stat(const Scratch& s, int what, unsigned long long v) {
+    if (v) atomicAdd(s.sstat + (blockIdx.x & (kSeg - 1)) * kStatStride + what, v);
+}
+
+// A claim goes to segment seg (the same for the whole wave) of the claim list.
+__device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, int seg, unsigned long long tag,
+                                           int vid, int kind, int src, int tedge, int tlane, float X, float vc,
+                                           float f, int lo, int hi) {
+    const int ci = seg * s.cl_seg + wave_slot(s.ccnt + seg * kSegStride);
     s.cl_vid[ci] = vid;
     const ClaimRec C = net.cr[tedge];
     s.cl_key[ci] = net.er[tedge].lane_base + tlane;

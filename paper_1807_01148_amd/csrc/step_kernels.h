@@ -120,7 +120,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
-        push_claim(s, net, ctr, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
+        push_claim(s, net, (i / kBlock) & (kSeg - 1), tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
         return;
     }
     s.xs[i] = xs;
@@ -128,9 +128,50 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     s.stay[i] = 1;
     if (tp.on) tp.flags[i] = (unsigned short)own_fl;
 
-    // lane change: eligibility
+    // lane change (Sec. 6.3.2): a vehicle past the cool-down on a multi-lane
+    // link is listed for k_change, which evaluates the listed vehicles in
+    // dense waves
+    if (E.lanes < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
+    LcRec r;
+    r.i = i;
+    r.meta = L.kind | (held ? 4 : 0);
+    r.ac = ac;
+    r.lidx = L.idx;
+    r.ls = L.s;
+    r.lxl = L.xl;
+    r.lvl = L.vl;
+    r.lll = L.ll;
+    const int q = (i / kBlock) & (kSeg - 1);  // the same for the whole wave
+    s.lc[(size_t)q * s.lc_seg + wave_slot(s.lcnt + q * kSegStride)] = r;
+}
+
+// Lane-change evaluation of one listed vehicle (Sec. 6.3.2): candidate lanes
+// (the mandatory one when the vehicle is outside its turn band near the link
+// end, else the neighbours inside the band), gap acceptance, the safety
+// criterion for the new follower, the incentive criterion; the best candidate
+// claims its cells in the target lane.
+__device__ void change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
+                               Counters* ctr, int N, unsigned ep, unsigned long long tag, const LcRec& r) {
+    const int i = r.i;
+    const int k = in.key[i];
+    const float x = in.x[i];
+    const float v = in.v[i];
+    const int e = in.edge[i];
+    const int nx = in.next[i];
+    const int ty = in.ty[i];
+    const int vid = in.vid[i];
+    const EdgeRec E = net.er[e];
+    const float len = E.len;
+    const float lme = P.tlen[ty];
+    const int nt = P.nt;
+    const DrvRec D = net.drv[e * nt + ty];
+    const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
+    const int lb = E.lane_base;
+    const int l = k - lb;
+    const bool held = (r.meta & 4) != 0;
+    const Lead L = {r.meta & 3, r.ls, r.lvl, r.lxl, r.lidx, r.lll};
+    const float ac = r.ac;
     const int n = E.lanes;
-    if (n < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
         const int r0 = E.r0;
@@ -244,7 +285,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         }
         int lo, hi;
         claim_cells(P, net, e, ty, best_X, lo, hi);
-        push_claim(s, net, ctr, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+        push_claim(s, net, (i / kBlock) & (kSeg - 1), tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
     }
 }
 
@@ -278,7 +319,8 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
     if (bsp >= P.tclaim[ty]) {
         int lo, hi;
         claim_cells(P, net, e0, ty, P.tlen[ty], lo, hi);
-        push_claim(s, net, ctr, tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best, P.tlen[ty], 0.0f, 1.0f, lo, hi);
+        push_claim(s, net, (q / kBlock) & (kSeg - 1), tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best, P.tlen[ty],
+                   0.0f, 1.0f, lo, hi);
         ghost += tl - h - 1;
         issued += tl - h;
     }
@@ -298,9 +340,23 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (cw) atomicAdd(&ctr->clamps, cw);
-        if (aw) atomicAdd(&ctr->arrived, aw);
+        seg_stat(s, kStClamps, cw);
+        seg_stat(s, kStArrived, aw);
     }
+}
+
+// lane changes: one thread per listed vehicle; the grid is a multiple of kSeg
+// and block b reads segment b % kSeg
+__global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Scratch s, Tape tp, Counters* ctr) {
+    const int N = ctr->n;
+    const int q = blockIdx.x & (kSeg - 1);
+    const int M = s.lcnt[q * kSegStride];
+    const LcRec* seg = s.lc + (size_t)q * s.lc_seg;
+    const int nb = gridDim.x / kSeg;
+    const unsigned ep = *s.epoch;
+    const unsigned long long tag = epoch_tag(ep);
+    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock)
+        change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, seg[j]);
 }
 
 // departures: one thread per queue
@@ -314,11 +370,9 @@ __global__ __launch_bounds__(kBlock) void k_insert(Params P, Net net, Trips tr, 
     const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
     const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (gw) {
-            atomicAdd(&ctr->nghost, (int)gw);
-            atomicAdd(&ctr->claims_lost, gw);
-        }
-        if (iw) atomicAdd(&ctr->claims_dep, iw);
+        seg_stat(s, kStGhost, gw);
+        seg_stat(s, kStLost, gw);
+        seg_stat(s, kStDepClaims, iw);
     }
 }
 
@@ -329,7 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
                                                     Counters* ctr) {
     const int t = ctr->t;
     const int N = ctr->n;
-    const int C = ctr->nclaim;
+    const int seg = blockIdx.x & (kSeg - 1);  // the grid is a multiple of kSeg
+    const int M = s.ccnt[seg * kSegStride];
+    const int nb = gridDim.x / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -337,7 +393,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
         ctr->epoch_next = ep + 1u;
     }
     int lost = 0, departed = 0;
-    for (int ci = blockIdx.x * kBlock + threadIdx.x; ci < C; ci += gridDim.x * kBlock) {
+    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
+        const int ci = seg * s.cl_seg + j;
         const int vid = s.cl_vid[ci];
         const int tedge = s.cl_tedge[ci];
         const int key = s.cl_key[ci];
@@ -385,8 +442,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
     unsigned long long lw = wave_sum_u64((unsigned long long)lost);
     unsigned long long dw = wave_sum_u64((unsigned long long)departed);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (lw) atomicAdd(&ctr->claims_lost, lw);
-        if (dw) atomicAdd(&ctr->departed, dw);
+        seg_stat(s, kStLost, lw);
+        seg_stat(s, kStDeparted, dw);
     }
 }
 
@@ -633,11 +690,20 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
     }
     if (finalize && blockIdx.x == 0 && threadIdx.x == 0) {
         ctr->updates += (unsigned long long)ctr->n;
-        ctr->claims += (unsigned long long)ctr->nclaim;
+        for (int q = 0; q < kSeg; ++q) {
+            unsigned long long* st = s.sstat + q * kStatStride;
+            // claims: those with an entry, and departures that lose for certain
+            ctr->claims += (unsigned long long)s.ccnt[q * kSegStride] + st[kStGhost];
+            ctr->clamps += st[kStClamps];
+            ctr->arrived += st[kStArrived];
+            ctr->claims_lost += st[kStLost];
+            ctr->claims_dep += st[kStDepClaims];
+            ctr->departed += st[kStDeparted];
+            for (int w = 0; w < kStatStride; ++w) st[w] = 0;
+            s.ccnt[q * kSegStride] = 0;
+            s.lcnt[q * kSegStride] = 0;
+        }
         ctr->n = ctr->n_next;
-        ctr->claims += (unsigned long long)ctr->nghost;
-        ctr->nghost = 0;
-        ctr->nclaim = 0;
         ctr->nmove = 0;
         ctr->t = ctr->t + 1;
         *s.epoch = ep;
