@@ -37,7 +37,6 @@ enum : int { kCross = 1, kChange = 2, kInsert = 3 };
 struct Counters {
     int t;           // current step
     int n;           // vehicles on the road (entries of the current buffer)
-    int nmove;       // winning claims this step
     int n_next;      // entries of the next buffer
     unsigned scan_tile;
     unsigned epoch_next;  // epoch of the next step (set during the step, committed at its end)
@@ -209,6 +208,9 @@ struct Scratch {
     float* cl_X;
     float* cl_v;
     float* cl_f;
+    // movers (winning claims), in kSeg segments of cl_seg entries: the winners
+    // of claim segment q go to mover segment q
+    int* mvcnt;  // segment counters, kSegStride ints apart
     int* mv_claim;
     int* mv_p;
     int* mv_slot;

@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
         }
         if (win) {
             if (src >= 0) s.stay[src] = 0;
-            const int m = wave_slot(&ctr->nmove);
+            const int m = seg * s.cl_seg + wave_slot(s.mvcnt + seg * kSegStride);
             s.mv_claim[m] = ci;
             // its gap in the sorted order: inside its lane's run if the lane is
             // occupied, else before the first entry of a later lane
@@ -559,12 +559,11 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
 // ---------------------------------------------------------------------------
 // k_scatter: survivors to their new slot; movers stage their sort keys
 // ---------------------------------------------------------------------------
+// (the grid is a multiple of kSeg: block b stages the movers of segment b % kSeg)
 __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
     const int N = ctr->n;
-    const int M = ctr->nmove;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N + M; i += gridDim.x * kBlock) {
-        if (i < N) {
-            if (!s.stay[i]) continue;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        if (s.stay[i]) {
             const int j = s.cscan[i] + s.mcnt[i];
             if (tp.on) tp.next[i] = j;
             out.key[j] = in.key[i];
@@ -582,15 +581,19 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, S
             emissions(P, in.v[i], s.vs[i], fu, co);
             out.fuel[j] = fu;
             out.co[j] = co;
-        } else {
-            const int m = i - N;
-            const int p = s.mv_p[m];
-            const int ci = s.mv_claim[m];
-            const int b = s.cscan[p];
-            s.mv_g[m] = s.mcnt[p];
-            s.grp_key[b + s.mv_slot[m]] = s.cl_key[ci];
-            s.grp_X[b + s.mv_slot[m]] = s.cl_X[ci];
         }
+    }
+    const int seg = blockIdx.x & (kSeg - 1);
+    const int M = s.mvcnt[seg * kSegStride];
+    const int nb = gridDim.x / kSeg;
+    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
+        const int m = seg * s.cl_seg + j;
+        const int p = s.mv_p[m];
+        const int ci = s.mv_claim[m];
+        const int b = s.cscan[p];
+        s.mv_g[m] = s.mcnt[p];
+        s.grp_key[b + s.mv_slot[m]] = s.cl_key[ci];
+        s.grp_X[b + s.mv_slot[m]] = s.cl_X[ci];
     }
 }
 
@@ -600,8 +603,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, S
 __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Veh out, Scratch s, Tape tp,
                                                   int lc_none, Counters* ctr) {
     const int t = ctr->t;
-    const int M = ctr->nmove;
-    for (int m = blockIdx.x * kBlock + threadIdx.x; m < M; m += gridDim.x * kBlock) {
+    const int seg = blockIdx.x & (kSeg - 1);  // the grid is a multiple of kSeg
+    const int M = s.mvcnt[seg * kSegStride];
+    const int nb = gridDim.x / kSeg;
+    for (int jm = (blockIdx.x / kSeg) * kBlock + threadIdx.x; jm < M; jm += nb * kBlock) {
+        const int m = seg * s.cl_seg + jm;
         const int ci = s.mv_claim[m];
         const int p = s.mv_p[m];
         const int b = s.cscan[p];
@@ -688,25 +694,34 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
         }
         if (j == N - 1 || buf.key[j + 1] != k) s.lanes[k].hi = j;
     }
-    if (finalize && blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr->updates += (unsigned long long)ctr->n;
-        for (int q = 0; q < kSeg; ++q) {
+    if (finalize && blockIdx.x == 0 && threadIdx.x < kWave) {
+        // fold the per-XCD lines into the counters (lane q reads line q) and
+        // clear them for the next step
+        const int q = threadIdx.x;
+        unsigned long long v[kStDeparted + 2] = {};
+        if (q < kSeg) {
             unsigned long long* st = s.sstat + q * kStatStride;
-            // claims: those with an entry, and departures that lose for certain
-            ctr->claims += (unsigned long long)s.ccnt[q * kSegStride] + st[kStGhost];
-            ctr->clamps += st[kStClamps];
-            ctr->arrived += st[kStArrived];
-            ctr->claims_lost += st[kStLost];
-            ctr->claims_dep += st[kStDepClaims];
-            ctr->departed += st[kStDeparted];
+            for (int w = 0; w <= kStDeparted; ++w) v[w] = st[w];
+            v[kStDeparted + 1] = (unsigned long long)s.ccnt[q * kSegStride];
             for (int w = 0; w < kStatStride; ++w) st[w] = 0;
             s.ccnt[q * kSegStride] = 0;
             s.lcnt[q * kSegStride] = 0;
+            s.mvcnt[q * kSegStride] = 0;
         }
-        ctr->n = ctr->n_next;
-        ctr->nmove = 0;
-        ctr->t = ctr->t + 1;
-        *s.epoch = ep;
+        for (int w = 0; w < kStDeparted + 2; ++w) v[w] = wave_sum_u64(v[w]);
+        if (q == 0) {
+            ctr->updates += (unsigned long long)ctr->n;
+            // claims: those with an entry, and departures that lose for certain
+            ctr->claims += v[kStDeparted + 1] + v[kStGhost];
+            ctr->clamps += v[kStClamps];
+            ctr->arrived += v[kStArrived];
+            ctr->claims_lost += v[kStLost];
+            ctr->claims_dep += v[kStDepClaims];
+            ctr->departed += v[kStDeparted];
+            ctr->n = ctr->n_next;
+            ctr->t = ctr->t + 1;
+            *s.epoch = ep;
+        }
     }
 }
 

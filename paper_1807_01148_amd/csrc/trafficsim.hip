@@ -254,22 +254,22 @@ int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
 int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
+    // kernels that read the per-XCD segments run a multiple of kSeg blocks
+    const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg), gs8((S->grid_small + kSeg - 1) / kSeg * kSeg);
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
     hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
-    hipLaunchKernelGGL(k_change, dim3((S->grid + kSeg - 1) / kSeg * kSeg), b, 0, S->stream, S->P, S->net, in, sc, tp,
-                       ctr);
+    hipLaunchKernelGGL(k_change, g8, b, 0, S->stream, S->P, S->net, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
     hipLaunchKernelGGL(k_insert, dim3(S->grid_q), b, 0, S->stream, S->P, S->net, tr, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
-    hipLaunchKernelGGL(k_resolve, dim3((S->grid_small + kSeg - 1) / kSeg * kSeg), b, 0, S->stream, S->P, S->net, tr,
-                       in, sc, tp, ctr);
+    hipLaunchKernelGGL(k_resolve, gs8, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
     hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-    hipLaunchKernelGGL(k_scatter, g, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
+    hipLaunchKernelGGL(k_scatter, g8, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
-    hipLaunchKernelGGL(k_place, gs, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
+    hipLaunchKernelGGL(k_place, gs8, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
     hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
     if (ev) HIPCHECK(S, hipEventRecord(ev[8], S->stream));
@@ -722,15 +722,15 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     // a claim segment also takes the departures of queue chunks q, q + kSeg, ...
     s.cl_seg = s.lc_seg + (int)(((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
     const size_t ncl = (size_t)kSeg * s.cl_seg;
-    ok = ok && dalloc(S, s.lc, (size_t)kSeg * s.lc_seg) && dalloc(S, s.lcnt, (size_t)2 * kSeg * kSegStride) &&
+    ok = ok && dalloc(S, s.lc, (size_t)kSeg * s.lc_seg) && dalloc(S, s.lcnt, (size_t)3 * kSeg * kSegStride) &&
          dalloc(S, s.sstat, (size_t)kSeg * kStatStride) &&
          dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
          dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && dalloc(S, s.cl_vid, ncl) &&
          dalloc(S, s.cl_key, ncl) && dalloc(S, s.cl_lo, ncl) && dalloc(S, s.cl_hi, ncl) &&
          dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) && dalloc(S, s.cl_tedge, ncl) &&
          dalloc(S, s.cl_X, ncl) && dalloc(S, s.cl_v, ncl) && dalloc(S, s.cl_f, ncl) &&
-         dalloc(S, s.mv_claim, cap) && dalloc(S, s.mv_p, cap) && dalloc(S, s.mv_slot, cap) &&
-         dalloc(S, s.mv_g, cap) && dalloc(S, s.grp_key, cap) && dalloc(S, s.grp_X, cap) &&
+         dalloc(S, s.mv_claim, ncl) && dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) &&
+         dalloc(S, s.mv_g, ncl) && dalloc(S, s.grp_key, cap) && dalloc(S, s.grp_X, cap) &&
          dalloc(S, s.tile_status, ntiles);
     if (!ok) return fail(S, SIM_ENOMEM, "device allocation failed in sim_load_demand");
     int rc;
@@ -746,7 +746,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
     HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
     s.ccnt = s.lcnt + kSeg * kSegStride;
-    HIPCHECK(S, hipMemsetAsync(s.lcnt, 0, sizeof(int) * 2 * kSeg * kSegStride, S->stream));
+    s.mvcnt = s.lcnt + 2 * kSeg * kSegStride;
+    HIPCHECK(S, hipMemsetAsync(s.lcnt, 0, sizeof(int) * 3 * kSeg * kSegStride, S->stream));
     HIPCHECK(S, hipMemsetAsync(s.sstat, 0, sizeof(unsigned long long) * kSeg * kStatStride, S->stream));
     if (nq) HIPCHECK(S, hipMemsetAsync(S->qstate, 0, sizeof(int) * 2 * (size_t)nq, S->stream));
     HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));
