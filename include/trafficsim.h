@@ -91,6 +91,10 @@ typedef struct {
                                * enter one link by the same lane, only the one with
                                * the lowest id can win; the others are counted
                                * (here and in claims_lost) without a claim record */
+    int64_t lc_evaluated;       /* vehicles that passed the lane-change eligibility
+                                 * test (multi-lane link, cool-down over, fully on
+                                 * the link, not leaving it) and were evaluated */
+    int64_t claims_lane_change; /* of the claims, lane changes */
 } sim_stats_t;
 
 /* Create a simulation of `net` with `params` on `hip_stream` (a hipStream_t,

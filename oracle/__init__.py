@@ -100,7 +100,8 @@ def fparams(p):
 
 
 COUNTERS = ("step", "loaded", "waiting", "en_route", "arrived", "departed",
-            "vehicle_updates", "claims_lost", "clamps")
+            "vehicle_updates", "claims_lost", "clamps", "claims", "claims_departure",
+            "lc_evaluated", "claims_lane_change")
 
 
 class OracleError(RuntimeError):

@@ -95,6 +95,7 @@ typedef struct {
     int32_t* pend;
     int64_t *st_cnt, *st_steps, *st_us;
     int64_t departed, arrived, updates, claims_lost, clamps;
+    int64_t claims, claims_dep, lc_evaluated, claims_lc;
     real *fuel_total, *co_total; /* per vehicle id, at arrival */
     /* sampler: every `samp_every` steps, per link vehicle count and speed sum
      * (micrometres per second), accumulated in groups of `samp_group` samples */
@@ -535,6 +536,7 @@ typedef struct {
     real X, vc, f;               /* front on the target, speed, crossing fraction */
     int32_t lo, hi;              /* claim cells */
     int clamped;
+    int lc_eval;  /* passed the lane-change eligibility test */
     real vn;                     /* speed after the own-lane motion */
     int own_fl, chg_fl;          /* branch flags of the own-lane and the lane-change motion */
     int32_t own_lead, chg_lead;  /* vehicle ahead used by each (-1: free road) */
@@ -686,6 +688,7 @@ static dec_t decide(const view_t* W, int32_t o) {
     /* lane change (Sec. 6.3.2): eligibility */
     int32_t n = S->lanes[e];
     if (n < 2 || (S->t - me->lc) < S->lc_cool || x < lme) return D;
+    D.lc_eval = 1;
     int32_t lo = 0, hi = n - 1;
     if (me->next >= 0) {
         int32_t hn = S->col_idx[e];
@@ -876,8 +879,11 @@ static int step_once(osim* S) {
         if (D[o].kind == K_CROSS || D[o].kind == K_CHANGE) {
             claim_t c = {D[o].tkey, D[o].lo, D[o].hi, at(&W, o)->vid, o, 0};
             C[nclaim++] = c;
+            if (D[o].kind == K_CHANGE) S->claims_lc += 1;
         }
+        S->lc_evaluated += D[o].lc_eval;
     }
+    const int32_t nclaim_veh = nclaim;
     for (int32_t i = 0; i < ncand; ++i) {
         int32_t v = cand[i];
         int32_t e0 = S->route_edges[S->rbeg[v]];
@@ -898,6 +904,8 @@ static int step_once(osim* S) {
             C[nclaim++] = c;
         }
     }
+    S->claims += nclaim;
+    S->claims_dep += nclaim - nclaim_veh;
     /* a claim wins iff no overlapping claim on the same lane has a lower id */
     qsort(C, nclaim, sizeof(claim_t), cmp_claim);
     int32_t* cwin_veh = (int32_t*)calloc(N + 1, sizeof(int32_t));
@@ -1018,7 +1026,7 @@ int or_step(osim* S, int32_t n) {
 /* ------------------------------------------------------------------------ */
 /* outputs                                                                     */
 /* counters: step, loaded, waiting, en_route, arrived, departed, vehicle_updates,
- * claims_lost, clamps */
+ * claims_lost, clamps, claims, claims_departure, lc_evaluated, claims_lane_change */
 void or_counters(const osim* S, int64_t* out) {
     out[0] = S->t;
     out[1] = S->ntrips;
@@ -1029,6 +1037,10 @@ void or_counters(const osim* S, int64_t* out) {
     out[6] = S->updates;
     out[7] = S->claims_lost;
     out[8] = S->clamps;
+    out[9] = S->claims;
+    out[10] = S->claims_dep;
+    out[11] = S->lc_evaluated;
+    out[12] = S->claims_lc;
 }
 
 static int cmp_vid(const void* a, const void* b) {

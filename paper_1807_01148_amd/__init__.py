@@ -55,7 +55,7 @@ class SimParams(ctypes.Structure):
 class SimStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("step", "loaded", "waiting", "en_route", "arrived", "departed",
                                               "vehicle_updates", "claims_lost", "clamps", "claims",
-                                              "claims_departure")]
+                                              "claims_departure", "lc_evaluated", "claims_lane_change")]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)

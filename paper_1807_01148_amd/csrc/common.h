@@ -26,7 +26,7 @@ constexpr int kSegStride = 32;  // ints from one segment counter to the next
 // The step's statistics are summed the same way: one line of kStatStride
 // counters per XCD (block b adds to line b % kSeg), folded into the Counters
 // when the step ends.
-enum : int { kStClamps = 0, kStArrived, kStGhost, kStLost, kStDepClaims, kStDeparted };
+enum : int { kStClamps = 0, kStArrived, kStGhost, kStLost, kStDepClaims, kStLcEval, kStLcClaims, kStDeparted };
 constexpr int kStatStride = 16;
 
 enum : int { kCross = 1, kChange = 2, kInsert = 3 };
@@ -42,6 +42,8 @@ struct Counters {
     unsigned epoch_next;  // epoch of the next step (set during the step, committed at its end)
     unsigned long long arrived, departed, updates, claims_lost, clamps, claims;
     unsigned long long claims_dep;  // of which departures (those counted without an entry included)
+    unsigned long long lc_eval;     // vehicles evaluated for a lane change
+    unsigned long long claims_lc;   // lane-change claims
 };
 
 struct Params {

@@ -30,7 +30,7 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 // ---------------------------------------------------------------------------
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
-                               unsigned long long tag, int i, int& clamps, int& arrivals) {
+                               unsigned long long tag, int i, int& clamps, int& arrivals, int& lc_listed) {
     const int k = in.key[i];
     const float x = in.x[i];
     const float v = in.v[i];
@@ -132,6 +132,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // link is listed for k_change, which evaluates the listed vehicles in
     // dense waves
     if (E.lanes < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
+    lc_listed += 1;
     LcRec r;
     r.i = i;
     r.meta = L.kind | (held ? 4 : 0);
@@ -150,7 +151,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // end, else the neighbours inside the band), gap acceptance, the safety
 // criterion for the new follower, the incentive criterion; the best candidate
 // claims its cells in the target lane.
-__device__ void change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
+__device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
                                Counters* ctr, int N, unsigned ep, unsigned long long tag, const LcRec& r) {
     const int i = r.i;
     const int k = in.key[i];
@@ -286,7 +287,9 @@ __device__ void change_vehicle(const Params& P, const Net& net, const Veh& in, c
         int lo, hi;
         claim_cells(P, net, e, ty, best_X, lo, hi);
         push_claim(s, net, (i / kBlock) & (kSeg - 1), tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+        return true;
     }
+    return false;
 }
 
 // Departures (Sec. 6.2.2): a due trip enters the first link of its route in
@@ -332,16 +335,18 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
     const int N = ctr->n;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
-    int clamps = 0, arrivals = 0;
+    int clamps = 0, arrivals = 0, listed = 0;
     if (tp.on && blockIdx.x == 0 && threadIdx.x == 0) *tp.n = N;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
-        decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals);
+        decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals, listed);
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
+    unsigned long long lw = wave_sum_u64((unsigned long long)listed);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         seg_stat(s, kStClamps, cw);
         seg_stat(s, kStArrived, aw);
+        seg_stat(s, kStLcEval, lw);
     }
 }
 
@@ -355,8 +360,11 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
     const int nb = gridDim.x / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
+    int claims = 0;
     for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock)
-        change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, seg[j]);
+        claims += change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, seg[j]) ? 1 : 0;
+    const unsigned long long cw = wave_sum_u64((unsigned long long)claims);
+    if ((threadIdx.x & (kWave - 1)) == 0) seg_stat(s, kStLcClaims, cw);
 }
 
 // departures: one thread per queue
@@ -718,6 +726,8 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
             ctr->claims_lost += v[kStLost];
             ctr->claims_dep += v[kStDepClaims];
             ctr->departed += v[kStDeparted];
+            ctr->lc_eval += v[kStLcEval];
+            ctr->claims_lc += v[kStLcClaims];
             ctr->n = ctr->n_next;
             ctr->t = ctr->t + 1;
             *s.epoch = ep;

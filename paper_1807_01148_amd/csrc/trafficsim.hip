@@ -938,6 +938,8 @@ int sim_stats(sim_t* S, sim_stats_t* host_out, int64_t* edge_count, int64_t* edg
         host_out->clamps = (int64_t)c.clamps;
         host_out->claims = (int64_t)c.claims;
         host_out->claims_departure = (int64_t)c.claims_dep;
+        host_out->lc_evaluated = (int64_t)c.lc_eval;
+        host_out->claims_lane_change = (int64_t)c.claims_lc;
     }
     return SIM_OK;
 }
@@ -1354,7 +1356,7 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     HIPCHECK(S, hipMemcpyAsync(st_save + 2 * (size_t)S->ne, S->s.st_us, eb, hipMemcpyDeviceToDevice, S->stream));
     const long long t_save = S->host_t;
     const int g0 = S->grid;
-    const int gcand[] = {g0 / 4, g0 / 2, g0, g0 * 2};
+    const int gcand[] = {g0 / 4, g0 / 2, g0 * 3 / 4, g0, g0 * 3 / 2, g0 * 2};
     const int scand[] = {2, 4, 8};
     hipEvent_t e0, e1;
     HIPCHECK(S, hipEventCreate(&e0));
