@@ -25,7 +25,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
-KERNELS = ("k_decide", "k_change", "k_insert", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
+KERNELS = ("k_decide", "k_change", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 class SimError(RuntimeError):
@@ -303,10 +303,11 @@ class Sim:
 
     def read_timing(self):
         """(sum of ms per kernel over sampled steps, number of sampled steps)."""
-        ms = np.zeros(len(KERNELS), np.float64)
+        # room for more kernels than this binding names (a newer library)
+        ms = np.zeros(max(32, len(KERNELS)), np.float64)
         n = ctypes.c_int64(0)
         self._check(self.lib.sim_read_timing(self.h, _p(ms), ctypes.byref(n)))
-        return dict(zip(KERNELS, ms.tolist())), int(n.value)
+        return dict(zip(KERNELS, ms[:len(KERNELS)].tolist())), int(n.value)
 
     def tape_begin(self, checkpoint_every: int = 60):
         """Start a differentiation window at the current step."""

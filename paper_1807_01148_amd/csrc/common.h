@@ -28,6 +28,9 @@ constexpr int kSegStride = 32;  // ints from one segment counter to the next
 // when the step ends.
 enum : int { kStClamps = 0, kStArrived, kStGhost, kStLost, kStDepClaims, kStLcEval, kStLcClaims, kStDeparted };
 constexpr int kStatStride = 16;
+// Coarse index of the sorted keys: lanes are grouped in blocks of
+// 2^kLaneBlkLog; lblk[b] is the first entry whose lane is in block b or later.
+constexpr int kLaneBlkLog = 6;
 
 enum : int { kCross = 1, kChange = 2, kInsert = 3 };
 
@@ -233,6 +236,8 @@ struct Scratch {
     unsigned long long* stop_req;   // per stop node: lowest (epoch, id) waiting at the line
     unsigned* epoch;  // executed-step counter (claims, scan statuses, lane index are tagged with it)
     LaneIx* lanes;  // per global lane: first and last entry in the sorted arrays
+    int* lblk;      // [nlblk + 1]: first entry of lane block b (lblk[nlblk] = entries)
+    int nlblk;      // lane blocks
 };
 
 // Event tape of one step (recorded during the adjoint's recompute pass): the

@@ -329,17 +329,35 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
     }
 }
 
+// The first qblocks blocks (a multiple of kSeg) take the departure queues, one
+// thread per queue; the others the vehicles on the road, one thread per
+// vehicle.  The two parts share nothing but the claim list.
 __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                                   Counters* ctr) {
+                                                   Counters* ctr, int qblocks) {
     const int t = ctr->t;
     const int N = ctr->n;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
+    if ((int)blockIdx.x < qblocks) {
+        int ghost = 0, issued = 0;
+        for (int q = blockIdx.x * kBlock + threadIdx.x; q < tr.nq; q += qblocks * kBlock)
+            decide_queue(P, net, tr, s, ctr, ep, tag, t, q, ghost, issued);
+        const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
+        const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            seg_stat(s, kStGhost, gw);
+            seg_stat(s, kStLost, gw);
+            seg_stat(s, kStDepClaims, iw);
+        }
+        return;
+    }
+    const int vb = blockIdx.x - qblocks;
+    const int G = gridDim.x - qblocks;
     int clamps = 0, arrivals = 0, listed = 0;
-    if (tp.on && blockIdx.x == 0 && threadIdx.x == 0) *tp.n = N;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
+    if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
+    for (int i = vb * kBlock + threadIdx.x; i < N; i += G * kBlock)
         decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals, listed);
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.stay[N] = 0;
+    if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
     unsigned long long lw = wave_sum_u64((unsigned long long)listed);
@@ -367,22 +385,6 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
     if ((threadIdx.x & (kWave - 1)) == 0) seg_stat(s, kStLcClaims, cw);
 }
 
-// departures: one thread per queue
-__global__ __launch_bounds__(kBlock) void k_insert(Params P, Net net, Trips tr, Scratch s, Counters* ctr) {
-    const int t = ctr->t;
-    const unsigned ep = *s.epoch;
-    const unsigned long long tag = epoch_tag(ep);
-    int ghost = 0, issued = 0;
-    for (int q = blockIdx.x * kBlock + threadIdx.x; q < tr.nq; q += gridDim.x * kBlock)
-        decide_queue(P, net, tr, s, ctr, ep, tag, t, q, ghost, issued);
-    const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
-    const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        seg_stat(s, kStGhost, gw);
-        seg_stat(s, kStLost, gw);
-        seg_stat(s, kStDepClaims, iw);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // k_resolve
@@ -428,7 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
             // occupied, else before the first entry of a later lane
             int lo, hi;
             int p = lane_range(s.lanes, key, ep, lo, hi) ? lb_x(in.x, lo, hi + 1, s.cl_X[ci])
-                                                         : lb_key(in.key, 0, N, key);
+                                                         : lb_key(in.key, s.lblk[key >> kLaneBlkLog],
+                                                                  s.lblk[(key >> kLaneBlkLog) + 1], key);
             s.mv_p[m] = p;
             s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
             if (kind == kCross) {
@@ -684,7 +687,12 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
     const int N = finalize ? ctr->n_next : ctr->n;
     const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock) {
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j <= N; j += gridDim.x * kBlock) {
+        // lane blocks from the one after entry j-1's to entry j's begin at j
+        const int b0 = j == 0 ? 0 : (buf.key[j - 1] >> kLaneBlkLog) + 1;
+        const int b1 = j == N ? s.nlblk : (buf.key[j] >> kLaneBlkLog);
+        for (int b = b0; b <= b1; ++b) s.lblk[b] = j;
+        if (j == N) continue;
         const int k = buf.key[j];
         if (net.ctrl) {  // waiting at the line of a free stop node: ask to be admitted next step
             const int e = buf.edge[j];

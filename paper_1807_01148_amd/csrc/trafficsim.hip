@@ -257,22 +257,22 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
     // kernels that read the per-XCD segments run a multiple of kSeg blocks
     const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg), gs8((S->grid_small + kSeg - 1) / kSeg * kSeg);
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
-    hipLaunchKernelGGL(k_decide, g, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
+    // departure queues first, in a multiple of kSeg blocks, then the vehicles
+    const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
+    hipLaunchKernelGGL(k_decide, dim3(qb + S->grid), b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr, qb);
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
     hipLaunchKernelGGL(k_change, g8, b, 0, S->stream, S->P, S->net, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-    hipLaunchKernelGGL(k_insert, dim3(S->grid_q), b, 0, S->stream, S->P, S->net, tr, sc, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
     hipLaunchKernelGGL(k_resolve, gs8, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
+    if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
     hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
+    if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
     hipLaunchKernelGGL(k_scatter, g8, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
+    if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
     hipLaunchKernelGGL(k_place, gs8, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
+    if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
     hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[8], S->stream));
+    if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
@@ -446,6 +446,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
         S->lane_base[e + 1] = S->lane_base[e] + S->lanes[e];
     }
     S->nlanes = S->lane_base[ne];
+    S->s.nlblk = (int)(((size_t)S->nlanes + (1u << kLaneBlkLog) - 1) >> kLaneBlkLog);
     S->ncells = cells;
 
     Params& P = S->P;
@@ -482,6 +483,7 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
               dalloc(S, S->d_cT, ncls) && dalloc(S, S->d_cA, 4 * (size_t)ncls) && dalloc(S, S->d_cKab, 4 * (size_t)ncls) &&
               dalloc(S, S->d_cVs, ncls) && dalloc(S, S->d_cB, ncls) && dalloc(S, S->d_epoch, 1) &&
               dalloc(S, S->s.lanes, (size_t)S->nlanes) &&
+              dalloc(S, S->s.lblk, ((size_t)S->nlanes >> kLaneBlkLog) + 2) &&
               dalloc(S, S->s.cells, (size_t)cells) && dalloc(S, S->s.st_cnt, ne) &&
               dalloc(S, S->s.st_steps, ne) && dalloc(S, S->s.st_us, ne) && dalloc(S, S->ctr, 1) &&
               dalloc(S, S->s.holder, nn) && dalloc(S, S->s.stop_req, nn) && dalloc(S, dummy, 1);
