@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_own(Params P, Net net, Tape tp, 
             lead = mode == kModeChange ? tp.clead[i] : tp.lead[i];
             const float xL = lead >= 0 ? tp.x[lead] : 0.0f;
             const float vL = lead >= 0 ? tp.v[lead] : 0.0f;
-            const float lL = lead >= 0 ? P.tlen[a.vtype[tp.vid[lead]]] : 0.0f;
+            const float lL = lead >= 0 ? by_type(P.tlen, a.vtype[tp.vid[lead]]) : 0.0f;
             const int c = net.cls[e];
             const int ty = a.vtype[vid], nt = P.nt;
             const float A = net.cA[c * nt + ty], T = net.cT[c], kab = net.cKab[c * nt + ty];

@@ -448,9 +448,19 @@ __device__ __forceinline__ unsigned long long epoch_tag(unsigned epoch) {
     return (unsigned long long)(0xFFFFFFFFu - epoch) << 32;
 }
 
+// a per-type constant, picked from registers (the table lives in the kernel
+// arguments; indexing it with a per-lane type would be a memory read)
+__device__ __forceinline__ float by_type(const float (&a)[4], int ty) {
+    float r = a[0];
+    r = ty == 1 ? a[1] : r;
+    r = ty == 2 ? a[2] : r;
+    r = ty == 3 ? a[3] : r;
+    return r;
+}
+
 __device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, int ty, float X, int& lo,
                                             int& hi) {
-    int a = (int)floorf(X - P.tclaim[ty]);
+    int a = (int)floorf(X - by_type(P.tclaim, ty));
     int b = (int)floorf(X);
     int nc = net.cr[edge].ncell;
     lo = a < 0 ? 0 : a;

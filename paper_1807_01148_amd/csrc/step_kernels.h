@@ -31,40 +31,55 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
                                unsigned long long tag, int i, int& clamps, int& arrivals, int& lc_listed) {
+    // Every read that does not depend on another is issued here, before the
+    // first branch: the own entry and the entry after it (its leader if it is
+    // in the same lane: same cache lines), then the records of the own link,
+    // the own type and the next link (the latter needed by the front vehicle
+    // of a lane and by a crossing).
     const int k = in.key[i];
     const float x = in.x[i];
     const float v = in.v[i];
     const int e = in.edge[i];
     const int nx = in.next[i];
-    const EdgeRec E = net.er[e];
-    const float len = E.len;
     const int ty = in.ty[i];
-    const float lme = P.tlen[ty];  // own length
+    const int vid = in.vid[i];
+    const int lcs = in.lc[i];
+    const int ia = i + 1 < N ? i + 1 : i;
+    const int ka = in.key[ia];
+    const float xa = in.x[ia], va = in.v[ia];
+    const int tya = in.ty[ia];
     const int nt = P.nt;
+    const EdgeRec E = net.er[e];
     const DrvRec D = net.drv[e * nt + ty];
+    const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
+    const float len = E.len;
+    const float lme = by_type(P.tlen, ty);  // own length
     const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
     const int lb = E.lane_base;
     const int l = k - lb;
 
     // own leader: next element of the lane, else the rearmost vehicle of the
     // mapped lane of the next link of the route
-    const int vid = in.vid[i];
     const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
     Lead L = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
-    if (i + 1 < N && in.key[i + 1] == k) {
-        float xl = in.x[i + 1];
-        L.kind = 1; L.xl = xl; L.vl = in.v[i + 1]; L.ll = P.tlen[in.ty[i + 1]]; L.s = (xl - L.ll) - x; L.idx = i + 1;
+    if (i + 1 < N && ka == k) {
+        L.kind = 1; L.xl = xa; L.vl = va; L.ll = by_type(P.tlen, tya); L.s = (xa - L.ll) - x; L.idx = i + 1;
     } else if (held) {
         L = stop_line_lead(len, x);
     } else if (nx >= 0) {
-        const EdgeRec E2 = net.er[nx];
         int nl2 = E2.lanes;
         int k2 = E2.lane_base + (l < nl2 - 1 ? l : nl2 - 1);
         int j, tyr;
         float xl, vr;
-        if (lane_rear(s.lanes, k2, ep, j, xl, vr, tyr)) {
-            L.kind = 2; L.xl = xl; L.vl = vr; L.ll = P.tlen[tyr]; L.s = (len - x) + (xl - L.ll); L.idx = j;
-        }
+        // selects, not a branch: the lane record is then read whole at once
+        const bool ok = lane_rear(s.lanes, k2, ep, j, xl, vr, tyr);
+        const float ll = by_type(P.tlen, tyr);
+        L.kind = ok ? 2 : 0;
+        L.xl = ok ? xl : 0.0f;
+        L.vl = ok ? vr : 0.0f;
+        L.ll = ok ? ll : 0.0f;
+        L.s = ok ? (len - x) + (xl - ll) : 0.0f;
+        L.idx = ok ? j : -1;
     }
     int own_fl = lead_flags(L);
     const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
@@ -112,7 +127,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             arrivals += 1;
             return;
         }
-        int nl2 = net.er[nx].lanes;
+        int nl2 = E2.lanes;
         int tl = l < nl2 - 1 ? l : nl2 - 1;
         float X = xs - len;
         int lo, hi;
@@ -131,7 +146,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // lane change (Sec. 6.3.2): a vehicle past the cool-down on a multi-lane
     // link is listed for k_change, which evaluates the listed vehicles in
     // dense waves
-    if (E.lanes < 2 || (t - in.lc[i]) < P.lc_cool || x < lme) return;
+    if (E.lanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
     lc_listed += 1;
     LcRec r;
     r.i = i;
@@ -153,6 +168,9 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // claims its cells in the target lane.
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
                                Counters* ctr, int N, unsigned ep, unsigned long long tag, const LcRec& r) {
+    // independent reads first (as in decide_vehicle): the own entry and the
+    // one behind it (its follower if in the same lane), then the records of
+    // the own link, the types involved and the next link
     const int i = r.i;
     const int k = in.key[i];
     const float x = in.x[i];
@@ -161,11 +179,18 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
     const int nx = in.next[i];
     const int ty = in.ty[i];
     const int vid = in.vid[i];
-    const EdgeRec E = net.er[e];
-    const float len = E.len;
-    const float lme = P.tlen[ty];
+    const int ib = i > 0 ? i - 1 : i;
+    const int kb = in.key[ib];
+    const float xb = in.x[ib], vb = in.v[ib];
+    const int tyb = in.ty[ib];
     const int nt = P.nt;
+    const EdgeRec E = net.er[e];
     const DrvRec D = net.drv[e * nt + ty];
+    const DrvRec Db = net.drv[e * nt + tyb];
+    const int m = net.cr[e].m;
+    const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
+    const float len = E.len;
+    const float lme = by_type(P.tlen, ty);
     const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
     const int lb = E.lane_base;
     const int l = k - lb;
@@ -176,7 +201,6 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
         const int r0 = E.r0;
-        const int m = net.cr[e].m;
         int j = nx - r0;
         blo = (j * n) / m;
         bhi = ((j + 1) * n + m - 1) / m - 1;
@@ -196,10 +220,9 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             cand[nc++] = sd;
         }
     }
-    const bool hasF = i > 0 && in.key[i - 1] == k;
-    const float xF = hasF ? in.x[i - 1] : 0.0f;
-    const float vF = hasF ? in.v[i - 1] : 0.0f;
-    const int tyF = hasF ? in.ty[i - 1] : 0;
+    const bool hasF = i > 0 && kb == k;
+    const float xF = hasF ? xb : 0.0f;
+    const float vF = hasF ? vb : 0.0f;
 
     int best = -1, best_fl = 0, best_lead = -1;
     float best_inc = 0.0f, best_X = 0.0f, best_v = 0.0f;
@@ -214,19 +237,23 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
         if (occ && j <= thi) {
             float xl = in.x[j];
-            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.ll = P.tlen[in.ty[j]]; Lt.s = (xl - Lt.ll) - x; Lt.idx = j;
+            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.ll = by_type(P.tlen, in.ty[j]); Lt.s = (xl - Lt.ll) - x;
+            Lt.idx = j;
         } else if (held) {
             Lt = stop_line_lead(len, x);
         } else if (nx >= 0) {
-            const EdgeRec E2 = net.er[nx];
             int nl2 = E2.lanes;
             int k2 = E2.lane_base + (lt < nl2 - 1 ? lt : nl2 - 1);
             int j2, tyr;
             float xl, vr;
-            if (lane_rear(s.lanes, k2, ep, j2, xl, vr, tyr)) {
-                Lt.kind = 2; Lt.xl = xl; Lt.vl = vr; Lt.ll = P.tlen[tyr];
-                Lt.s = (len - x) + (xl - Lt.ll); Lt.idx = j2;
-            }
+            const bool ok = lane_rear(s.lanes, k2, ep, j2, xl, vr, tyr);
+            const float ll = by_type(P.tlen, tyr);
+            Lt.kind = ok ? 2 : 0;
+            Lt.xl = ok ? xl : 0.0f;
+            Lt.vl = ok ? vr : 0.0f;
+            Lt.ll = ok ? ll : 0.0f;
+            Lt.s = ok ? (len - x) + (xl - ll) : 0.0f;
+            Lt.idx = ok ? j2 : -1;
         }
         const bool hasFt = occ && j - 1 >= tlo;
         const float xFt = hasFt ? in.x[j - 1] : 0.0f;
@@ -263,8 +290,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             float d2 = hasFt ? (ant - an) : 0.0f;
             float d3 = 0.0f;
             if (hasF) {
-                const DrvRec Df = net.drv[e * nt + tyF];
-                const float Af = Df.A, kf = Df.kab, ivf = Df.iv;
+                const float Af = Db.A, kf = Db.kab, ivf = Db.iv;
                 Lead Lo = {1, (x - lme) - xF, v, x, i, lme};
                 float ao = idm_acc(P, Af, T, kf, ivf, vF, Lo);
                 float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(P, len, L, xF));
@@ -316,13 +342,14 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
     for (int l = 0; l < E0.lanes; ++l) {
         int jl, tyr;
         float xr, vr;
-        float sp = lane_rear(s.lanes, E0.lane_base + l, ep, jl, xr, vr, tyr) ? (xr - P.tlen[tyr]) : E0.len;
+        float sp = lane_rear(s.lanes, E0.lane_base + l, ep, jl, xr, vr, tyr) ? (xr - by_type(P.tlen, tyr)) : E0.len;
         if (best < 0 || sp > bsp) { best = l; bsp = sp; }
     }
-    if (bsp >= P.tclaim[ty]) {
+    if (bsp >= by_type(P.tclaim, ty)) {
         int lo, hi;
-        claim_cells(P, net, e0, ty, P.tlen[ty], lo, hi);
-        push_claim(s, net, (q / kBlock) & (kSeg - 1), tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best, P.tlen[ty],
+        claim_cells(P, net, e0, ty, by_type(P.tlen, ty), lo, hi);
+        push_claim(s, net, (q / kBlock) & (kSeg - 1), tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best,
+                   by_type(P.tlen, ty),
                    0.0f, 1.0f, lo, hi);
         ghost += tl - h - 1;
         issued += tl - h;
