@@ -484,7 +484,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "simulated_steps": [c0["step"], c1["step"]],
                    "vehicle_updates": upd, "claims": claims, "claims_crossing": claims_cross,
-                   "claims_lane_change": lc_claims, "en_route_end": c1["en_route"],
+                   "claims_lane_change": lc_claims,
+                   "lc_evaluated": c1["lc_evaluated"] - c0["lc_evaluated"], "en_route_end": c1["en_route"],
                    "arrived_end": c1["arrived"], "parallelism": "single GPU"},
         "roofline": roofline,
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

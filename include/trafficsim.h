@@ -269,9 +269,10 @@ int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
 int sim_step_graph(sim_t* sim, int32_t num_steps, int32_t chunk);
 
 /* Time `steps_per_trial` steps for each candidate launch shape, all from the
- * current state, then restore that state (vehicles, counters, statistics,
- * per-trip outcomes) and keep the fastest shape.  Outputs the shape and its
- * time per step (ms).  Allocates a copy of the state.  Synchronises. */
+ * current state (every candidate twice), then restore that state (vehicles,
+ * counters, statistics, per-trip outcomes) and keep the fastest shape.
+ * Outputs the shape and its time per step (ms).  Allocates a copy of the
+ * state.  Synchronises. */
 int sim_autotune(sim_t* sim, int32_t steps_per_trial, int32_t* best_grid, int32_t* best_small, float* best_ms);
 
 /* Route subsequent work to another HIP stream. */

@@ -1368,6 +1368,9 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     float best = 1e30f;
     int bg = S->grid, bs = S->grid_small;
     const Tape off{};
+    // two passes over the candidates; a shape's time is the faster of its two
+    // trials (the fastest over all trials wins)
+    for (int pass = 0; pass < 2; ++pass)
     for (int gc : gcand) {
         if (gc < 1) continue;
         for (int sd : scand) {
