@@ -181,18 +181,10 @@ __device__ __forceinline__ bool lane_rear(const LaneIx* __restrict__ lanes, int 
     return (unsigned)w.x == ep;
 }
 
-// A vehicle that may change lanes this step, listed by k_decide for k_change:
-// its entry index, its own-lane acceleration and its own leader (kind in bits
-// 0-1 of meta, bit 2 set when its movement at the link end is held).
-struct __align__(16) LcRec {
-    int i, meta;
-    float ac;
-    int lidx;
-    float ls, lxl, lvl, lll;
-};
-
 struct Scratch {
-    LcRec* lc;    // kSeg segments of lc_seg records
+    // vehicles listed for the lane-change evaluation: entry index, bit 31 set
+    // when the vehicle's movement at the link end is held this step
+    int* lc;      // kSeg segments of lc_seg entries
     int* lcnt;    // their counters, kSegStride ints apart
     int lc_seg;
     int* ccnt;    // counters of the kSeg segments of the claim list (cl_*)

@@ -28,6 +28,35 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
+// Own leader: the next entry if it is in the same lane (ka, xa, va, tya), else
+// the stop line if the movement at the link end is held, else the rearmost
+// vehicle of the mapped lane of the next link of the route (E2), if any.
+__device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, unsigned ep, int i, int N, int k,
+                                           float x, float len, int l, bool held, int nx, const EdgeRec& E2, int ka,
+                                           float xa, float va, int tya) {
+    Lead L = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
+    if (i + 1 < N && ka == k) {
+        L.kind = 1; L.xl = xa; L.vl = va; L.ll = by_type(P.tlen, tya); L.s = (xa - L.ll) - x; L.idx = i + 1;
+    } else if (held) {
+        L = stop_line_lead(len, x);
+    } else if (nx >= 0) {
+        int nl2 = E2.lanes;
+        int k2 = E2.lane_base + (l < nl2 - 1 ? l : nl2 - 1);
+        int j, tyr;
+        float xl, vr;
+        // selects, not a branch: the lane record is then read whole at once
+        const bool ok = lane_rear(s.lanes, k2, ep, j, xl, vr, tyr);
+        const float ll = by_type(P.tlen, tyr);
+        L.kind = ok ? 2 : 0;
+        L.xl = ok ? xl : 0.0f;
+        L.vl = ok ? vr : 0.0f;
+        L.ll = ok ? ll : 0.0f;
+        L.s = ok ? (len - x) + (xl - ll) : 0.0f;
+        L.idx = ok ? j : -1;
+    }
+    return L;
+}
+
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
                                unsigned long long tag, int i, int& clamps, int& arrivals, int& lc_listed) {
@@ -58,29 +87,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const int lb = E.lane_base;
     const int l = k - lb;
 
-    // own leader: next element of the lane, else the rearmost vehicle of the
-    // mapped lane of the next link of the route
     const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
-    Lead L = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
-    if (i + 1 < N && ka == k) {
-        L.kind = 1; L.xl = xa; L.vl = va; L.ll = by_type(P.tlen, tya); L.s = (xa - L.ll) - x; L.idx = i + 1;
-    } else if (held) {
-        L = stop_line_lead(len, x);
-    } else if (nx >= 0) {
-        int nl2 = E2.lanes;
-        int k2 = E2.lane_base + (l < nl2 - 1 ? l : nl2 - 1);
-        int j, tyr;
-        float xl, vr;
-        // selects, not a branch: the lane record is then read whole at once
-        const bool ok = lane_rear(s.lanes, k2, ep, j, xl, vr, tyr);
-        const float ll = by_type(P.tlen, tyr);
-        L.kind = ok ? 2 : 0;
-        L.xl = ok ? xl : 0.0f;
-        L.vl = ok ? vr : 0.0f;
-        L.ll = ok ? ll : 0.0f;
-        L.s = ok ? (len - x) + (xl - ll) : 0.0f;
-        L.idx = ok ? j : -1;
-    }
+    Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
     int own_fl = lead_flags(L);
     const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
     float dx, vn;
@@ -148,17 +156,8 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // dense waves
     if (E.lanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
     lc_listed += 1;
-    LcRec r;
-    r.i = i;
-    r.meta = L.kind | (held ? 4 : 0);
-    r.ac = ac;
-    r.lidx = L.idx;
-    r.ls = L.s;
-    r.lxl = L.xl;
-    r.lvl = L.vl;
-    r.lll = L.ll;
     const int q = (i / kBlock) & (kSeg - 1);  // the same for the whole wave
-    s.lc[(size_t)q * s.lc_seg + wave_slot(s.lcnt + q * kSegStride)] = r;
+    s.lc[(size_t)q * s.lc_seg + wave_slot(s.lcnt + q * kSegStride)] = (int)((unsigned)i | (held ? 0x80000000u : 0u));
 }
 
 // Lane-change evaluation of one listed vehicle (Sec. 6.3.2): candidate lanes
@@ -167,11 +166,12 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // criterion for the new follower, the incentive criterion; the best candidate
 // claims its cells in the target lane.
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               Counters* ctr, int N, unsigned ep, unsigned long long tag, const LcRec& r) {
+                               Counters* ctr, int N, unsigned ep, unsigned long long tag, int rec) {
     // independent reads first (as in decide_vehicle): the own entry and the
-    // one behind it (its follower if in the same lane), then the records of
-    // the own link, the types involved and the next link
-    const int i = r.i;
+    // ones behind and ahead of it (follower and leader if in the same lane),
+    // then the records of the own link, the types involved and the next link
+    const int i = rec & 0x7FFFFFFF;
+    const bool held = rec < 0;
     const int k = in.key[i];
     const float x = in.x[i];
     const float v = in.v[i];
@@ -183,6 +183,10 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
     const int kb = in.key[ib];
     const float xb = in.x[ib], vb = in.v[ib];
     const int tyb = in.ty[ib];
+    const int ia = i + 1 < N ? i + 1 : i;
+    const int ka = in.key[ia];
+    const float xa = in.x[ia], va = in.v[ia];
+    const int tya = in.ty[ia];
     const int nt = P.nt;
     const EdgeRec E = net.er[e];
     const DrvRec D = net.drv[e * nt + ty];
@@ -194,9 +198,10 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
     const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
     const int lb = E.lane_base;
     const int l = k - lb;
-    const bool held = (r.meta & 4) != 0;
-    const Lead L = {r.meta & 3, r.ls, r.lvl, r.lxl, r.lidx, r.lll};
-    const float ac = r.ac;
+    // the own leader and own-lane acceleration, as k_decide found them
+    const Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
+    int own_fl = lead_flags(L);
+    const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
     const int n = E.lanes;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
     const int N = ctr->n;
     const int q = blockIdx.x & (kSeg - 1);
     const int M = s.lcnt[q * kSegStride];
-    const LcRec* seg = s.lc + (size_t)q * s.lc_seg;
+    const int* seg = s.lc + (size_t)q * s.lc_seg;
     const int nb = gridDim.x / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
