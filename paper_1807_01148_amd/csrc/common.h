@@ -16,11 +16,12 @@ constexpr int kLcNone = -(1 << 30);
 constexpr int kMaxGrid = 2048;
 // A list that every wave of a step may append to (lane-change candidates,
 // claims) is split into kSeg segments with one counter each, in lines of their
-// own: the entries of 256-vehicle (or 256-queue) chunk c go to segment
-// c % kSeg.  With a grid that is a multiple of kSeg, chunk c is handled by a
-// block on XCD c % kSeg, so the appends of one XCD meet one counter and stay
-// in that XCD's L2; one counter for the whole chip would serialise every
-// wave's append.
+// own.  Blocks are dispatched to the XCDs in turn, so block b runs on XCD
+// b % kSeg: the vehicle blocks of XCD q take the q-th eighth of the sorted
+// entries (in 256-entry chunks) and append to segment q, and departure queue
+// chunk c (256 queues) appends to segment c % kSeg.  The appends of one XCD
+// meet one counter and stay in its L2; one counter for the whole chip would
+// serialise every wave's append.
 constexpr int kSeg = 8;
 constexpr int kSegStride = 32;  // ints from one segment counter to the next
 // The step's statistics are summed the same way: one line of kStatStride

@@ -59,7 +59,8 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
 
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
-                               unsigned long long tag, int i, int& clamps, int& arrivals, int& lc_listed) {
+                               unsigned long long tag, int i, int seg, int& clamps, int& arrivals,
+                               int& lc_listed) {
     // Every read that does not depend on another is issued here, before the
     // first branch: the own entry and the entry after it (its leader if it is
     // in the same lane: same cache lines), then the records of the own link,
@@ -143,7 +144,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
-        push_claim(s, net, (i / kBlock) & (kSeg - 1), tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
+        push_claim(s, net, seg, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
         return;
     }
     s.xs[i] = xs;
@@ -156,8 +157,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // dense waves
     if (E.lanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
     lc_listed += 1;
-    const int q = (i / kBlock) & (kSeg - 1);  // the same for the whole wave
-    s.lc[(size_t)q * s.lc_seg + wave_slot(s.lcnt + q * kSegStride)] = (int)((unsigned)i | (held ? 0x80000000u : 0u));
+    s.lc[(size_t)seg * s.lc_seg + wave_slot(s.lcnt + seg * kSegStride)] = (int)((unsigned)i | (held ? 0x80000000u : 0u));
 }
 
 // Lane-change evaluation of one listed vehicle (Sec. 6.3.2): candidate lanes
@@ -166,7 +166,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // criterion for the new follower, the incentive criterion; the best candidate
 // claims its cells in the target lane.
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               Counters* ctr, int N, unsigned ep, unsigned long long tag, int rec) {
+                               Counters* ctr, int N, unsigned ep, unsigned long long tag, int rec, int seg) {
     // independent reads first (as in decide_vehicle): the own entry and the
     // ones behind and ahead of it (follower and leader if in the same lane),
     // then the records of the own link, the types involved and the next link
@@ -317,7 +317,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         }
         int lo, hi;
         claim_cells(P, net, e, ty, best_X, lo, hi);
-        push_claim(s, net, (i / kBlock) & (kSeg - 1), tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+        push_claim(s, net, seg, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
         return true;
     }
     return false;
@@ -383,12 +383,21 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
         }
         return;
     }
+    // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
+    // the q-th eighth of the sorted entries, 256-entry chunks in order, so
+    // that the link and lane records of neighbouring vehicles are shared in
+    // that XCD's L2; q is also the segment of every list entry they append
     const int vb = blockIdx.x - qblocks;
-    const int G = gridDim.x - qblocks;
+    const int per = (gridDim.x - qblocks) / kSeg;
+    const int q = vb & (kSeg - 1);
+    const int nch = (N + kBlock - 1) / kBlock;
+    const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
     int clamps = 0, arrivals = 0, listed = 0;
     if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
-    for (int i = vb * kBlock + threadIdx.x; i < N; i += G * kBlock)
-        decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, clamps, arrivals, listed);
+    for (int c = (int)(((long long)nch * q) / kSeg) + vb / kSeg; c < c_end; c += per) {
+        const int i = c * kBlock + threadIdx.x;
+        if (i < N) decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, q, clamps, arrivals, listed);
+    }
     if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
@@ -406,13 +415,13 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
     const int N = ctr->n;
     const int q = blockIdx.x & (kSeg - 1);
     const int M = s.lcnt[q * kSegStride];
-    const int* seg = s.lc + (size_t)q * s.lc_seg;
+    const int* list = s.lc + (size_t)q * s.lc_seg;
     const int nb = gridDim.x / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
     int claims = 0;
     for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock)
-        claims += change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, seg[j]) ? 1 : 0;
+        claims += change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, list[j], q) ? 1 : 0;
     const unsigned long long cw = wave_sum_u64((unsigned long long)claims);
     if ((threadIdx.x & (kWave - 1)) == 0) seg_stat(s, kStLcClaims, cw);
 }

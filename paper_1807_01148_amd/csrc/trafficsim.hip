@@ -259,7 +259,7 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
-    hipLaunchKernelGGL(k_decide, dim3(qb + S->grid), b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr, qb);
+    hipLaunchKernelGGL(k_decide, dim3(qb + g8.x), b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr, qb);
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
     hipLaunchKernelGGL(k_change, g8, b, 0, S->stream, S->P, S->net, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
@@ -719,7 +719,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
              dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap) && dalloc(S, V.ty, cap);
     }
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
-    // segment q holds the candidates of chunks q, q + kSeg, ... of kBlock entries
+    // segment q holds the candidates of one eighth of the chunks of kBlock entries
     s.lc_seg = (int)(((size_t)(cap + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
     // a claim segment also takes the departures of queue chunks q, q + kSeg, ...
     s.cl_seg = s.lc_seg + (int)(((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
