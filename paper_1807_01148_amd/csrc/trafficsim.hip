@@ -818,8 +818,10 @@ int sim_step(sim_t* S, int32_t num_steps) {
         if (timed) {
             for (int q = 0; q <= SIM_NUM_KERNELS; ++q) {
                 if (S->ev_free.empty()) {
+                    // timing only: no system-scope fence, so that recording the
+                    // event does not add a cache write-back to the kernel's time
                     hipEvent_t e;
-                    HIPCHECK(S, hipEventCreate(&e));
+                    HIPCHECK(S, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                     S->ev_free.push_back(e);
                 }
                 ev[q] = S->ev_free.back();
