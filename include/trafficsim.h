@@ -222,6 +222,46 @@ int sim_set_timing(sim_t* sim, int32_t every);
  * *samples; the sampled events are released. */
 int sim_read_timing(sim_t* sim, double* kernel_ms, int64_t* samples);
 
+/* State views, checkpoint and resume.
+ *
+ * The vehicles on the road at the current step, as DEVICE arrays owned by the
+ * handle (valid until the next call that advances or replaces the state),
+ * num_vehicles entries each, sorted by (key, x): key = global lane id =
+ * lane_base[edge] + lane, where lane_base is the exclusive prefix sum of the
+ * lanes of the edges in edge-id order; x = front-bumper position from the link
+ * start (m); v = speed (m/s); edge; vid = vehicle id (rank of the trip by
+ * (departure step, trip index)); type = vehicle type. */
+typedef struct {
+    int64_t step;
+    int32_t num_vehicles;
+    const int32_t* key;
+    const float* x;
+    const float* v;
+    const int32_t* edge;
+    const int32_t* vid;
+    const uint8_t* type;
+} sim_state_view;
+
+/* Size in bytes of a state image of this handle (after sim_load_demand). */
+int sim_state_bytes(sim_t* sim, size_t* bytes);
+
+/* Fill *out with the current step, vehicle count and views; if image is not
+ * NULL, also copy the whole dynamic state into it: DEVICE memory of
+ * sim_state_bytes bytes, owned by the caller (vehicles, departure queues,
+ * counters, stop-node holders, per-trip outcomes, emissions and link
+ * statistics; not the utilization samples).  Synchronises.
+ * Errors: SIM_EINVAL (null out), SIM_ESTATE (no demand), SIM_EHIP. */
+int sim_get_state(sim_t* sim, sim_state_view* out, void* image);
+
+/* Replace the dynamic state by an image (DEVICE, `bytes` bytes) written by
+ * sim_get_state of this handle or of another one created with the same
+ * network, parameters, vehicle types and demand; the simulation continues from
+ * the image's step exactly as the one that wrote it would.  Synchronises.
+ * Errors: SIM_EINVAL (null, wrong size or an image of a different
+ * simulation), SIM_ESTATE (no demand, or inside a differentiation window),
+ * SIM_EHIP. */
+int sim_set_state(sim_t* sim, const void* image, size_t bytes);
+
 /* Start a differentiation window at the current step: subsequent sim_step
  * calls save a full-state checkpoint every `checkpoint_every` steps (device
  * memory, ~44 B x trips each).  At most 16 link classes.  Errors: SIM_EINVAL,

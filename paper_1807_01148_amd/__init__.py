@@ -24,7 +24,8 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_read_trips", "sim_set_idm", "sim_set_timing", "sim_read_timing", "sim_tape_begin",
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
-            "sim_set_vehicle_types", "sim_set_control", "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
+            "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
 KERNELS = ("k_decide", "k_change", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -50,6 +51,11 @@ class SimParams(ctypes.Structure):
                 ("idm", ctypes.c_void_p), ("mobil_p", ctypes.c_float), ("mobil_athr", ctypes.c_float),
                 ("mobil_bsafe", ctypes.c_float), ("mand_dist", ctypes.c_float),
                 ("lc_cooldown_steps", ctypes.c_int32)]
+
+
+class SimStateView(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("num_vehicles", ctypes.c_int32)] + \
+               [(n, ctypes.c_void_p) for n in ("key", "x", "v", "edge", "vid", "type")]
 
 
 class SimStats(ctypes.Structure):
@@ -103,6 +109,12 @@ def library(path: str = LIB_PATH):
         lib.sim_set_vehicle_types.restype = ctypes.c_int
         lib.sim_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
         lib.sim_set_control.restype = ctypes.c_int
+        lib.sim_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        lib.sim_state_bytes.restype = ctypes.c_int
+        lib.sim_get_state.argtypes = [P, ctypes.POINTER(SimStateView), P]
+        lib.sim_get_state.restype = ctypes.c_int
+        lib.sim_set_state.argtypes = [P, P, ctypes.c_size_t]
+        lib.sim_set_state.restype = ctypes.c_int
         lib.sim_set_stream.argtypes = [P, P]
         lib.sim_set_stream.restype = ctypes.c_int
         lib.sim_destroy.argtypes = [P]
@@ -271,6 +283,29 @@ class Sim:
         out = {k: a[:m][o] for k, a in iv.items()}
         out.update({k: a[:m][o] for k, a in fv.items()})
         return out
+
+    def state_view(self) -> SimStateView:
+        """Step, vehicle count and DEVICE pointers of the current vehicle arrays."""
+        v = SimStateView()
+        self._check(self.lib.sim_get_state(self.h, ctypes.byref(v), None))
+        return v
+
+    def save_state(self):
+        """The whole dynamic state as a uint8 tensor on the device (a checkpoint)."""
+        import torch
+        nb = ctypes.c_size_t(0)
+        self._check(self.lib.sim_state_bytes(self.h, ctypes.byref(nb)))
+        img = torch.empty(nb.value, dtype=torch.uint8, device="cuda:%d" % self.device)
+        self.stream.synchronize()  # the tensor's memory is ready before the library's stream writes it
+        v = SimStateView()
+        self._check(self.lib.sim_get_state(self.h, ctypes.byref(v), ctypes.c_void_p(img.data_ptr())))
+        return img
+
+    def load_state(self, img):
+        """Continue from a checkpoint written by save_state (this simulation or
+        another one with the same network, parameters, types and demand)."""
+        self.stream.synchronize()
+        self._check(self.lib.sim_set_state(self.h, ctypes.c_void_p(img.data_ptr()), img.numel()))
 
     def trips(self) -> dict:
         da = np.zeros(self.num_trips, np.int32)

@@ -998,6 +998,124 @@ int sim_read_trips(sim_t* S, int32_t* depart_actual, int32_t* arrive_step) {
     return SIM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// state image: a header, then the sections below, each 256-byte aligned
+// ---------------------------------------------------------------------------
+namespace {
+constexpr unsigned long long kStateMagic = 0x3154415453534D54ull;  // "TMSSTAT1"
+struct StateHdr {
+    unsigned long long magic;
+    long long step, cap, nq, nn, ne, ntrips, bytes;
+};
+struct StateLayout {
+    size_t veh[13];
+    size_t q, ctr, hold, trip[4], st[3], total;
+};
+StateLayout state_layout(const sim_t* S) {
+    StateLayout L{};
+    size_t o = 256;  // the header
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = (o + bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t n = (size_t)S->cap;
+    for (int f = 0; f < 12; ++f) L.veh[f] = take(4 * n);
+    L.veh[12] = take(n);
+    L.q = take(sizeof(int) * 2 * (size_t)S->tr.nq);
+    L.ctr = take(sizeof(Counters));
+    L.hold = take(sizeof(int) * (size_t)S->nn);
+    for (int f = 0; f < 4; ++f) L.trip[f] = take(4 * n);
+    for (int f = 0; f < 3; ++f) L.st[f] = take(sizeof(unsigned long long) * (size_t)S->ne);
+    L.total = o;
+    return L;
+}
+// the 13 vehicle arrays of a buffer, in image order
+void veh_fields(const Veh& V, void* f[13]) {
+    void* a[13] = {V.key, V.x, V.v, V.edge, V.rcur, V.next, V.lc, V.kin, V.phin, V.vid, V.fuel, V.co, V.ty};
+    for (int i = 0; i < 13; ++i) f[i] = a[i];
+}
+}  // namespace
+
+int sim_state_bytes(sim_t* S, size_t* bytes) {
+    if (!S || !bytes) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    *bytes = state_layout(S).total;
+    return SIM_OK;
+}
+
+int sim_get_state(sim_t* S, sim_state_view* out, void* image) {
+    if (!S || !out) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    const Veh& V = S->buf[S->host_t & 1];
+    if (image) {
+        const StateLayout L = state_layout(S);
+        char* img = static_cast<char*>(image);
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        const size_t n = (size_t)S->cap;
+        void* f[13];
+        veh_fields(V, f);
+        for (int i = 0; i < 13; ++i) HIPCHECK(S, hipMemcpyAsync(img + L.veh[i], f[i], i < 12 ? 4 * n : n, k, S->stream));
+        if (S->tr.nq) HIPCHECK(S, hipMemcpyAsync(img + L.q, S->qstate, sizeof(int) * 2 * (size_t)S->tr.nq, k, S->stream));
+        HIPCHECK(S, hipMemcpyAsync(img + L.ctr, S->ctr, sizeof(Counters), k, S->stream));
+        HIPCHECK(S, hipMemcpyAsync(img + L.hold, S->s.holder, sizeof(int) * (size_t)S->nn, k, S->stream));
+        const void* tf[4] = {S->tr.depart_actual, S->tr.arrive_step, S->tr.fuel_total, S->tr.co_total};
+        for (int i = 0; i < 4; ++i) HIPCHECK(S, hipMemcpyAsync(img + L.trip[i], tf[i], 4 * n, k, S->stream));
+        const void* sf[3] = {S->s.st_cnt, S->s.st_steps, S->s.st_us};
+        for (int i = 0; i < 3; ++i)
+            HIPCHECK(S, hipMemcpyAsync(img + L.st[i], sf[i], sizeof(unsigned long long) * (size_t)S->ne, k, S->stream));
+        const StateHdr h{kStateMagic, S->host_t, S->cap, S->tr.nq, S->nn, S->ne, S->ntrips, (long long)L.total};
+        HIPCHECK(S, hipMemcpyAsync(img, &h, sizeof(h), hipMemcpyHostToDevice, S->stream));
+        HIPCHECK(S, hipStreamSynchronize(S->stream));  // before h goes out of scope
+    }
+    Counters c{};
+    HIPCHECK(S, hipMemcpyAsync(&c, S->ctr, sizeof(Counters), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    out->step = S->host_t;
+    out->num_vehicles = c.n;
+    out->key = V.key;
+    out->x = V.x;
+    out->v = V.v;
+    out->edge = V.edge;
+    out->vid = V.vid;
+    out->type = V.ty;
+    return SIM_OK;
+}
+
+int sim_set_state(sim_t* S, const void* image, size_t bytes) {
+    if (!S || !image) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (S->tape_on || S->adj_ready) return fail(S, SIM_ESTATE, "no state replacement inside a differentiation window");
+    const StateLayout L = state_layout(S);
+    if (bytes != L.total) return fail(S, SIM_EINVAL, "state image size does not match this simulation");
+    StateHdr h{};
+    HIPCHECK(S, hipMemcpyAsync(&h, image, sizeof(h), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    if (h.magic != kStateMagic || h.cap != S->cap || h.nq != S->tr.nq || h.nn != S->nn || h.ne != S->ne ||
+        h.ntrips != S->ntrips || h.bytes != (long long)L.total || h.step < 0)
+        return fail(S, SIM_EINVAL, "not a state image of this simulation");
+    const char* img = static_cast<const char*>(image);
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    const size_t n = (size_t)S->cap;
+    const int p = (int)(h.step & 1);
+    void* f[13];
+    veh_fields(S->buf[p], f);
+    for (int i = 0; i < 13; ++i) HIPCHECK(S, hipMemcpyAsync(f[i], img + L.veh[i], i < 12 ? 4 * n : n, k, S->stream));
+    if (S->tr.nq) HIPCHECK(S, hipMemcpyAsync(S->qstate, img + L.q, sizeof(int) * 2 * (size_t)S->tr.nq, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->ctr, img + L.ctr, sizeof(Counters), k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->s.holder, img + L.hold, sizeof(int) * (size_t)S->nn, k, S->stream));
+    void* tf[4] = {S->tr.depart_actual, S->tr.arrive_step, S->tr.fuel_total, S->tr.co_total};
+    for (int i = 0; i < 4; ++i) HIPCHECK(S, hipMemcpyAsync(tf[i], img + L.trip[i], 4 * n, k, S->stream));
+    void* sf[3] = {S->s.st_cnt, S->s.st_steps, S->s.st_us};
+    for (int i = 0; i < 3; ++i)
+        HIPCHECK(S, hipMemcpyAsync(sf[i], img + L.st[i], sizeof(unsigned long long) * (size_t)S->ne, k, S->stream));
+    S->host_t = h.step;
+    int rc = reindex(S, S->buf[p], S->s, S->ctr);
+    if (rc) return rc;
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
 int sim_read_emissions(sim_t* S, float* fuel, float* co) {
     if (!S) return SIM_EINVAL;
     if (!S->loaded || S->ntrips == 0) return SIM_OK;
