@@ -341,6 +341,24 @@ def bench_reroute(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_ceiling(nbytes=1 << 29, reps=5):
+    """Device-to-device copy bandwidth on this GPU (read + write bytes per
+    second, GB/s), the practical ceiling for a streaming kernel."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def copy_calibration(args):
     """A plain device-to-device copy of 1 GiB, five times: the reference
     dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters (each copy
@@ -473,10 +491,17 @@ def main():
     alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
     achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     step_achieved = (B_PER_VEH * upd + B_PER_EVENT * claims) / secs / 1e9
+    traffic = measured_traffic() if dom == "k_decide" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic() if dom == "k_decide" else None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": alg_bytes,
                 "sampled_steps": samples}
+    if traffic and avg[dom] > 0:
+        # the measured HBM bytes over the same launch time, and their ratio to the algorithmic bytes
+        roofline["traffic_gbs"] = traffic / (avg[dom] * 1e-3) / 1e9
+        roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
+        roofline["amplification"] = traffic / alg_bytes
+    roofline["copy_ceiling_gbs"] = copy_ceiling()
     out = {
         "metric": METRIC, "value": value, "unit": "vehicle-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev_ms / args.steps,
