@@ -345,7 +345,7 @@ __device__ __forceinline__ int clamp_to_leader(const Lead& L, float& dx, float& 
     return clamp_to_leader_fl(L, dx, vn, fl);
 }
 
-__device__ __forceinline__ Lead relead(const Params& P, float len, const Lead& L, float xf) {
+__device__ __forceinline__ Lead relead(float len, const Lead& L, float xf) {
     Lead R = L;
     if (L.kind == 1) R.s = (L.xl - L.ll) - xf;
     else if (L.kind == 2) R.s = (len - xf) + (L.xl - L.ll);

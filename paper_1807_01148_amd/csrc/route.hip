@@ -248,7 +248,7 @@ __global__ void k_tile_sums(const long long* len, int n, long long* tsum) {
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) tsum[blockIdx.x] = red[0];
@@ -266,7 +266,7 @@ __global__ void k_scan_tiles(long long* tsum, int ntiles) {
         buf[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < kBlock; o <<= 1) {
-            long long y = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            long long y = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
             __syncthreads();
             buf[threadIdx.x] += y;
             __syncthreads();
@@ -292,7 +292,7 @@ __global__ void k_tile_apply(const long long* len, int n, const long long* toff,
     buf[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < kBlock; o <<= 1) {
-        long long y = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+        long long y = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
         __syncthreads();
         buf[threadIdx.x] += y;
         __syncthreads();

@@ -58,9 +58,8 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
 }
 
 __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                               const Scratch& s, const Tape& tp, Counters* ctr, int N, int t, unsigned ep,
-                               unsigned long long tag, int i, int seg, int& clamps, int& arrivals,
-                               int& lc_listed) {
+                               const Scratch& s, const Tape& tp, int N, int t, unsigned ep, unsigned long long tag,
+                               int i, int seg, int& clamps, int& arrivals, int& lc_listed) {
     // Every read that does not depend on another is issued here, before the
     // first branch: the own entry and the entry after it (its leader if it is
     // in the same lane: same cache lines), then the records of the own link,
@@ -166,7 +165,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // criterion for the new follower, the incentive criterion; the best candidate
 // claims its cells in the target lane.
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               Counters* ctr, int N, unsigned ep, unsigned long long tag, int rec, int seg) {
+                               int N, unsigned ep, unsigned long long tag, int rec, int seg) {
     // independent reads first (as in decide_vehicle): the own entry and the
     // ones behind and ahead of it (follower and leader if in the same lane),
     // then the records of the own link, the types involved and the next link
@@ -279,7 +278,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         if (hasFt) {  // the lag follows with its own type's constants
             const DrvRec Df = net.drv[e * nt + tyFt];
             const float Af = Df.A, kf = Df.kab, ivf = Df.iv;
-            an = idm_acc(P, Af, T, kf, ivf, vFt, relead(P, len, Lt, xFt));
+            an = idm_acc(P, Af, T, kf, ivf, vFt, relead(len, Lt, xFt));
             Lead Li = {1, (x - lme) - xFt, v, x, i, lme};
             ant = idm_acc(P, Af, T, kf, ivf, vFt, Li);
             if (ant < -P.bsafe) continue;
@@ -298,7 +297,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
                 const float Af = Db.A, kf = Db.kab, ivf = Db.iv;
                 Lead Lo = {1, (x - lme) - xF, v, x, i, lme};
                 float ao = idm_acc(P, Af, T, kf, ivf, vF, Lo);
-                float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(P, len, L, xF));
+                float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(len, L, xF));
                 d3 = aot - ao;
             }
             inc = d1 + P.pol * (d2 + d3);
@@ -331,8 +330,8 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
 // queue's head (its lowest vehicle id) can win, and its claim blocks every
 // third claim any other member's would.  The head claims; the others are
 // counted as claims that lost.
-__device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, const Scratch& s, Counters* ctr,
-                             unsigned ep, unsigned long long tag, int t, int q, int& ghost, int& issued) {
+__device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, const Scratch& s, unsigned ep,
+                             unsigned long long tag, int t, int q, int& ghost, int& issued) {
     const int q0 = tr.qoff[q], qn = tr.qoff[q + 1] - q0;
     const int h = tr.qhead[q];
     int tl = tr.qtail[q];
@@ -373,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
     if ((int)blockIdx.x < qblocks) {
         int ghost = 0, issued = 0;
         for (int q = blockIdx.x * kBlock + threadIdx.x; q < tr.nq; q += qblocks * kBlock)
-            decide_queue(P, net, tr, s, ctr, ep, tag, t, q, ghost, issued);
+            decide_queue(P, net, tr, s, ep, tag, t, q, ghost, issued);
         const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
         const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
         if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -396,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
     if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
     for (int c = (int)(((long long)nch * q) / kSeg) + vb / kSeg; c < c_end; c += per) {
         const int i = c * kBlock + threadIdx.x;
-        if (i < N) decide_vehicle(P, net, tr, in, s, tp, ctr, N, t, ep, tag, i, q, clamps, arrivals, listed);
+        if (i < N) decide_vehicle(P, net, tr, in, s, tp, N, t, ep, tag, i, q, clamps, arrivals, listed);
     }
     if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
@@ -421,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
     const unsigned long long tag = epoch_tag(ep);
     int claims = 0;
     for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock)
-        claims += change_vehicle(P, net, in, s, tp, ctr, N, ep, tag, list[j], q) ? 1 : 0;
+        claims += change_vehicle(P, net, in, s, tp, N, ep, tag, list[j], q) ? 1 : 0;
     const unsigned long long cw = wave_sum_u64((unsigned long long)claims);
     if ((threadIdx.x & (kWave - 1)) == 0) seg_stat(s, kStLcClaims, cw);
 }
@@ -433,7 +432,6 @@ __global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Sc
 __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
                                                     Counters* ctr) {
     const int t = ctr->t;
-    const int N = ctr->n;
     const int seg = blockIdx.x & (kSeg - 1);  // the grid is a multiple of kSeg
     const int M = s.ccnt[seg * kSegStride];
     const int nb = gridDim.x / kSeg;
