@@ -49,7 +49,8 @@ typedef void (*sim_free_fn)(void* ctx, void* ptr);
 
 /* Road network (Sec. 6.2.1): directed multigraph in CSR form by tail node.
  * Edge id == CSR position.  All arrays are HOST memory.
- *   row_ptr   [num_nodes+1]  row_ptr[0] = 0, row_ptr[num_nodes] = num_edges
+ *   row_ptr   [num_nodes+1]  row_ptr[0] = 0, row_ptr[num_nodes] = num_edges,
+ *                            non-decreasing, at most 32767 out-links per node
  *   col_idx   [num_edges]    head node of each edge (self-loops allowed)
  *   lanes     [num_edges]    1..8
  *   length_m  [num_edges]    >= veh_length + s0

@@ -71,8 +71,14 @@ struct __align__(16) EdgeRec {
     int lanes;
     int r0;  // first out-link of the head node
 };
-struct __align__(16) DrvRec {  // per (link, vehicle type)
-    float iv, A, T, kab;       // 1/v0, acceleration, time gap, 1/(2 sqrt(ab))
+// Per (link, vehicle type): what a vehicle needs of its own link, in one
+// 32-byte record (one cache line): the driver constants and the link fields.
+struct __align__(32) DrvRec {
+    float iv, A, T, kab;  // 1/v0, acceleration, time gap, 1/(2 sqrt(ab))
+    float len;
+    int lane_base;
+    int lanes_m;          // lanes | (out-degree of the head node) << 16
+    int r0;               // first out-link of the head node
 };
 struct __align__(16) ClaimRec {
     long long cbase;  // first claim cell of lane 0

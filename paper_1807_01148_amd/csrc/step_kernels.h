@@ -78,13 +78,13 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const float xa = in.x[ia], va = in.v[ia];
     const int tya = in.ty[ia];
     const int nt = P.nt;
-    const EdgeRec E = net.er[e];
     const DrvRec D = net.drv[e * nt + ty];
     const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
-    const float len = E.len;
+    const float len = D.len;
     const float lme = by_type(P.tlen, ty);  // own length
     const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
-    const int lb = E.lane_base;
+    const int lb = D.lane_base;
+    const int nlanes = D.lanes_m & 0xFFFF;
     const int l = k - lb;
 
     const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
@@ -154,7 +154,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     // lane change (Sec. 6.3.2): a vehicle past the cool-down on a multi-lane
     // link is listed for k_change, which evaluates the listed vehicles in
     // dense waves
-    if (E.lanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
+    if (nlanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
     lc_listed += 1;
     s.lc[(size_t)seg * s.lc_seg + wave_slot(s.lcnt + seg * kSegStride)] = (int)((unsigned)i | (held ? 0x80000000u : 0u));
 }
@@ -187,24 +187,23 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
     const float xa = in.x[ia], va = in.v[ia];
     const int tya = in.ty[ia];
     const int nt = P.nt;
-    const EdgeRec E = net.er[e];
     const DrvRec D = net.drv[e * nt + ty];
     const DrvRec Db = net.drv[e * nt + tyb];
-    const int m = net.cr[e].m;
+    const int m = D.lanes_m >> 16;
     const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
-    const float len = E.len;
+    const float len = D.len;
     const float lme = by_type(P.tlen, ty);
     const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
-    const int lb = E.lane_base;
+    const int lb = D.lane_base;
     const int l = k - lb;
     // the own leader and own-lane acceleration, as k_decide found them
     const Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
     int own_fl = lead_flags(L);
     const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
-    const int n = E.lanes;
+    const int n = D.lanes_m & 0xFFFF;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
-        const int r0 = E.r0;
+        const int r0 = D.r0;
         int j = nx - r0;
         blo = (j * n) / m;
         bhi = ((j + 1) * n + m - 1) / m - 1;

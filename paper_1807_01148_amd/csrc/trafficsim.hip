@@ -231,7 +231,11 @@ int upload_idm(sim_t* S, const float* idm) {
     for (int e = 0; e < S->ne; ++e)
         for (int k = 0; k < nt; ++k) {
             const size_t ck = (size_t)S->cls[e] * nt + k;
-            drv[(size_t)e * nt + k] = DrvRec{inv[(size_t)e * nt + k], A[ck], T[S->cls[e]], K[ck]};
+            const int h = S->col_idx[e];
+            drv[(size_t)e * nt + k] = DrvRec{inv[(size_t)e * nt + k], A[ck], T[S->cls[e]], K[ck], S->len[e],
+                                             S->lane_base[e],
+                                             S->lanes[e] | ((S->row_ptr[h + 1] - S->row_ptr[h]) << 16),
+                                             S->row_ptr[h]};
         }
     HIPCHECK(S, hipMemcpyAsync(S->d_drv, drv.data(), sizeof(DrvRec) * drv.size(), h, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->d_capV, capV.data(), capV.size(), h, S->stream));
@@ -426,8 +430,14 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
     S->lane_base.resize(ne + 1);
     S->ncell.resize(ne);
     S->tail.resize(ne);
-    for (int u = 0; u < nn; ++u)
+    for (int u = 0; u < nn; ++u) {
+        if (S->row_ptr[u + 1] - S->row_ptr[u] > 32767) {  // packed beside the lane count in the link records
+            int code = fail(S, SIM_EINVAL, "node " + std::to_string(u) + " has more than 32767 out-links");
+            delete S;
+            return code;
+        }
         for (int e = S->row_ptr[u]; e < S->row_ptr[u + 1]; ++e) S->tail[e] = u;
+    }
     std::vector<long long> cbase(ne);
     S->lane_base[0] = 0;
     long long cells = 0;
