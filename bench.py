@@ -81,6 +81,20 @@ def workload(name):
     return s, desc
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "available_cores": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The FP32 oracle, single-threaded, on a bounded sample of the metro
     workload: the metro network with a synthetic ~1M-vehicle snapshot
@@ -102,7 +116,8 @@ def cpu_baseline(seconds_budget=20.0):
     upd = o.counters()["vehicle_updates"]
     return {"value": upd / el, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",
             "sample": "FP32 C oracle, 1 thread, metro network (1M nodes / 2.5M links) with a synthetic "
-                      "snapshot of %d placed vehicles, %d steps, %.1f s" % (scen["demand"]["init_x"].size, steps, el)}
+                      "snapshot of %d placed vehicles, %d steps, %.1f s" % (scen["demand"]["init_x"].size, steps, el),
+            "host": host_cpu()}
 
 
 def ensemble_scenarios(seed=1811, n=64, steps=3600):
@@ -336,7 +351,7 @@ def bench_reroute(args):
                         "unit": "GB/s", "frac": rate * ne * B_PER_RELAX / 1e9 / HBM_PEAK_GBS, "traffic": None},
            "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "trees/s", "cores": 1, "kind": "oracle",
                             "sample": "binary-heap Dijkstra (int64) from %d origins of the workload, each "
-                                      "relaxing every link once" % len(sample)},
+                                      "relaxing every link once" % len(sample), "host": host_cpu()},
            "iterations": its}
     print(json.dumps(out), flush=True)
 
