@@ -545,12 +545,31 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
         const int base = tile * kScanTile + threadIdx.x * kScanItems;
         int vals[kScanItems];
         int tsum = 0;
-        for (int q = 0; q < kScanItems; ++q) {
-            int idx = base + q;
-            int w = 0;
-            if (idx < total) w = s.mcnt[idx] + (idx < N ? (int)s.stay[idx] : 0);
-            vals[q] = w;
-            tsum += w;
+        if (base + kScanItems <= total) {
+            // a whole run of 16: four 16-byte loads of the counts and one of the
+            // stay flags (stay[N] is 0)
+            const int4* m4 = reinterpret_cast<const int4*>(s.mcnt + base);
+            const uint4 st = *reinterpret_cast<const uint4*>(s.stay + base);
+            const unsigned sw[4] = {st.x, st.y, st.z, st.w};
+#pragma unroll
+            for (int h = 0; h < kScanItems / 4; ++h) {
+                const int4 m = m4[h];
+                const int mm[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int w = mm[r] + (int)((sw[h] >> (8 * r)) & 0xFFu);
+                    vals[4 * h + r] = w;
+                    tsum += w;
+                }
+            }
+        } else {
+            for (int q = 0; q < kScanItems; ++q) {
+                int idx = base + q;
+                int w = 0;
+                if (idx < total) w = s.mcnt[idx] + (idx < N ? (int)s.stay[idx] : 0);
+                vals[q] = w;
+                tsum += w;
+            }
         }
         int agg;
         int excl = block_excl_scan(tsum, agg);
@@ -597,10 +616,27 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
         }
         __syncthreads();
         int run = s_prefix + excl;
-        for (int q = 0; q < kScanItems; ++q) {
-            int idx = base + q;
-            if (idx < total) s.cscan[idx] = run;
-            run += vals[q];
+        if (base + kScanItems <= total) {
+            int4* c4 = reinterpret_cast<int4*>(s.cscan + base);
+#pragma unroll
+            for (int h = 0; h < kScanItems / 4; ++h) {
+                int4 o;
+                o.x = run;
+                run += vals[4 * h];
+                o.y = run;
+                run += vals[4 * h + 1];
+                o.z = run;
+                run += vals[4 * h + 2];
+                o.w = run;
+                run += vals[4 * h + 3];
+                c4[h] = o;
+            }
+        } else {
+            for (int q = 0; q < kScanItems; ++q) {
+                int idx = base + q;
+                if (idx < total) s.cscan[idx] = run;
+                run += vals[q];
+            }
         }
     }
 }
