@@ -767,22 +767,26 @@ __global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Sc
         const int b1 = j == N ? s.nlblk : (buf.key[j] >> kLaneBlkLog);
         for (int b = b0; b <= b1; ++b) s.lblk[b] = j;
         if (j == N) continue;
+        // the entry and its neighbours' lanes, read before any branch
         const int k = buf.key[j];
+        const int kp = buf.key[j > 0 ? j - 1 : j];
+        const int kn = buf.key[j + 1 < N ? j + 1 : j];
+        const int tyj = buf.ty[j];
+        const float xj = buf.x[j], vj = buf.v[j];
         if (net.ctrl) {  // waiting at the line of a free stop node: ask to be admitted next step
             const int e = buf.edge[j];
             const int h = net.head[e];
-            if (net.ctrl[h] == 1 && buf.next[j] >= 0 && s.holder[h] == -1 && (net.len[e] - buf.x[j]) <= P.stop_dist &&
-                buf.v[j] <= P.stop_speed)
+            if (net.ctrl[h] == 1 && buf.next[j] >= 0 && s.holder[h] == -1 && (net.len[e] - xj) <= P.stop_dist &&
+                vj <= P.stop_speed)
                 atomicMin(s.stop_req + h, tag | (unsigned)buf.vid[j]);
         }
-        if (j == 0 || buf.key[j - 1] != k) {
-            s.lanes[k].lo = j;
-            s.lanes[k].ty = buf.ty[j];
-            s.lanes[k].x = buf.x[j];
-            s.lanes[k].v = buf.v[j];
-            s.lanes[k].ep = ep;
+        LaneIx* lx = s.lanes + k;
+        if (j == 0 || kp != k) {  // the lane's rearmost entry: epoch and first entry, type, position and speed
+            *reinterpret_cast<uint2*>(&lx->ep) = make_uint2(ep, (unsigned)j);
+            lx->ty = tyj;
+            *reinterpret_cast<float2*>(&lx->x) = make_float2(xj, vj);
         }
-        if (j == N - 1 || buf.key[j + 1] != k) s.lanes[k].hi = j;
+        if (j == N - 1 || kn != k) lx->hi = j;
     }
     if (finalize && blockIdx.x == 0 && threadIdx.x < kWave) {
         // fold the per-XCD lines into the counters (lane q reads line q) and
