@@ -443,19 +443,29 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
     int lost = 0, departed = 0;
     for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
         const int ci = seg * s.cl_seg + j;
+        // the claim's fields, then everything they point to, before any branch:
+        // the target link's records, the target lane's index record and key
+        // block bounds (for the gap), the source vehicle's link and entry time
         const int vid = s.cl_vid[ci];
         const int tedge = s.cl_tedge[ci];
         const int key = s.cl_key[ci];
+        const int clo = s.cl_lo[ci], chi = s.cl_hi[ci];
+        const int kind = s.cl_kind[ci];
+        const int src = s.cl_src[ci];
+        const float cX = s.cl_X[ci], cf = s.cl_f[ci];
         const int tl = key - net.er[tedge].lane_base;
         const ClaimRec C = net.cr[tedge];
+        int lo, hi;
+        const bool occ = lane_range(s.lanes, key, ep, lo, hi);
+        const int kb0 = s.lblk[key >> kLaneBlkLog], kb1 = s.lblk[(key >> kLaneBlkLog) + 1];
+        const int sx = src >= 0 ? src : 0;
+        const int se = in.edge[sx], skin = in.kin[sx];
+        const float sphin = in.phin[sx];
+        // ownership of every claimed cell (all read at once: no early exit)
         const unsigned long long* cell = s.cells + C.cbase + (long long)tl * C.ncell;
         const unsigned long long mine = tag | (unsigned)vid;
         bool win = true;
-        for (int c = s.cl_lo[ci]; c <= s.cl_hi[ci]; ++c) {
-            if (cell[c] != mine) { win = false; break; }
-        }
-        const int kind = s.cl_kind[ci];
-        const int src = s.cl_src[ci];
+        for (int c = clo; c <= chi; ++c) win &= cell[c] == mine;
         if (tp.on && src >= 0) {
             if (kind == kCross) tp.mode[src] = win ? kModeCross : kModeYield;
             else tp.mode[src] = win ? kModeChange : kModeStay;
@@ -466,16 +476,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
             s.mv_claim[m] = ci;
             // its gap in the sorted order: inside its lane's run if the lane is
             // occupied, else before the first entry of a later lane
-            int lo, hi;
-            int p = lane_range(s.lanes, key, ep, lo, hi) ? lb_x(in.x, lo, hi + 1, s.cl_X[ci])
-                                                         : lb_key(in.key, s.lblk[key >> kLaneBlkLog],
-                                                                  s.lblk[(key >> kLaneBlkLog) + 1], key);
+            const int p = occ ? lb_x(in.x, lo, hi + 1, cX) : lb_key(in.key, kb0, kb1, key);
             s.mv_p[m] = p;
             s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
             if (kind == kCross) {
-                record_exit(P, s, in.edge[src], in.kin[src], in.phin[src], s.cl_f[ci], t);
+                record_exit(P, s, se, skin, sphin, cf, t);
                 if (net.ctrl) {  // reaching the next link frees a stop node
-                    const int h = net.head[in.edge[src]];
+                    const int h = net.head[se];
                     if (s.holder[h] == vid) s.holder[h] = -1;
                 }
             }
@@ -695,10 +702,24 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
         const int m = seg * s.cl_seg + jm;
         const int ci = s.mv_claim[m];
         const int p = s.mv_p[m];
-        const int b = s.cscan[p];
         const int g = s.mv_g[m];
+        // reads in three dependent rounds, each issued before any branch: the
+        // claim and its gap; the source vehicle's fields and the trip's; the
+        // route's next link
+        const int b = s.cscan[p];
         const int key = s.cl_key[ci];
         const float X = s.cl_X[ci];
+        const int kind = s.cl_kind[ci];
+        const int src = s.cl_src[ci];
+        const int vid = s.cl_vid[ci];
+        const float cv = s.cl_v[ci];
+        const int cedge = s.cl_tedge[ci];
+        const float cf = s.cl_f[ci];
+        const int sx = src >= 0 ? src : 0;
+        const float sfu = in.fuel[sx], sco = in.co[sx], sv = in.v[sx];
+        const int srcur = in.rcur[sx], snext = in.next[sx], slc = in.lc[sx], skin = in.kin[sx];
+        const float sphin = in.phin[sx];
+        const int vty = tr.vtype[vid], rend = tr.rend[vid], rbeg = tr.rbeg[vid];
         int r = 0;
         if (g > 1) {
             for (int q = 0; q < g; ++q) {
@@ -707,45 +728,35 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
             }
         }
         const int j = b + r;
-        const int kind = s.cl_kind[ci];
-        const int src = s.cl_src[ci];
-        const int vid = s.cl_vid[ci];
         if (tp.on && src >= 0) tp.next[src] = j;
         out.key[j] = key;
         out.x[j] = X;
-        out.v[j] = s.cl_v[ci];
-        out.edge[j] = s.cl_tedge[ci];
+        out.v[j] = cv;
+        out.edge[j] = cedge;
         out.vid[j] = vid;
-        out.ty[j] = tr.vtype[vid];
+        out.ty[j] = vty;
         if (src >= 0) {
-            float fu = in.fuel[src], co = in.co[src];
-            emissions(P, in.v[src], s.cl_v[ci], fu, co);
+            float fu = sfu, co = sco;
+            emissions(P, sv, cv, fu, co);
             out.fuel[j] = fu;
             out.co[j] = co;
         } else {
             out.fuel[j] = 0.0f;
             out.co[j] = 0.0f;
         }
-        if (kind == kCross) {
-            const int rc = in.rcur[src] + 1;
-            out.rcur[j] = rc;
-            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
-            out.lc[j] = in.lc[src];
-            out.kin[j] = t + 1;
-            out.phin[j] = s.cl_f[ci];
-        } else if (kind == kChange) {
-            out.rcur[j] = in.rcur[src];
-            out.next[j] = in.next[src];
+        if (kind == kChange) {
+            out.rcur[j] = srcur;
+            out.next[j] = snext;
             out.lc[j] = t;
-            out.kin[j] = in.kin[src];
-            out.phin[j] = in.phin[src];
-        } else {
-            const int rc = tr.rbeg[vid];
+            out.kin[j] = skin;
+            out.phin[j] = sphin;
+        } else {  // a crossing enters the next link of its route, a departure the first
+            const int rc = kind == kCross ? srcur + 1 : rbeg;
             out.rcur[j] = rc;
-            out.next[j] = (rc + 1 < tr.rend[vid]) ? tr.route_edges[rc + 1] : -1;
-            out.lc[j] = lc_none;
+            out.next[j] = (rc + 1 < rend) ? tr.route_edges[rc + 1] : -1;
+            out.lc[j] = kind == kCross ? slc : lc_none;
             out.kin[j] = t + 1;
-            out.phin[j] = 1.0f;
+            out.phin[j] = kind == kCross ? cf : 1.0f;
         }
         s.mcnt[p] = 0;
     }
