@@ -267,13 +267,13 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
     if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
     hipLaunchKernelGGL(k_change, g8, b, 0, S->stream, S->P, S->net, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-    hipLaunchKernelGGL(k_resolve, gs8, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
+    hipLaunchKernelGGL(k_resolve, g8, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
     hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
     hipLaunchKernelGGL(k_scatter, g8, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-    hipLaunchKernelGGL(k_place, gs8, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
+    hipLaunchKernelGGL(k_place, g8, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
     if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
     hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
     if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
