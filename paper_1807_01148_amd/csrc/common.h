@@ -457,11 +457,10 @@ __device__ __forceinline__ float by_type(const float (&a)[4], int ty) {
     return r;
 }
 
-__device__ __forceinline__ void claim_cells(const Params& P, const Net& net, int edge, int ty, float X, int& lo,
-                                            int& hi) {
+// cells [lo, hi] of a lane of nc cells that a front at X claims for type ty
+__device__ __forceinline__ void claim_cells(const Params& P, int nc, int ty, float X, int& lo, int& hi) {
     int a = (int)floorf(X - by_type(P.tclaim, ty));
     int b = (int)floorf(X);
-    int nc = net.cr[edge].ncell;
     lo = a < 0 ? 0 : a;
     hi = b > nc - 1 ? nc - 1 : b;
 }
@@ -485,14 +484,18 @@ __device__ __forceinline__ void seg_stat(const Scratch& s, int what, unsigned lo
     if (v) atomicAdd(s.sstat + (blockIdx.x & (kSeg - 1)) * kStatStride + what, v);
 }
 
-// A claim goes to segment seg (the same for the whole wave) of the claim list.
-__device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, int seg, unsigned long long tag,
-                                           int vid, int kind, int src, int tedge, int tlane, float X, float vc,
-                                           float f, int lo, int hi) {
+// A claim on lane tlane of link tedge (claim record C, first global lane
+// lane_base) takes its cells, then a slot in segment seg (the same for the
+// whole wave) of the claim list.
+__device__ __forceinline__ void push_claim(const Scratch& s, const ClaimRec& C, int lane_base, int seg,
+                                           unsigned long long tag, int vid, int kind, int src, int tedge, int tlane,
+                                           float X, float vc, float f, int lo, int hi) {
+    unsigned long long* cell = s.cells + C.cbase + (long long)tlane * C.ncell;
+    const unsigned long long mine = tag | (unsigned)vid;
+    for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
     const int ci = seg * s.cl_seg + wave_slot(s.ccnt + seg * kSegStride);
     s.cl_vid[ci] = vid;
-    const ClaimRec C = net.cr[tedge];
-    s.cl_key[ci] = net.er[tedge].lane_base + tlane;
+    s.cl_key[ci] = lane_base + tlane;
     s.cl_lo[ci] = lo;
     s.cl_hi[ci] = hi;
     s.cl_src[ci] = src;
@@ -501,9 +504,6 @@ __device__ __forceinline__ void push_claim(const Scratch& s, const Net& net, int
     s.cl_X[ci] = X;
     s.cl_v[ci] = vc;
     s.cl_f[ci] = f;
-    unsigned long long* cell = s.cells + C.cbase + (long long)tlane * C.ncell;
-    unsigned long long mine = tag | (unsigned)vid;
-    for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
 }
 
 __device__ __forceinline__ void record_exit(const Params& P, const Scratch& s, int edge, int kin,

@@ -139,11 +139,12 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         int tl = l < nl2 - 1 ? l : nl2 - 1;
         float X = xs - len;
         int lo, hi;
-        claim_cells(P, net, nx, ty, X, lo, hi);
+        const ClaimRec C2 = net.cr[nx];
+        claim_cells(P, C2.ncell, ty, X, lo, hi);
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
-        push_claim(s, net, seg, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
+        push_claim(s, C2, E2.lane_base, seg, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
         return;
     }
     s.xs[i] = xs;
@@ -314,8 +315,9 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             tp.clead[i] = best_lead;
         }
         int lo, hi;
-        claim_cells(P, net, e, ty, best_X, lo, hi);
-        push_claim(s, net, seg, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+        const ClaimRec C = net.cr[e];
+        claim_cells(P, C.ncell, ty, best_X, lo, hi);
+        push_claim(s, C, lb, seg, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
         return true;
     }
     return false;
@@ -350,8 +352,9 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
     }
     if (bsp >= by_type(P.tclaim, ty)) {
         int lo, hi;
-        claim_cells(P, net, e0, ty, by_type(P.tlen, ty), lo, hi);
-        push_claim(s, net, (q / kBlock) & (kSeg - 1), tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best,
+        const ClaimRec C = net.cr[e0];
+        claim_cells(P, C.ncell, ty, by_type(P.tlen, ty), lo, hi);
+        push_claim(s, C, E0.lane_base, (q / kBlock) & (kSeg - 1), tag, tr.qvid[q0 + h], kInsert, -2 - q, e0, best,
                    by_type(P.tlen, ty),
                    0.0f, 1.0f, lo, hi);
         ghost += tl - h - 1;
@@ -655,25 +658,30 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
 __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
     const int N = ctr->n;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-        if (s.stay[i]) {
-            const int j = s.cscan[i] + s.mcnt[i];
-            if (tp.on) tp.next[i] = j;
-            out.key[j] = in.key[i];
-            out.x[j] = s.xs[i];
-            out.v[j] = s.vs[i];
-            out.edge[j] = in.edge[i];
-            out.rcur[j] = in.rcur[i];
-            out.next[j] = in.next[i];
-            out.lc[j] = in.lc[i];
-            out.kin[j] = in.kin[i];
-            out.phin[j] = in.phin[i];
-            out.vid[j] = in.vid[i];
-            out.ty[j] = in.ty[i];
-            float fu = in.fuel[i], co = in.co[i];
-            emissions(P, in.v[i], s.vs[i], fu, co);
-            out.fuel[j] = fu;
-            out.co[j] = co;
-        }
+        // every field read before the branch (almost every entry stays)
+        const bool st = s.stay[i] != 0;
+        const int j = s.cscan[i] + s.mcnt[i];
+        const int key = in.key[i], edge = in.edge[i], rcur = in.rcur[i], next = in.next[i], lc = in.lc[i];
+        const int kin = in.kin[i], vid = in.vid[i];
+        const unsigned char ty = in.ty[i];
+        const float xs = s.xs[i], vs = s.vs[i], v = in.v[i], phin = in.phin[i];
+        float fu = in.fuel[i], co = in.co[i];
+        if (!st) continue;
+        if (tp.on) tp.next[i] = j;
+        out.key[j] = key;
+        out.x[j] = xs;
+        out.v[j] = vs;
+        out.edge[j] = edge;
+        out.rcur[j] = rcur;
+        out.next[j] = next;
+        out.lc[j] = lc;
+        out.kin[j] = kin;
+        out.phin[j] = phin;
+        out.vid[j] = vid;
+        out.ty[j] = ty;
+        emissions(P, v, vs, fu, co);
+        out.fuel[j] = fu;
+        out.co[j] = co;
     }
     const int seg = blockIdx.x & (kSeg - 1);
     const int M = s.mvcnt[seg * kSegStride];
