@@ -298,8 +298,9 @@ int sim_load_demand_batch(sim_t* sim, int32_t n, const int32_t* num_trips, const
                           const int32_t* const* trip_route, const int32_t* num_routes,
                           const int64_t* const* route_ptr, const int32_t* const* route_edges);
 
-/* Launch shape: blocks of 256 threads for the per-vehicle kernels (grid) and
- * for the per-claim kernels (grid_small).  Results do not depend on it. */
+/* Launch shape: blocks of 256 threads for the per-vehicle, per-claim and
+ * per-mover kernels (grid) and for the persistent blocks of the step's scan
+ * (grid_small).  Results do not depend on it. */
 int sim_set_launch(sim_t* sim, int32_t grid, int32_t grid_small);
 int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
 

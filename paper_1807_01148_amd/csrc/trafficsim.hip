@@ -98,8 +98,8 @@ struct sim_t {
     int ntrips = 0;
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
-    int grid_small = 1;  // kernels that work on claims and movers (a few % of the vehicles)
-    int grid_q = 1;      // the departure kernel: one thread per queue
+    int grid_small = 1;  // k_scan's persistent blocks
+    int grid_q = 1;      // k_decide's departure-queue blocks: one thread per queue
     std::vector<int> h_rbeg;
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
@@ -259,7 +259,7 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     // kernels that read the per-XCD segments run a multiple of kSeg blocks
-    const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg), gs8((S->grid_small + kSeg - 1) / kSeg * kSeg);
+    const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg);
     if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
