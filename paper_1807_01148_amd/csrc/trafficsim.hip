@@ -2,27 +2,31 @@
 // as hand-written HIP for CDNA4 (gfx950).
 //
 // One synchronous step t -> t+1 (every decision reads state t only):
-//   k_decide   per vehicle: leader search, IDM acceleration (Sec. 6.3.2,
-//              car-following equation), ballistic update, link-end crossing or
-//              arrival (Sec. 6.3.1 routes), lane-change intent with gap
-//              acceptance (Sec. 6.3.2 lane changing / gap acceptance);
-//              per due trip (Sec. 6.2.2): entry-lane choice.  Crossings, lane
-//              changes and insertions claim one-metre cells of their target
+//   k_decide   first blocks, per departure queue (Sec. 6.2.2): release the
+//              trips due now, entry-lane choice, the head's entry claim.
+//              Other blocks, per vehicle: leader search, IDM acceleration
+//              (Sec. 6.3.2, car-following equation), ballistic update,
+//              link-end crossing (claim) or arrival (Sec. 6.3.1 routes);
+//              vehicles that may change lanes are listed.
+//   k_change   per listed vehicle: lane-change candidates, gap acceptance,
+//              safety and incentive (Sec. 6.3.2 lane changing); the best
+//              candidate claims.  Claims take one-metre cells of their target
 //              lane with a 64-bit atomicMin of (epoch, vehicle id).
 //   k_resolve  per claim: it wins iff it still owns all its cells (no
-//              overlapping claim with a lower id); winners locate their gap in
-//              the sorted order by binary search and take a slot in it.
+//              overlapping claim with a lower id); winners find their gap in
+//              the sorted order and take a slot in it.
 //   k_scan     exclusive scan (decoupled look-back) of stay[i] + movers-in-gap[i]
-//              gives every survivor and every mover its new position.
+//              gives every survivor and every gap its new position.
 //   k_scatter  survivors write their record to the new buffer; movers stage
 //              their (lane, x) keys per gap.
 //   k_place    movers rank themselves inside their gap and write their
-//              record; the last block advances the device-side counters.
+//              record.
+//   k_lanes    index the lanes of the new buffer; commit the step's counters.
 //
 // Vehicle state is structure-of-arrays, double-buffered, kept sorted by
 // (global lane id, position), so the vehicle ahead in the lane is the next
-// array element (coalesced) and the lane of another link is found by binary
-// search over the sorted keys.  The whole loop runs without host round trips.
+// array element (coalesced) and the run of any lane is one read of the lane
+// index.  The whole loop runs without host round trips.
 //
 // Floating point: built with -ffp-contract=off; every expression below is
 // evaluated in float in the order written (correctly rounded divide), so a
