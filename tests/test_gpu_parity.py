@@ -203,3 +203,19 @@ def test_errors_are_reported_not_fatal():
     with pytest.raises(P.SimError) as ei:
         P.Sim(bad)
     assert ei.value.code == P.SIM_EINVAL
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_widest_links_and_four_vehicle_types_every_step(seed):
+    """The largest values the step packs into its records: links of 1 to 8
+    lanes (8 being the maximum) and four vehicle types of different lengths
+    and caps, compared with the oracle at every step."""
+    probs = np.full(8, 1.0 / 8)
+    scen = tiny_grid(40 + seed, side=4, n_trips=160, horizon=40, lane_probs=tuple(probs), lognormal=(60.0, 0.3))
+    scen["params"]["vehicle_types"] = np.array([(5.0, np.inf, np.inf), (12.0, 0.8, 12.0), (7.5, 1.2, 20.0),
+                                               (3.0, np.inf, 9.0)], np.float32)
+    n = scen["demand"]["depart_step"].size
+    scen["demand"]["trip_type"] = np.random.default_rng(seed).integers(0, 4, n).astype(np.uint8)
+    assert scen["net"]["lanes"].max() == 8
+    g, o = lockstep(scen, 400, 1, "wide%d" % seed)
+    assert o.counters()["claims_lane_change"] > 0
