@@ -87,8 +87,11 @@ int rt_tree(rt_t* rt, int32_t src_node, int64_t* dist, int32_t* pred);
  * number of sources it searched from. */
 int rt_last_work(rt_t* rt, int64_t* relaxations, int32_t* sources);
 
-/* Largest number of origins searched at once (default: as many as fit in
- * 32 bytes x nodes x count <= 4 GiB).  Errors: SIM_EINVAL. */
+/* Largest number of origins searched at once.  Default: as many as fit in
+ * 32 bytes x nodes x count within a quarter of the device memory free at the
+ * plan (at least 4 GiB, at most 64 GiB), at most 4096, and count x nodes
+ * below 2^32.  Larger batches need fewer search rounds per plan.
+ * Errors: SIM_EINVAL. */
 int rt_set_batch(rt_t* rt, int32_t sources_per_batch);
 
 /* Band width of the search in ms (the search relaxes labels below a threshold

@@ -42,6 +42,8 @@ constexpr unsigned long long kUnreached = ~0ull;
 constexpr int kMaxGrid = 8192;
 constexpr int kScanTile = 2048;  // entries per block in the route-length scan
 constexpr int kRoundsPerCheck = 4;
+constexpr int kRelaxMaxGrid = 16384;
+constexpr int kMaxBatch = 4096;  // origins per search batch
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -102,13 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(const int* __restrict__ row_pt
     const unsigned mark = (unsigned)r + 1u;
     if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(r + 2) % 3] = 0u;
     unsigned long long done = 0;
-    for (unsigned q = blockIdx.x * kBlock + threadIdx.x; q < nin; q += gridDim.x * kBlock) {
+    for (unsigned long long q = blockIdx.x * kBlock + threadIdx.x; q < nin; q += gridDim.x * kBlock) {
         const unsigned long long i = fin[q];
         const long long u = (long long)(i % (unsigned long long)nn);
         const unsigned long long base = i - (unsigned long long)u;
         const unsigned long long d = key[i] >> kEdgeBits;
-        const int e1 = row_ptr[u + 1];
-        for (int e = row_ptr[u]; e < e1; ++e) {
+        const int e0 = row_ptr[u], e1 = row_ptr[u + 1];
+        for (int e = e0; e < e1; ++e) {
             const unsigned long long x = base + (unsigned long long)col[e];
             const unsigned long long nd = d + (unsigned long long)w[e];
             const unsigned long long old = atomicMin(key + x, (nd << kEdgeBits) | (unsigned long long)e);
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(const int* __restrict__ row_pt
                 }
             }
         }
-        done += (unsigned long long)(e1 - row_ptr[u]);
+        done += (unsigned long long)(e1 - e0);
     }
     done = wave_sum(done);
     if ((threadIdx.x & (kWave - 1)) == 0 && done) atomicAdd(work, done);
@@ -134,7 +136,7 @@ __global__ void k_split(const unsigned long long* key, unsigned* stamp, unsigned
                         int r, unsigned* far_out, unsigned* nfar_out) {
     const unsigned n = *nfar_in;
     unsigned* nnear = cnt + r % 3;
-    for (unsigned q = blockIdx.x * kBlock + threadIdx.x; q < n; q += gridDim.x * kBlock) {
+    for (unsigned long long q = blockIdx.x * kBlock + threadIdx.x; q < n; q += gridDim.x * kBlock) {
         const unsigned i = far_in[q];
         if ((key[i] >> kEdgeBits) < thr) {
             if (atomicExch(stamp + i, (unsigned)r) != (unsigned)r) fr[wave_slot(nnear)] = i;
@@ -419,11 +421,25 @@ int grid_for(long long n) {
 }
 
 int auto_batch(const rt_t* R) {
-    // key (8 B) + two stamps (8 B) + two frontier and two far entries (16 B) per (origin, node)
+    // key (8 B) + two stamps (8 B) + two frontier and two far entries (16 B)
+    // per (origin, node), within a quarter of the free device memory and at
+    // most 64 GiB: the more origins per batch, the fewer rounds per plan (the
+    // rounds of a batch follow the depth of the graph, not the origin count)
     const long long per = 32ll * R->nn;
-    long long b = (4ll << 30) / std::max<long long>(per, 1);
+    size_t free_b = 0, total_b = 0;
+    long long budget = 4ll << 30;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        budget = std::max<long long>(budget, std::min<long long>((long long)(free_b / 4), 64ll << 30));
+    long long b = budget / std::max<long long>(per, 1);
     b = std::min<long long>(b, (long long)(UINT32_MAX / (unsigned long long)R->nn));
-    return (int)std::max<long long>(1, std::min<long long>(b, 1024));
+    return (int)std::max<long long>(1, std::min<long long>(b, kMaxBatch));
+}
+
+// blocks for a relaxation round whose frontier was last seen at est entries:
+// room for four times that (it grows between checks); larger frontiers loop
+int relax_grid(unsigned long long est) {
+    const unsigned long long t = (4ull * std::max<unsigned long long>(est, 1ull) + kBlock - 1) / kBlock;
+    return (int)std::min<unsigned long long>(t, (unsigned long long)kRelaxMaxGrid);
 }
 
 int ensure_batch(rt_t* R, int B) {
@@ -461,13 +477,14 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
     const long long delta = R->delta > 0 ? R->delta : std::max<long long>(1, 3 * R->wsum / std::max(R->ne, 1));
     unsigned long long thr = (unsigned long long)delta;
     unsigned band = 1;
-    const int g = grid_for(n);
+    unsigned long long est = (unsigned long long)B;  // frontier size last seen (the seeds)
     int r = 0;
     long long launched = 0;
     for (;;) {
         // rounds of the current band until its frontier runs dry
         unsigned c[5];
         for (;;) {
+            const int g = relax_grid(est);
             for (int k = 0; k < kRoundsPerCheck; ++k, ++r) {
                 hipLaunchKernelGGL(k_relax, dim3(g), dim3(kBlock), 0, R->stream, R->d_row_ptr, R->d_col, R->d_w,
                                    R->d_key, R->d_stamp, (long long)R->nn, R->d_fr[r & 1], R->d_fr[(r + 1) & 1],
@@ -479,6 +496,7 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
             RCHECK(R, hipStreamSynchronize(R->stream));
             launched += kRoundsPerCheck;
             if (c[r % 3] == 0) break;  // the frontier the next round would read
+            est = c[r % 3];
             if (launched > 64ll * R->nn + 1024) return rfail(R, SIM_EHIP, "search did not converge");
         }
         if (c[3 + (band & 1)] == 0) break;  // nothing waits: every label is final
@@ -489,6 +507,7 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
                            R->d_stamp, R->d_fstamp, R->d_far[band & 1], R->d_cnt + 3 + (band & 1), thr, band + 1,
                            R->d_fr[r & 1], R->d_cnt, r, R->d_far[(band + 1) & 1], R->d_cnt + 3 + ((band + 1) & 1));
         RCHECK(R, hipGetLastError());
+        est = c[3 + (band & 1)];  // the new frontier is part of the far list
         ++band;
     }
     unsigned long long w = 0;
