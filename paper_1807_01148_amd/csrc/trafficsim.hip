@@ -32,6 +32,7 @@
 // evaluated in float in the order written (correctly rounded divide), so a
 // CPU float implementation of the same rules reproduces it bit for bit.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -107,7 +108,7 @@ struct sim_t {
     std::vector<int> h_rbeg;
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
-    std::vector<std::vector<hipEvent_t>> ev_steps;  // SIM_NUM_KERNELS + 1 events per sampled step
+    std::vector<std::vector<hipEvent_t>> ev_steps;  // a start and a stop event per kernel of a sampled step
 
     // differentiation window: checkpoints every `tape_every` steps from tape_t0
     struct Ckpt {
@@ -259,31 +260,34 @@ int h2d(sim_t* S, T* dst, const T* src, size_t n) {
 int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
 
 
+// With events (a sampled step), kernel q carries start event ev[2q] and stop
+// event ev[2q + 1], which take that kernel's own begin and end timestamps.
+#define STEP_LAUNCH(q, kern, grid, ...)                                                                   \
+    do {                                                                                                 \
+        if (ev)                                                                                          \
+            hipExtLaunchKernelGGL(kern, grid, b, 0, S->stream, ev[2 * (q)], ev[2 * (q) + 1], 0u, __VA_ARGS__); \
+        else                                                                                             \
+            hipLaunchKernelGGL(kern, grid, b, 0, S->stream, __VA_ARGS__);                               \
+    } while (0)
+
 int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     // kernels that read the per-XCD segments run a multiple of kSeg blocks
     const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[0], S->stream));
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
-    hipLaunchKernelGGL(k_decide, dim3(qb + g8.x), b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr, qb);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[1], S->stream));
-    hipLaunchKernelGGL(k_change, g8, b, 0, S->stream, S->P, S->net, in, sc, tp, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[2], S->stream));
-    hipLaunchKernelGGL(k_resolve, g8, b, 0, S->stream, S->P, S->net, tr, in, sc, tp, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[3], S->stream));
-    hipLaunchKernelGGL(k_scan, gs, b, 0, S->stream, sc, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[4], S->stream));
-    hipLaunchKernelGGL(k_scatter, g8, b, 0, S->stream, S->P, in, out, sc, tp, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[5], S->stream));
-    hipLaunchKernelGGL(k_place, g8, b, 0, S->stream, S->P, tr, in, out, sc, tp, kLcNone, ctr);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[6], S->stream));
-    hipLaunchKernelGGL(k_lanes, g, b, 0, S->stream, S->P, S->net, out, sc, ctr, 1);
-    if (ev) HIPCHECK(S, hipEventRecord(ev[7], S->stream));
+    STEP_LAUNCH(0, k_decide, dim3(qb + g8.x), S->P, S->net, tr, in, sc, tp, ctr, qb);
+    STEP_LAUNCH(1, k_change, g8, S->P, S->net, in, sc, tp, ctr);
+    STEP_LAUNCH(2, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
+    STEP_LAUNCH(3, k_scan, gs, sc, ctr);
+    STEP_LAUNCH(4, k_scatter, g8, S->P, in, out, sc, tp, ctr);
+    STEP_LAUNCH(5, k_place, g8, S->P, tr, in, out, sc, tp, kLcNone, ctr);
+    STEP_LAUNCH(6, k_lanes, g, S->P, S->net, out, sc, ctr, 1);
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
+#undef STEP_LAUNCH
 
 // index the lanes of a state that did not come from the previous step
 int reindex(sim_t* S, const Veh& buf, const Scratch& sc, Counters* ctr) {
@@ -827,15 +831,13 @@ int sim_step(sim_t* S, int32_t num_steps) {
             int rc = take_checkpoint(S, p);
             if (rc) return rc;
         }
-        hipEvent_t ev[SIM_NUM_KERNELS + 1] = {};
+        hipEvent_t ev[2 * SIM_NUM_KERNELS] = {};
         const bool timed = S->timing_every > 0 && (S->host_t % S->timing_every) == 0;
         if (timed) {
-            for (int q = 0; q <= SIM_NUM_KERNELS; ++q) {
+            for (int q = 0; q < 2 * SIM_NUM_KERNELS; ++q) {
                 if (S->ev_free.empty()) {
-                    // timing only: no system-scope fence, so that recording the
-                    // event does not add a cache write-back to the kernel's time
                     hipEvent_t e;
-                    HIPCHECK(S, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+                    HIPCHECK(S, hipEventCreate(&e));
                     S->ev_free.push_back(e);
                 }
                 ev[q] = S->ev_free.back();
@@ -845,7 +847,7 @@ int sim_step(sim_t* S, int32_t num_steps) {
         int rc = launch_step(S, S->buf[p], S->buf[p ^ 1], S->tr, S->s, off, S->ctr,
                              timed ? ev : nullptr);
         if (rc) return rc;
-        if (timed) S->ev_steps.emplace_back(ev, ev + SIM_NUM_KERNELS + 1);
+        if (timed) S->ev_steps.emplace_back(ev, ev + 2 * SIM_NUM_KERNELS);
         S->host_t += 1;
     }
     return SIM_OK;
@@ -1256,7 +1258,7 @@ int sim_read_timing(sim_t* S, double* kernel_ms, int64_t* samples) {
     for (auto& evs : S->ev_steps) {
         for (int q = 0; q < SIM_NUM_KERNELS; ++q) {
             float ms = 0.0f;
-            HIPCHECK(S, hipEventElapsedTime(&ms, evs[q], evs[q + 1]));
+            HIPCHECK(S, hipEventElapsedTime(&ms, evs[2 * q], evs[2 * q + 1]));
             kernel_ms[q] += ms;
         }
         for (hipEvent_t e : evs) S->ev_free.push_back(e);
