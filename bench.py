@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "vehicle-updates/sec at 1 GPU + % HBM roofline; adjoint & ensemble vs plain"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes (per unit): x and v read and written once
-# per vehicle-update, plus one 64-byte record per event (claim)
+# algorithmic bytes of k_decide: x and v read and written once per
+# vehicle-update (16 B), plus one 64-byte record per crossing claim
 B_PER_VEH = 16.0
 B_PER_EVENT = 64.0
 
@@ -277,7 +277,7 @@ def bench_adjoint(args):
 
 
 # algorithmic bytes per relaxed link of the route search: its weight (8 B),
-# its head node (4 B) and the 8-byte label it lowers (see DESIGN.md)
+# its head node (4 B) and the 8-byte label it lowers
 B_PER_RELAX = 20.0
 
 
@@ -408,7 +408,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
