@@ -411,8 +411,11 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
 }
 
 // lane changes: one thread per listed vehicle; the grid is a multiple of kSeg
-// and block b reads segment b % kSeg
-__global__ __launch_bounds__(kBlock) void k_change(Params P, Net net, Veh in, Scratch s, Tape tp, Counters* ctr) {
+// and block b reads segment b % kSeg.  7 waves per SIMD instead of the 6 its
+// registers would otherwise allow (no spills): more evaluations in flight to
+// cover the gathers.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_change(
+    Params P, Net net, Veh in, Scratch s, Tape tp, Counters* ctr) {
     const int N = ctr->n;
     const int q = blockIdx.x & (kSeg - 1);
     const int M = s.lcnt[q * kSegStride];
@@ -774,9 +777,10 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
 // k_lanes: index the lanes of the new sorted arrays (first and last entry per
 // lane, tagged with the next step's epoch).  With `finalize` it also commits
 // the step: the kernels of the step are the only readers of the counters it
-// advances, and they have all completed.
+// advances, and they have all completed.  8 waves per SIMD (no spills).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_lanes(Params P, Net net, Veh buf, Scratch s, Counters* ctr, int finalize) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_lanes(
+    Params P, Net net, Veh buf, Scratch s, Counters* ctr, int finalize) {
     const int N = finalize ? ctr->n_next : ctr->n;
     const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
