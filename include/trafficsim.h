@@ -302,7 +302,9 @@ int sim_load_demand_batch(sim_t* sim, int32_t n, const int32_t* num_trips, const
 
 /* Launch shape: blocks of 256 threads for the per-vehicle, per-claim and
  * per-mover kernels (grid) and for the persistent blocks of the step's scan
- * (grid_small).  Results do not depend on it. */
+ * (grid_small).  The lane-change kernel runs the whole number of device-wide
+ * waves of its resident blocks nearest to grid (grid itself when smaller
+ * than one wave).  Results do not depend on the shape. */
 int sim_set_launch(sim_t* sim, int32_t grid, int32_t grid_small);
 int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
 

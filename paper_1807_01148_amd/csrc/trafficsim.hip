@@ -104,6 +104,7 @@ struct sim_t {
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
     int grid_small = 1;  // k_scan's persistent blocks
+    int change_res = 0;  // k_change blocks resident on the whole device at once (a multiple of kSeg; 0 unknown)
     int grid_q = 1;      // k_decide's departure-queue blocks: one thread per queue
     std::vector<int> h_rbeg;
     int timing_every = 0;
@@ -270,15 +271,24 @@ int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
             hipLaunchKernelGGL(kern, grid, b, 0, S->stream, __VA_ARGS__);                               \
     } while (0)
 
+// k_change's grid: the whole number of device-wide waves of resident blocks
+// nearest to the other kernels' grid, so that no partly filled wave trails
+// the launch (the others keep theirs: measured, only k_change gains)
+int change_grid(int g8, int res) {
+    if (res <= 0 || g8 < res) return g8;
+    return (g8 + res / 2) / res * res;
+}
+
 int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     // kernels that read the per-XCD segments run a multiple of kSeg blocks
     const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg);
+    const dim3 gc(change_grid((int)g8.x, S->change_res));
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
     STEP_LAUNCH(0, k_decide, dim3(qb + g8.x), S->P, S->net, tr, in, sc, tp, ctr, qb);
-    STEP_LAUNCH(1, k_change, g8, S->P, S->net, in, sc, tp, ctr);
+    STEP_LAUNCH(1, k_change, gc, S->P, S->net, in, sc, tp, ctr);
     STEP_LAUNCH(2, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
     STEP_LAUNCH(3, k_scan, gs, sc, ctr);
     STEP_LAUNCH(4, k_scatter, g8, S->P, in, out, sc, tp, ctr);
@@ -422,6 +432,14 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
 
     sim_t* S = new sim_t();
     S->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        int dev = 0, cus = 0, nb = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_change, kBlock, 0) == hipSuccess && cus > 0 && nb > 0)
+            S->change_res = (cus * nb + kSeg - 1) / kSeg * kSeg;
+        (void)hipGetLastError();
+    }
     S->alloc = alloc;
     S->free_fn = free_fn;
     S->ctx = alloc_ctx;
