@@ -90,8 +90,8 @@ int rt_last_work(rt_t* rt, int64_t* relaxations, int32_t* sources);
 /* Largest number of origins searched at once.  Default: as many as fit in
  * 32 bytes x nodes x count within a quarter of the device memory free at the
  * plan (at least 4 GiB, at most 64 GiB), at most 4096, and count x nodes
- * below 2^32.  Larger batches need fewer search rounds per plan.
- * Errors: SIM_EINVAL. */
+ * below 2^32, or the batch of an earlier plan if larger (its memory is kept).
+ * Larger batches need fewer search rounds per plan.  Errors: SIM_EINVAL. */
 int rt_set_batch(rt_t* rt, int32_t sources_per_batch);
 
 /* Band width of the search in ms (the search relaxes labels below a threshold

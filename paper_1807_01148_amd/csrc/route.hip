@@ -671,7 +671,9 @@ int rt_plan(rt_t* R, const uint8_t* select, int64_t* total_route_edges) {
     std::vector<int> todo;  // origin indices
     for (int s = 0; s < R->nsrc; ++s)
         if (need[s]) todo.push_back(s);
-    const int B = R->batch > 0 ? R->batch : auto_batch(R);
+    // automatic: at least the batch the router already holds memory for (its
+    // own buffers no longer count as free)
+    const int B = R->batch > 0 ? R->batch : std::max(auto_batch(R), R->batch_alloc);
     unsigned long long relax = 0;
     std::vector<int> nodes;
     for (size_t b0 = 0; b0 < todo.size(); b0 += (size_t)B) {
