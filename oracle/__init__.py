@@ -27,7 +27,10 @@ def build(force: bool = False):
     """Compile liboracle_f32.so, liboracle_f64.so, libadjoint.so and
     liboracle_route.so with gcc."""
     outs = []
+    # f32omp: the FP32 oracle with its per-vehicle decision loop split over
+    # threads (OpenMP); the same source, the same results
     for prec, defs, name in (("f32", [], "oracle.c"), ("f64", ["-DORACLE_F64"], "oracle.c"),
+                             ("f32omp", ["-fopenmp"], "oracle.c"),
                              ("adj", [], "adjoint.c"), ("route", [], "routing.c")):
         src = os.path.join(_HERE, name)
         out = os.path.join(_HERE, "liboracle_%s.so" % prec if prec != "adj" else "libadjoint.so")
@@ -85,6 +88,8 @@ def _lib(prec):
         lib.or_tape_size.argtypes = [P]
         lib.or_tape_size.restype = ctypes.c_int64
         lib.or_tape_get.argtypes = [P] + [P] * 8
+        lib.or_set_state.argtypes = [P, i32, i32] + [P] * 10
+        lib.or_set_state.restype = ctypes.c_int
         _LIBS[prec] = lib
     return _LIBS[prec]
 
@@ -231,7 +236,7 @@ class Oracle:
         rv = np.zeros((max(n, 1), 5), np.float64)
         n = self.lib.or_get_vehicles(self.h, _p(iv), _p(rv))
         iv, rv = iv[:n], rv[:n]
-        dt = np.float32 if self.precision == "f32" else np.float64
+        dt = np.float32 if self.precision != "f64" else np.float64
         return {"vid": iv[:, 0].copy(), "edge": iv[:, 1].copy(), "lane": iv[:, 2].copy(),
                 "cursor": iv[:, 3].copy(), "lc": iv[:, 4].copy(), "kin": iv[:, 5].copy(),
                 "x": rv[:, 0].astype(dt), "v": rv[:, 1].astype(dt), "phin": rv[:, 2].astype(dt),
@@ -242,7 +247,7 @@ class Oracle:
         f = np.zeros(self.ntrips, np.float64)
         c = np.zeros(self.ntrips, np.float64)
         self.lib.or_get_emissions(self.h, _p(f), _p(c))
-        dt = np.float32 if self.precision == "f32" else np.float64
+        dt = np.float32 if self.precision != "f64" else np.float64
         return {"fuel": f.astype(dt), "co": c.astype(dt)}
 
     def set_control(self, node_control, signal_green: int = 20, stop_dist: float = 3.0, stop_speed: float = 0.5):
@@ -279,6 +284,27 @@ class Oracle:
         t.update({k: np.zeros(max(n, 1), np.float64) for k in TAPE_F64})
         self.lib.or_tape_get(self.h, *[_p(t[k]) for k in TAPE_INT + TAPE_F64])
         return {k: a[:n] for k, a in t.items()}
+
+    def set_state(self, step, veh, trips, emissions, edge_stats, counters):
+        """Continue from another simulation's state at ``step`` (before any
+        step of this one; no intersection control): ``veh`` = vehicles on the
+        road as returned by ``vehicles()`` (any order), ``trips`` and
+        ``emissions`` per vehicle id, ``edge_stats`` per link, ``counters``
+        as returned by ``counters()``."""
+        n = int(veh["vid"].size)
+        iv = np.ascontiguousarray(np.stack([veh[k] for k in ("vid", "edge", "lane", "cursor", "lc", "kin")],
+                                           axis=1), np.int32)
+        rv = np.ascontiguousarray(np.stack([veh[k] for k in ("x", "v", "phin", "fuel", "co")], axis=1),
+                                  np.float64)
+        arrs = [np.ascontiguousarray(trips["depart_actual"], np.int32),
+                np.ascontiguousarray(trips["arrive_step"], np.int32),
+                np.ascontiguousarray(emissions["fuel"], np.float64), np.ascontiguousarray(emissions["co"], np.float64),
+                np.ascontiguousarray(edge_stats["count"], np.int64), np.ascontiguousarray(edge_stats["tt_steps"], np.int64),
+                np.ascontiguousarray(edge_stats["tt_us"], np.int64),
+                np.ascontiguousarray([counters[k] for k in COUNTERS], np.int64)]
+        rc = self.lib.or_set_state(self.h, int(step), n, _p(iv), _p(rv), *[_p(a) for a in arrs])
+        if rc != 0:
+            raise OracleError("or_set_state failed: %d" % rc)
 
     def edge_stats(self) -> dict:
         c = np.zeros(self.ne, np.int64)

@@ -339,14 +339,23 @@ int or_load_demand(osim* S, int32_t ntrips, const int32_t* depart_step, const in
     if (route_ptr[0] != 0) return OR_EROUTE;
     int64_t nre = route_ptr[nroutes];
     if (nre < 0 || nre > INT32_MAX - 2) return OR_EROUTE;
+    int32_t* tail = (int32_t*)malloc(sizeof(int32_t) * (S->ne + 1));
+    for (int32_t e = 0; e < S->ne; ++e) tail[e] = tail_of(S, e);
     for (int32_t r = 0; r < nroutes; ++r) {
-        if (route_ptr[r + 1] <= route_ptr[r]) return OR_EROUTE;
-        for (int64_t k = route_ptr[r]; k < route_ptr[r + 1]; ++k) {
+        int bad = route_ptr[r + 1] <= route_ptr[r];
+        for (int64_t k = route_ptr[r]; k < route_ptr[r + 1] && !bad; ++k) {
             int32_t e = route_edges[k];
-            if (e < 0 || e >= S->ne) return OR_EROUTE;
-            if (k + 1 < route_ptr[r + 1] && S->col_idx[e] != tail_of(S, route_edges[k + 1])) return OR_EROUTE;
+            if (e < 0 || e >= S->ne) bad = 1;
+            else if (k + 1 < route_ptr[r + 1] && (route_edges[k + 1] < 0 || route_edges[k + 1] >= S->ne ||
+                                                  S->col_idx[e] != tail[route_edges[k + 1]]))
+                bad = 1;
+        }
+        if (bad) {
+            free(tail);
+            return OR_EROUTE;
         }
     }
+    free(tail);
     for (int32_t i = 0; i < ntrips; ++i) {
         if (trip_route[i] < 0 || trip_route[i] >= nroutes) return OR_EINVAL;
         if (depart_step[i] < S->t) return OR_ESTATE;
@@ -861,6 +870,9 @@ static int step_once(osim* S) {
 
     /* 1. decisions of the vehicles on the road */
     dec_t* D = (dec_t*)malloc(sizeof(dec_t) * (N + 1));
+    /* each decision reads state t only: the all-cores build (-fopenmp) splits
+     * this loop over threads, with the same result */
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int32_t o = 0; o < N; ++o) D[o] = decide(&W, o);
 
     /* 2. insertion candidates: waiting trips due now, in vehicle-id order */
@@ -1124,3 +1136,67 @@ void or_tape_get(const osim* S, int32_t* step, int32_t* vid, int32_t* mode, int3
     memcpy(v0, S->tp_v0, sizeof(double) * n);
 }
 int32_t or_num_pending(const osim* S) { return S->npend; }
+
+/* Continue from a state taken from another simulation of the same network,
+ * parameters, vehicle types and demand at step t (after or_load_demand, before
+ * any step, no intersection control):
+ *   n vehicles on the road, ints iv[6n] = (vid, edge, lane, cursor in the
+ *   route, step of the last lane change, entry step), reals rv[5n] as float =
+ *   (x, v, entry fraction, fuel, co);
+ *   per vehicle id: depart_actual, arrive_step, fuel_total, co_total;
+ *   per link: traversal count, whole steps, interpolated microseconds;
+ *   counters[13] in the order of or_counters.
+ * The trips still waiting are those not on the road whose departure step is
+ * before t; they queue in vehicle-id order, as they would have. */
+int or_set_state(osim* S, int32_t t, int32_t n, const int32_t* iv, const double* rv, const int32_t* depart_actual,
+                 const int32_t* arrive_step, const double* fuel_total, const double* co_total, const int64_t* cnt,
+                 const int64_t* steps, const int64_t* us, const int64_t* counters) {
+    if (!S->loaded || S->ctrl || S->t != 0 || t < 0 || n < 0 || n > S->ntrips) return OR_ESTATE;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t vid = iv[6 * i + 0], e = iv[6 * i + 1], l = iv[6 * i + 2], cur = iv[6 * i + 3];
+        if (vid < 0 || vid >= S->ntrips || cur < 0 || S->rbeg[vid] + cur >= S->rend[vid]) return OR_EINVAL;
+        if (S->route_edges[S->rbeg[vid] + cur] != e || l < 0 || l >= S->lanes[e]) return OR_EINVAL;
+        if (!(rv[5 * i + 0] >= 0) || !(rv[5 * i + 0] <= (double)S->len[e]) || !(rv[5 * i + 1] >= 0)) return OR_EINVAL;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        veh_t* q = &S->act[i];
+        q->vid = iv[6 * i + 0];
+        q->edge = iv[6 * i + 1];
+        q->lane = iv[6 * i + 2];
+        q->rcur = S->rbeg[q->vid] + iv[6 * i + 3];
+        q->next = (q->rcur + 1 < S->rend[q->vid]) ? S->route_edges[q->rcur + 1] : -1;
+        q->lc = iv[6 * i + 4];
+        q->kin = iv[6 * i + 5];
+        q->ty = S->vtype[q->vid];
+        q->x = (real)rv[5 * i + 0];
+        q->v = (real)rv[5 * i + 1];
+        q->phin = (real)rv[5 * i + 2];
+        q->fuel = (real)rv[5 * i + 3];
+        q->co = (real)rv[5 * i + 4];
+    }
+    S->nact = n;
+    for (int32_t v = 0; v < S->ntrips; ++v) {
+        S->depart_actual[v] = depart_actual[v];
+        S->arrive_step[v] = arrive_step[v];
+        S->fuel_total[v] = (real)fuel_total[v];
+        S->co_total[v] = (real)co_total[v];
+    }
+    memcpy(S->st_cnt, cnt, sizeof(int64_t) * S->ne);
+    memcpy(S->st_steps, steps, sizeof(int64_t) * S->ne);
+    memcpy(S->st_us, us, sizeof(int64_t) * S->ne);
+    S->npend = 0;
+    for (int32_t v = 0; v < S->ntrips; ++v)
+        if (S->dep[v] < t && S->depart_actual[v] < 0) S->pend[S->npend++] = v;
+    S->relc = 0;
+    S->t = t;
+    S->arrived = counters[4];
+    S->departed = counters[5];
+    S->updates = counters[6];
+    S->claims_lost = counters[7];
+    S->clamps = counters[8];
+    S->claims = counters[9];
+    S->claims_dep = counters[10];
+    S->lc_evaluated = counters[11];
+    S->claims_lc = counters[12];
+    return OR_OK;
+}
