@@ -36,7 +36,17 @@ def per_trip(sim, dep):
     return {k: a[v] for k, a in tr.items()}
 
 
-def test_batch_equals_separate_runs():
+def oracle_trips(o, dep):
+    from paper_1807_01148_amd.ensemble import vehicle_ids
+    tr = o.trips()
+    v = vehicle_ids(dep)
+    return {k: a[v] for k, a in tr.items()}
+
+
+def test_batch_equals_separate_runs_and_the_oracle():
+    """Every member of a batch equals its own simulation and the FP32 oracle
+    run of that scenario alone: link statistics and per-trip outcomes."""
+    import oracle
     import paper_1807_01148_amd as P
     from paper_1807_01148_amd.ensemble import Ensemble
     scens = small_scenarios()
@@ -47,13 +57,18 @@ def test_batch_equals_separate_runs():
     for q, sc in enumerate(scens):
         one = P.Sim(sc)
         one.step(500)
-        a, b = ens.scenario_edge_stats(q, est), one.edge_stats()
-        for k in b:
-            assert np.array_equal(a[k], b[k]), (q, k)
-        ta, tb = ens.scenario_trips(q, etr), per_trip(one, sc["demand"]["depart_step"])
-        for k in tb:
-            assert np.array_equal(ta[k], tb[k]), (q, k)
+        o = oracle.Oracle(sc, "f32")
+        o.step(500)
+        a = ens.scenario_edge_stats(q, est)
+        for b in (one.edge_stats(), o.edge_stats()):
+            for k in b:
+                assert np.array_equal(a[k], b[k]), (q, k)
+        ta = ens.scenario_trips(q, etr)
+        for tb in (per_trip(one, sc["demand"]["depart_step"]), oracle_trips(o, sc["demand"]["depart_step"])):
+            for k in tb:
+                assert np.array_equal(ta[k], tb[k]), (q, k)
         total += one.counters()["vehicle_updates"]
+        assert one.counters()["vehicle_updates"] == o.counters()["vehicle_updates"]
     assert ens.counters()["vehicle_updates"] == total
 
 

@@ -16,6 +16,7 @@ import pytest
 import oracle
 import scenarios as S
 
+from fp64check import link_time_gap, one_step_vs_fp64
 from tiny import tiny_grid
 
 pytestmark = pytest.mark.gpu
@@ -124,26 +125,23 @@ def test_sampler_and_emissions_grid50():
     assert so["count"].sum() > 0
 
 
+@pytest.mark.timeout(600)
 def test_snapshot_vs_fp64_one_step():
+    """HIP (FP32) against the FP64 oracle from identical states -- placed
+    snapshots on a 50x50 grid, and the 50x50 grid workload's own state at
+    steps 3,600 and 7,200 (queues, platoons, lane changes in progress): every
+    discrete mismatch is listed and must be a decision whose FP64 margin lies
+    within FP32 rounding (an input change of a few float32 ulps flips the
+    FP64 decision to the GPU's); positions and speeds within 1e-5."""
     net = S.grid(50, seed=3, lane_probs=(0.5, 0.35, 0.15), lognormal=(120.0, 0.4))
     for seed in range(3):
         scen = S.placed_snapshot(net, 20000, seed=seed)
-        g, o = sim(scen), oracle.Oracle(scen, "f64")
-        g.step(1)
-        o.step(1)
-        G, O = g.vehicles(), o.vehicles()
-        assert np.array_equal(G["vid"], O["vid"])
-        disc = np.ones(G["vid"].size, bool)
-        for k in ("edge", "lane", "cursor"):
-            disc &= G[k] == O[k]
-        # discrete outcomes may only differ where FP32 and FP64 round a
-        # decision differently; such cases are rare
-        assert disc.mean() > 0.999
-        L = net["length"][G["edge"]].astype(np.float64)
-        x64, v64 = O["x"].astype(np.float64), O["v"].astype(np.float64)
-        ex = np.abs(G["x"].astype(np.float64) - x64) / np.maximum(np.abs(x64), L)
-        ev = np.abs(G["v"].astype(np.float64) - v64) / np.maximum(np.abs(v64), 1.0)
-        assert ex[disc].max() <= 1e-5 and ev[disc].max() <= 1e-5, (ex[disc].max(), ev[disc].max())
+        one_step_vs_fp64(scen, sim(scen), "snapshot %d" % seed)
+    scen = S.mid_grid()
+    g = sim(scen)
+    for t in (3600, 7200):
+        g.step(t - g.counters()["step"])
+        one_step_vs_fp64(scen, g, "grid50 t=%d" % t)
 
 
 def test_small_grid_link_times_vs_fp64():
@@ -158,6 +156,22 @@ def test_small_grid_link_times_vs_fp64():
     assert np.sum(np.abs(tg - to) * eo["count"][m]) / np.sum(to * eo["count"][m]) < 0.005
     assert abs(eg["tt_us"].sum() / eg["count"].sum() - eo["tt_us"].sum() / eo["count"].sum()) \
         / (eo["tt_us"].sum() / eo["count"].sum()) < 0.005
+
+
+@pytest.mark.timeout(600)
+def test_mid_grid_link_times_vs_fp64_before_gridlock():
+    """50x50 grid workload, its first 3,600 steps (before its centre locks
+    up): traversal-weighted mean link travel time and network-wide mean
+    travel time within 0.5% of the FP64 oracle.  Later the uncontrolled
+    merges gridlock the centre and FP32 and FP64 runs take different
+    discrete paths (a chaotic regime; reported, not gated)."""
+    scen = S.mid_grid()
+    g, o = sim(scen), oracle.Oracle(scen, "f64")
+    g.step(3600)
+    o.step(3600)
+    weighted, network, nlinks = link_time_gap(g.edge_stats(), o.edge_stats())
+    print("grid50 3,600 steps: %d links, weighted %.3g, network %.3g" % (nlinks, weighted, network))
+    assert nlinks > 3000 and weighted < 0.005 and network < 0.005
 
 
 def test_determinism_two_runs():
