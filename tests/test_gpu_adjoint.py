@@ -6,7 +6,9 @@ event tape (the adjoint oracle is pinned by central differences):
   * linearized at the recorded FP32 states -- the same trajectory the GPU
     adjoint linearizes at: agreement to 1e-5 of the largest component;
   * with the states replayed in FP64 -- differs from the FP32 trajectory by
-    rounding that the traffic dynamics amplify: agreement to 3e-3.
+    rounding that the traffic dynamics amplify (the events are the same):
+    agreement to 1.5e-3 (measured: 1.03e-3 on this workload, which is also
+    the gap between the two CPU references themselves).
 """
 import numpy as np
 import pytest
@@ -70,7 +72,8 @@ def test_gpu_adjoint_matches_fp64_cpu_adjoint(every):
     assert err < 1e-5, (err, g_g, g_c)
     _, g_r, _ = cpu_reference(scen, tgt, at_tape_states=False)
     err_r = np.abs(g_g - g_r).max() / np.abs(g_r).max()
-    assert err_r < 3e-3, err_r
+    print("adjoint vs FP64 at the FP32 states: %.3g; vs the FP64-replayed states: %.3g" % (err, err_r))
+    assert err_r < 1.5e-3, err_r
 
 
 def test_gpu_adjoint_independent_of_checkpoint_interval_and_deterministic():
