@@ -6,9 +6,14 @@ path: leader search, IDM, lane changes, claims, crossings/arrivals/insertions
 and the re-sort of the vehicle arrays.  The default workload is the
 metro-scale configuration: random planar road graph with 1M nodes and 2.5M
 directed links, 4M gravity-model trips with departures over a 3-hour two-peak
-mixture, 21,600 steps.  ``--warmup W`` steps run untimed first (they advance
-the simulation), then exactly ``--steps K`` steps are timed with the inputs
-already resident in HBM.
+mixture, 21,600 steps.  The run is first advanced, untimed, to the step where
+the workload carries its most vehicles (``--start-step``, default the
+workload's load peak: 1.78M vehicles on the road for metro), then through
+``--warmup W`` more untimed steps; then exactly ``--steps K`` steps are timed
+(HIP events on the stream, graph replays, inputs resident in HBM).  The same
+K steps are then replayed from a saved state image with every kernel launched
+between its own start and stop events, for the per-kernel times and the
+roofline; the FP32 oracle is timed on the host from the same state.
 
 value = vehicle-updates per second over the timed steps (a vehicle-update is
 one vehicle on the road advanced by one step).  Prints ONE JSON line on stdout;
@@ -31,6 +36,14 @@ B_PER_VEH = 16.0
 B_PER_EVENT = 64.0
 
 
+# Step near which each workload carries its most vehicles (measured on one
+# MI355X, vehicles on the road every 300 steps (120 for grid10): the first
+# step within 1% of the maximum).  metro: 1.78M vehicles at step 18,300
+# (maximum 1.79M at 19,500; 777k at 7,200, the peak of the departures);
+# grid50: 58k at 13,200; grid10: 214 at 600.
+PEAK_STEP = {"metro": 18300, "grid50": 13200, "grid10": 600}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -48,14 +61,18 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload="metro", start_step=None):
     """HBM bytes per k_decide launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None when
-    there is none or the kernel sources changed since it was taken."""
+    there is none, the kernel sources changed since it was taken, or it was
+    taken on another workload or window (its first step)."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as f:
             kv = dict(line.strip()[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
         if kv.get("kernel_sources_sha256") != kernel_sources_sha():
+            return None
+        if kv.get("workload") != workload or (start_step is not None and
+                                              int(kv.get("window_start_step", -1)) != start_step):
             return None
         return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -95,29 +112,50 @@ def host_cpu():
     return {"model": model, "available_cores": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(seconds_budget=20.0):
-    """The FP32 oracle, single-threaded, on a bounded sample of the metro
-    workload: the metro network with a synthetic ~1M-vehicle snapshot
-    (mid-simulation density), stepped until ~seconds_budget of CPU work."""
+def gpu_state_for_oracle(sim):
+    """The simulation's dynamic state on the host, in the form the oracle's
+    state import takes (vehicles, trip outcomes, emissions, link statistics,
+    counters)."""
+    return {"veh": sim.vehicles(), "trips": sim.trips(), "emissions": sim.emissions(),
+            "edge_stats": sim.edge_stats(), "counters": sim.counters()}
+
+
+def _time_oracle(scen, state, precision, seconds_budget, max_steps):
     import oracle
-    import scenarios as S
-    net = S.metro()
-    net.pop("xy", None)
-    scen = S.placed_snapshot(net, 1_000_000, seed=11, route_len=40)
-    o = oracle.Oracle(scen, "f32")
+    o = oracle.Oracle(scen, precision)
+    c = state["counters"]
+    o.set_state(c["step"], state["veh"], state["trips"], state["emissions"], state["edge_stats"], c)
+    u0 = o.counters()["vehicle_updates"]
     steps = 0
     t0 = time.perf_counter()
-    while True:
+    while steps < max_steps:
         o.step(1)
         steps += 1
-        el = time.perf_counter() - t0
-        if el > seconds_budget or steps >= 2000:
+        if time.perf_counter() - t0 > seconds_budget:
             break
-    upd = o.counters()["vehicle_updates"]
-    return {"value": upd / el, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "FP32 C oracle, 1 thread, metro network (1M nodes / 2.5M links) with a synthetic "
-                      "snapshot of %d placed vehicles, %d steps, %.1f s" % (scen["demand"]["init_x"].size, steps, el),
-            "host": host_cpu()}
+    el = time.perf_counter() - t0
+    c1 = o.counters()
+    del o
+    return (c1["vehicle_updates"] - u0) / el, steps, el, c1
+
+
+def cpu_baseline(scen, state, seconds_budget=20.0):
+    """The FP32 oracle from the GPU's own state at the start of the timed
+    window (same network, demand and step), stepped for about seconds_budget
+    of CPU work: single-threaded, then the all-cores build (the per-vehicle
+    decision loop split over OpenMP threads) for the same number of steps,
+    whose counters must equal the single-threaded run's."""
+    cores = len(os.sched_getaffinity(0))
+    v1, steps, el1, c1 = _time_oracle(scen, state, "f32", seconds_budget, 2000)
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    threads = int(os.environ["OMP_NUM_THREADS"])
+    vn, _, eln, cn = _time_oracle(scen, state, "f32omp", 1e30, steps)
+    c = state["counters"]
+    sample = ("FP32 C oracle from the GPU state at step %d (%d vehicles on the road, %d waiting), %d steps: "
+              "%.1f s on 1 thread, %.1f s on %d threads" % (c["step"], c["en_route"], c["waiting"], steps, el1, eln,
+                                                          threads))
+    return {"value": vn, "unit": "vehicle-updates/s", "cores": threads, "kind": "oracle", "sample": sample,
+            "single_thread": {"value": v1, "cores": 1}, "threads_agree": c1 == cn, "host": host_cpu()}
 
 
 def ensemble_scenarios(seed=1811, n=64, steps=3600):
@@ -392,10 +430,14 @@ def copy_calibration(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=21540)
+    ap.add_argument("--steps", type=int, default=1200)
     ap.add_argument("--warmup", type=int, default=60)
     ap.add_argument("--workload", default="metro", choices=["metro", "grid50", "grid10"])
-    ap.add_argument("--timing-every", type=int, default=50)
+    ap.add_argument("--start-step", type=int, default=-1,
+                    help="step at which the warm-up and then the timed window start (default: the workload's "
+                         "load peak)")
+    ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
+                    help="skip the per-kernel replay of the timed window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
@@ -433,7 +475,6 @@ def main():
     stream = torch.cuda.current_stream(dev)
     t = time.perf_counter()
     sim = P.Sim(scen, device=0, stream=stream)
-    del scen["demand"]
     log("[bench] loaded in %.1f s" % (time.perf_counter() - t))
     cache = os.path.join(ROOT, "paper_1807_01148_amd", "autotune_cache.json")
     if args.tune_at > 0:
@@ -464,11 +505,24 @@ def main():
     launch = E.get_launch(sim)
     log("[bench] launch shape %s: grid %d, small grid %d" % (shape, launch[0], launch[1]))
 
-    E.step_graph(sim, args.warmup, args.chunk)
+    # the timed window sits at the load the workload is quoted on: the run is
+    # first advanced (untimed, graph replays) to the start step, then through
+    # the warm-up steps
+    start = PEAK_STEP[args.workload] if args.start_step < 0 else args.start_step
+    evp0, evp1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evp0.record(stream)
+    E.step_graph(sim, start + args.warmup, args.chunk)
+    evp1.record(stream)
     torch.cuda.synchronize()
     c0 = sim.counters()
-    log("[bench] warmup done: step %d en_route %d" % (c0["step"], c0["en_route"]))
-    sim.set_timing(args.timing_every)
+    # the untimed approach, reported beside the window: all steps from the
+    # start of the run (ramp-up included; graph captures happen on the host)
+    approach = {"steps": c0["step"], "vehicle_updates": c0["vehicle_updates"],
+                "seconds": evp0.elapsed_time(evp1) / 1000.0}
+    approach["value"] = approach["vehicle_updates"] / approach["seconds"] if approach["seconds"] > 0 else None
+    log("[bench] at step %d: en_route %d waiting %d" % (c0["step"], c0["en_route"], c0["waiting"]))
+    img = sim.save_state()  # the window's start, for the per-kernel replay
+    host_state = None if args.no_cpu_baseline else gpu_state_for_oracle(sim)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -486,43 +540,58 @@ def main():
     wall = time.perf_counter() - t0
     ev_ms = ev0.elapsed_time(ev1)
     c1 = sim.counters()
-    kms, samples = sim.read_timing()
-    sim.set_timing(0)
     upd = c1["vehicle_updates"] - c0["vehicle_updates"]
     claims = c1["claims"] - c0["claims"]
     lc_claims = c1["claims_lane_change"] - c0["claims_lane_change"]
     claims_cross = claims - (c1["claims_departure"] - c0["claims_departure"]) - lc_claims
     secs = ev_ms / 1000.0
-    value = upd / secs
-    log("[bench] %d steps in %.3f s (wall %.3f s), %d vehicle-updates, final en_route %d arrived %d"
+    value = upd / secs if secs > 0 else 0.0
+    log("[bench] %d steps in %.4f s (wall %.4f s), %d vehicle-updates, final en_route %d arrived %d"
         % (args.steps, secs, wall, upd, c1["en_route"], c1["arrived"]))
 
-    avg = {k: (v / samples if samples else 0.0) for k, v in kms.items()}
-    dom = max(avg, key=avg.get)
-    per_launch_units = upd / args.steps
-    # k_decide advances the vehicles; its events are their crossing claims (the
-    # lane-change claims are k_change's)
-    per_launch_claims = claims_cross / args.steps
-    alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
-    achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
-    step_achieved = (B_PER_VEH * upd + B_PER_EVENT * claims) / secs / 1e9
-    traffic = measured_traffic() if dom == "k_decide" else None
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": alg_bytes,
-                "sampled_steps": samples}
-    if traffic and avg[dom] > 0:
-        # the measured HBM bytes over the same launch time, and their ratio to the algorithmic bytes
-        roofline["traffic_gbs"] = traffic / (avg[dom] * 1e-3) / 1e9
-        roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
-        roofline["amplification"] = traffic / alg_bytes
-    roofline["copy_ceiling_gbs"] = copy_ceiling()
+    # the same window again from its saved start, every step's kernels
+    # launched with their own start and stop events (outside the graphs); the
+    # replay must reach the same counters
+    samples, avg, replay_same = 0, {}, None
+    if args.steps > 0 and args.kernel_timing:
+        sim.load_state(img)
+        sim.set_timing(1)
+        E.step_graph(sim, args.steps, args.chunk)
+        kms, samples = sim.read_timing()
+        sim.set_timing(0)
+        replay_same = sim.counters() == c1
+        avg = {k: v / samples for k, v in kms.items()} if samples else {}
+        log("[bench] per-kernel replay: %d sampled steps, identical counters %s" % (samples, replay_same))
+    del img
+
+    roofline = None
+    if samples:
+        dom = max(avg, key=avg.get)
+        per_launch_units = upd / args.steps
+        # k_decide advances the vehicles; its events are their crossing claims
+        # (the lane-change claims are k_change's)
+        per_launch_claims = claims_cross / args.steps
+        alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
+        achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9
+        traffic = measured_traffic(args.workload, c0["step"]) if dom == "k_decide" else None
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": alg_bytes,
+                    "sampled_steps": samples}
+        if traffic:
+            # the measured HBM bytes over the same launch time, and their ratio to the algorithmic bytes
+            roofline["traffic_gbs"] = traffic / (avg[dom] * 1e-3) / 1e9
+            roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
+            roofline["amplification"] = traffic / alg_bytes
+        roofline["copy_ceiling_gbs"] = copy_ceiling()
+    step_achieved = (B_PER_VEH * upd + B_PER_EVENT * claims) / secs / 1e9 if secs > 0 else 0.0
     out = {
         "metric": METRIC, "value": value, "unit": "vehicle-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev_ms / args.steps,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ev_ms / args.steps if args.steps else 0.0,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "simulated_steps": [c0["step"], c1["step"]],
+        "config": {"workload": desc, "start_step": start, "simulated_steps": [c0["step"], c1["step"]],
+                   "en_route_start": c0["en_route"], "waiting_start": c0["waiting"],
                    "vehicle_updates": upd, "claims": claims, "claims_crossing": claims_cross,
                    "claims_lane_change": lc_claims,
                    "lc_evaluated": c1["lc_evaluated"] - c0["lc_evaluated"], "en_route_end": c1["en_route"],
@@ -530,15 +599,18 @@ def main():
         "roofline": roofline,
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": step_achieved / HBM_PEAK_GBS},
-        "kernel_avg_us": {k: v * 1e3 for k, v in avg.items()},
+        "kernel_avg_us": {k: v * 1e3 for k, v in avg.items()} or None,
+        "kernel_replay_identical": replay_same,
+        "run_to_window": approach,
         "launch": {"grid": launch[0], "grid_small": launch[1], "shape": shape, "graph_chunk": args.chunk},
     }
     sim.close()
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    else:
-        out["cpu_baseline"] = None
+    del sim
+    torch.cuda.empty_cache()
+    out["cpu_baseline"] = None
+    if host_state is not None:
+        log("[bench] timing the CPU oracle baseline on the same state")
+        out["cpu_baseline"] = cpu_baseline(scen, host_state, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

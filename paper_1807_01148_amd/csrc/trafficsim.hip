@@ -1432,7 +1432,13 @@ int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
             }
             len = std::min(chunk, to_timed);
         }
-        if (num_steps - done < len || len < 2) break;
+        if (num_steps - done < len) break;
+        if (len < 2) {  // one step before the next timed one: no graph for it
+            int rc = sim_step(S, 1);
+            if (rc) return rc;
+            done += 1;
+            continue;
+        }
         int rc0 = graph_stream(S);
         if (rc0) return rc0;
         const int parity = (int)(S->host_t & 1);

@@ -10,11 +10,11 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def write_summary(path, sha, fetch="1000", write="24"):
+def write_summary(path, sha, fetch="1000", write="24", workload="metro", start=18300):
     with open(path, "w") as f:
         f.write("# summary\n\ntext: not a field\n\n")
         f.write("- kernel_sources_sha256: %s\n- fetch_bytes_per_launch: %s\n- write_bytes_per_launch: %s\n"
-                % (sha, fetch, write))
+                "- workload: %s\n- window_start_step: %d\n" % (sha, fetch, write, workload, start))
 
 
 def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
@@ -30,6 +30,10 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
 
     write_summary(tmp_path / "summary.md", sha)
     assert bench.measured_traffic() == 1024.0
+    assert bench.measured_traffic("metro", 18300) == 1024.0
+    # counters of another window or workload do not describe this one
+    assert bench.measured_traffic("metro", 7205) is None
+    assert bench.measured_traffic("grid50", 18300) is None
 
     # a changed kernel source: the counters no longer describe it
     with open(tmp_path / bench.KERNEL_SOURCES[-1], "ab") as f:
@@ -49,6 +53,7 @@ def test_committed_summary_parses():
         kv = dict(line.strip()[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
     assert len(kv["kernel_sources_sha256"]) == 64
     assert float(kv["fetch_bytes_per_launch"]) > 0 and float(kv["write_bytes_per_launch"]) > 0
+    assert kv["workload"] in ("metro", "grid50", "grid10") and int(kv["window_start_step"]) >= 0
 
 
 def test_more_than_one_gpu_is_refused():
