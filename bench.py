@@ -6,14 +6,17 @@ path: leader search, IDM, lane changes, claims, crossings/arrivals/insertions
 and the re-sort of the vehicle arrays.  The default workload is the
 metro-scale configuration: random planar road graph with 1M nodes and 2.5M
 directed links, 4M gravity-model trips with departures over a 3-hour two-peak
-mixture, 21,600 steps.  The run is first advanced, untimed, to the step where
-the workload carries its most vehicles (``--start-step``, default the
-workload's load peak: 1.78M vehicles on the road for metro), then through
-``--warmup W`` more untimed steps; then exactly ``--steps K`` steps are timed
-(HIP events on the stream, graph replays, inputs resident in HBM).  The same
-K steps are then replayed from a saved state image with every kernel launched
-between its own start and stop events, for the per-kernel times and the
-roofline; the FP32 oracle is timed on the host from the same state.
+mixture, 21,600 steps.  The timed window starts at the step where the
+workload carries its most vehicles (``--start-step``, default the workload's
+load peak: 1.78M vehicles on the road for metro at step 18,300).  The run is
+advanced there untimed (graph replays), or loaded from a state image written
+by an earlier run (``--state-file``).  ``--warmup W`` steps then run untimed
+from that state (graph capture, caches), the state is put back, and exactly
+``--steps K`` steps are timed from the window start (HIP events on the
+stream, graph replays, inputs resident in HBM).  The same K steps are then
+replayed from the saved state with every kernel launched between its own
+start and stop events, for the per-kernel times and the roofline; the FP32
+oracle is timed on the host from the same state.
 
 value = vehicle-updates per second over the timed steps (a vehicle-update is
 one vehicle on the road advanced by one step).  Prints ONE JSON line on stdout;
@@ -49,7 +52,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = ("paper_1807_01148_amd/csrc/common.h", "paper_1807_01148_amd/csrc/step_kernels.h")
-TRAFFIC_SUMMARY = "profiles/k_decide_traffic_metro1M.md"
+TRAFFIC_SUMMARY = "profiles/step_traffic_metro1M.md"
+STEP_KERNELS = ("k_decide", "k_change", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 def kernel_sources_sha():
@@ -62,10 +66,11 @@ def kernel_sources_sha():
 
 
 def measured_traffic(workload="metro", start_step=None):
-    """HBM bytes per k_decide launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None when
-    there is none, the kernel sources changed since it was taken, or it was
-    taken on another workload or window (its first step)."""
+    """HBM bytes per launch of every step kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), as
+    {kernel: (fetch, write)}, or None when there is none, the kernel sources
+    changed since it was taken, or it was taken on another workload or window
+    (its first step)."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as f:
             kv = dict(line.strip()[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
@@ -74,7 +79,11 @@ def measured_traffic(workload="metro", start_step=None):
         if kv.get("workload") != workload or (start_step is not None and
                                               int(kv.get("window_start_step", -1)) != start_step):
             return None
-        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+        out = {}
+        for k in STEP_KERNELS:
+            if k + "_fetch_bytes_per_launch" in kv:
+                out[k] = (float(kv[k + "_fetch_bytes_per_launch"]), float(kv[k + "_write_bytes_per_launch"]))
+        return out or None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -436,6 +445,9 @@ def main():
     ap.add_argument("--start-step", type=int, default=-1,
                     help="step at which the warm-up and then the timed window start (default: the workload's "
                          "load peak)")
+    ap.add_argument("--state-file", default="",
+                    help="state image at the window start: loaded if it exists (instead of the approach), else "
+                         "written after the approach")
     ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
                     help="skip the per-kernel replay of the timed window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -506,22 +518,42 @@ def main():
     log("[bench] launch shape %s: grid %d, small grid %d" % (shape, launch[0], launch[1]))
 
     # the timed window sits at the load the workload is quoted on: the run is
-    # first advanced (untimed, graph replays) to the start step, then through
-    # the warm-up steps
+    # advanced there untimed (graph replays), or its state there is loaded
     start = PEAK_STEP[args.workload] if args.start_step < 0 else args.start_step
-    evp0, evp1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    evp0.record(stream)
-    E.step_graph(sim, start + args.warmup, args.chunk)
-    evp1.record(stream)
+    approach = None
+    meta = {"workload": args.workload, "step": start}
+    if args.state_file and os.path.exists(args.state_file) and os.path.exists(args.state_file + ".json"):
+        with open(args.state_file + ".json") as f:
+            got = json.load(f)
+        if got != meta:
+            raise SystemExit("state file %s holds %s, not %s" % (args.state_file, got, meta))
+        import numpy as np
+        sim.load_state(torch.from_numpy(np.fromfile(args.state_file, dtype=np.uint8)).to(dev))
+        log("[bench] state at step %d loaded from %s" % (start, args.state_file))
+    else:
+        evp0, evp1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evp0.record(stream)
+        E.step_graph(sim, start, args.chunk)
+        evp1.record(stream)
+        torch.cuda.synchronize()
+        # the untimed approach, reported beside the window: all steps from the
+        # start of the run (ramp-up included; graph captures happen on the host)
+        ca = sim.counters()
+        approach = {"steps": ca["step"], "vehicle_updates": ca["vehicle_updates"],
+                    "seconds": evp0.elapsed_time(evp1) / 1000.0}
+        approach["value"] = approach["vehicle_updates"] / approach["seconds"] if approach["seconds"] > 0 else None
+    img = sim.save_state()  # the window's start: warm-up, timed window and per-kernel replay all begin here
+    if args.state_file and approach is not None:
+        img.cpu().numpy().tofile(args.state_file)
+        with open(args.state_file + ".json", "w") as f:
+            json.dump(meta, f)
+        log("[bench] state at step %d saved to %s" % (start, args.state_file))
+    if args.warmup > 0:
+        E.step_graph(sim, args.warmup, args.chunk)
+        sim.load_state(img)
     torch.cuda.synchronize()
     c0 = sim.counters()
-    # the untimed approach, reported beside the window: all steps from the
-    # start of the run (ramp-up included; graph captures happen on the host)
-    approach = {"steps": c0["step"], "vehicle_updates": c0["vehicle_updates"],
-                "seconds": evp0.elapsed_time(evp1) / 1000.0}
-    approach["value"] = approach["vehicle_updates"] / approach["seconds"] if approach["seconds"] > 0 else None
     log("[bench] at step %d: en_route %d waiting %d" % (c0["step"], c0["en_route"], c0["waiting"]))
-    img = sim.save_state()  # the window's start, for the per-kernel replay
     host_state = None if args.no_cpu_baseline else gpu_state_for_oracle(sim)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -565,6 +597,7 @@ def main():
     del img
 
     roofline = None
+    traffic = measured_traffic(args.workload, c0["step"]) if samples else None
     if samples:
         dom = max(avg, key=avg.get)
         per_launch_units = upd / args.steps
@@ -573,17 +606,29 @@ def main():
         per_launch_claims = claims_cross / args.steps
         alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
         achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9
-        traffic = measured_traffic(args.workload, c0["step"]) if dom == "k_decide" else None
+        tb = sum(traffic[dom]) if traffic and dom in traffic else None
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
                     "avg_launch_us": avg[dom] * 1e3, "alg_bytes_per_launch": alg_bytes,
                     "sampled_steps": samples}
-        if traffic:
+        if tb:
             # the measured HBM bytes over the same launch time, and their ratio to the algorithmic bytes
-            roofline["traffic_gbs"] = traffic / (avg[dom] * 1e-3) / 1e9
+            roofline["traffic_gbs"] = tb / (avg[dom] * 1e-3) / 1e9
             roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
-            roofline["amplification"] = traffic / alg_bytes
+            roofline["amplification"] = tb / alg_bytes
         roofline["copy_ceiling_gbs"] = copy_ceiling()
+    step_traffic = None
+    if traffic and samples and all(k in traffic for k in STEP_KERNELS):
+        # every kernel's measured bytes per launch, over the step: bytes per
+        # vehicle-update and their ratio to the method's algorithmic bytes
+        tot = sum(sum(traffic[k]) for k in STEP_KERNELS)
+        per_upd = tot / (upd / args.steps)
+        alg_step = (B_PER_VEH * upd + B_PER_EVENT * claims) / args.steps
+        step_traffic = {"bytes_per_step": tot, "bytes_per_vehicle_update": per_upd,
+                        "alg_bytes_per_step": alg_step, "amplification": tot / alg_step,
+                        "per_kernel_bytes": {k: sum(traffic[k]) for k in STEP_KERNELS},
+                        "per_kernel_gbs": {k: sum(traffic[k]) / (avg[k] * 1e-3) / 1e9 for k in STEP_KERNELS
+                                           if avg.get(k)}}
     step_achieved = (B_PER_VEH * upd + B_PER_EVENT * claims) / secs / 1e9 if secs > 0 else 0.0
     out = {
         "metric": METRIC, "value": value, "unit": "vehicle-updates/s", "n_gpus": 1,
@@ -599,6 +644,7 @@ def main():
         "roofline": roofline,
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": step_achieved / HBM_PEAK_GBS},
+        "step_traffic": step_traffic,
         "kernel_avg_us": {k: v * 1e3 for k, v in avg.items()} or None,
         "kernel_replay_identical": replay_same,
         "run_to_window": approach,

@@ -13,8 +13,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def write_summary(path, sha, fetch="1000", write="24", workload="metro", start=18300):
     with open(path, "w") as f:
         f.write("# summary\n\ntext: not a field\n\n")
-        f.write("- kernel_sources_sha256: %s\n- fetch_bytes_per_launch: %s\n- write_bytes_per_launch: %s\n"
-                "- workload: %s\n- window_start_step: %d\n" % (sha, fetch, write, workload, start))
+        f.write("- kernel_sources_sha256: %s\n- workload: %s\n- window_start_step: %d\n" % (sha, workload, start))
+        for i, k in enumerate(bench.STEP_KERNELS):
+            f.write("- %s_fetch_bytes_per_launch: %s\n- %s_write_bytes_per_launch: %s\n" % (k, fetch, k, i))
+        f.write("- k_decide_write_bytes_per_launch: %s\n" % write)
 
 
 def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
@@ -29,8 +31,10 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
     assert len(sha) == 64
 
     write_summary(tmp_path / "summary.md", sha)
-    assert bench.measured_traffic() == 1024.0
-    assert bench.measured_traffic("metro", 18300) == 1024.0
+    tr = bench.measured_traffic()
+    assert sorted(tr) == sorted(bench.STEP_KERNELS)
+    assert tr["k_decide"] == (1000.0, 24.0) and tr["k_lanes"] == (1000.0, 6.0)
+    assert bench.measured_traffic("metro", 18300) == tr
     # counters of another window or workload do not describe this one
     assert bench.measured_traffic("metro", 7205) is None
     assert bench.measured_traffic("grid50", 18300) is None
@@ -52,7 +56,8 @@ def test_committed_summary_parses():
     with open(os.path.join(ROOT, bench.TRAFFIC_SUMMARY)) as f:
         kv = dict(line.strip()[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
     assert len(kv["kernel_sources_sha256"]) == 64
-    assert float(kv["fetch_bytes_per_launch"]) > 0 and float(kv["write_bytes_per_launch"]) > 0
+    for k in bench.STEP_KERNELS:
+        assert float(kv[k + "_fetch_bytes_per_launch"]) > 0 and float(kv[k + "_write_bytes_per_launch"]) > 0
     assert kv["workload"] in ("metro", "grid50", "grid10") and int(kv["window_start_step"]) >= 0
 
 
