@@ -83,6 +83,29 @@ int rt_read_routes(rt_t* rt, int64_t* route_ptr, int32_t* route_edges);
  * unreachable nodes).  Either pointer may be NULL.  Errors: SIM_EINVAL. */
 int rt_tree(rt_t* rt, int32_t src_node, int64_t* dist, int32_t* pred);
 
+/* Bytes of the static per-GPU search scratch of rt_tree_static. */
+#define RT_STATIC_SCRATCH_BYTES (48u << 20)
+
+/* rt_tree for callers that cannot allocate device memory (code between
+ * other work that must not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation): the same tree, computed with no allocation at
+ * all.  Its search scratch (a 64-bit label, two stamps and four frontier
+ * entries per node, plus counters: about 32 bytes per node) lives in one
+ * static device array of RT_STATIC_SCRATCH_BYTES per GPU, held by every GPU
+ * the library runs on until the process ends; networks of up to about
+ * 1.57M nodes fit.  dist DEVICE int64 [num_nodes] (INT64_MAX where
+ * unreachable) and pred DEVICE int32 [num_nodes] (last edge of the route to
+ * each node, -1 at the source and at unreachable nodes) are the caller's
+ * buffers; either may be NULL.  Call with the router's device current.  The
+ * search reads frontier counts back to the host between rounds, so the call
+ * is not capturable into a graph; it returns once dist and pred are written.
+ * Every call on one GPU shares that GPU's array and overwrites what the last
+ * call left there (the scratch is re-initialised on every call): calls that
+ * overlap on one GPU (from other threads or streams) race.
+ * Errors: SIM_EINVAL (network too large for the static scratch, with the
+ * sizes in rt_last_error; bad source; another device current), SIM_EHIP. */
+int rt_tree_static(rt_t* rt, int32_t src_node, int64_t* dist, int32_t* pred);
+
 /* Edge relaxations performed by the last rt_plan (work counter) and the
  * number of sources it searched from. */
 int rt_last_work(rt_t* rt, int64_t* relaxations, int32_t* sources);

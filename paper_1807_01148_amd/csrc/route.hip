@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,17 @@ __global__ void k_fill_keys(unsigned long long* key, unsigned* stamp, unsigned* 
         stamp[i] = 0u;
         fstamp[i] = 0u;
     }
+}
+
+// counters of a search cleared by a kernel (no memset nodes in the stream):
+// the five frontier and far-list counts (if cnt) and the first 64-bit word
+__global__ void k_clear_counters(unsigned* cnt, unsigned long long* u64) {
+    if (blockIdx.x == 0 && threadIdx.x < 5 && cnt) cnt[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && u64) u64[0] = 0ull;
+}
+
+__global__ void k_zero_u32(unsigned* p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = 0u;
 }
 
 // origin b of the batch: distance 0, no edge; it forms the first frontier
@@ -313,6 +325,7 @@ __global__ void k_tile_apply(const long long* len, int n, const long long* toff,
 using namespace troute;
 
 struct rt_t {
+    int device = 0;  // current device at rt_create
     hipStream_t stream = nullptr;
     sim_alloc_fn alloc = nullptr;
     sim_free_fn free_fn = nullptr;
@@ -461,18 +474,34 @@ int ensure_batch(rt_t* R, int B) {
     return SIM_OK;
 }
 
-// shortest-path labels of origins[0..B) in d_key; returns relaxations
-int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
-    int rc = ensure_batch(R, B);
-    if (rc) return rc;
+// The buffers of one search: per (origin, node) the label, the two stamps, two
+// frontier and two far-list entries; the origins; five counters (three
+// rotating frontier counts, two far-list counts) and two 64-bit words
+// (relaxations, weight sum).
+struct SearchBufs {
+    unsigned long long* key;
+    unsigned* stamp;
+    unsigned* fstamp;
+    unsigned* fr[2];
+    unsigned* far[2];
+    int* origins;
+    unsigned* cnt;
+    unsigned long long* u64;
+};
+
+SearchBufs handle_bufs(rt_t* R) {
+    return SearchBufs{R->d_key, R->d_stamp, R->d_fstamp, {R->d_fr[0], R->d_fr[1]}, {R->d_far[0], R->d_far[1]},
+                      R->d_origins, R->d_cnt, R->d_u64};
+}
+
+// shortest-path labels of the B origins already in b.origins, in b.key;
+// adds the relaxations to *relax
+int search_in(rt_t* R, const SearchBufs& b, int B, unsigned long long* relax) {
     const long long n = (long long)B * R->nn;
-    if ((rc = rh2d(R, R->d_origins, origins, (size_t)B))) return rc;
-    hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n)), dim3(kBlock), 0, R->stream, R->d_key, R->d_stamp,
-                       R->d_fstamp, n);
-    RCHECK(R, hipMemsetAsync(R->d_cnt, 0, 5 * sizeof(unsigned), R->stream));
-    hipLaunchKernelGGL(k_seed, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, R->stream, R->d_key, R->d_origins,
-                       B, (long long)R->nn, R->d_fr[0], R->d_cnt);
-    RCHECK(R, hipMemsetAsync(R->d_u64, 0, sizeof(unsigned long long), R->stream));
+    hipLaunchKernelGGL(k_fill_keys, dim3(grid_for(n)), dim3(kBlock), 0, R->stream, b.key, b.stamp, b.fstamp, n);
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(kWave), 0, R->stream, b.cnt, b.u64);
+    hipLaunchKernelGGL(k_seed, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, R->stream, b.key, b.origins, B,
+                       (long long)R->nn, b.fr[0], b.cnt);
     RCHECK(R, hipGetLastError());
     const long long delta = R->delta > 0 ? R->delta : std::max<long long>(1, 3 * R->wsum / std::max(R->ne, 1));
     unsigned long long thr = (unsigned long long)delta;
@@ -487,12 +516,11 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
             const int g = relax_grid(est);
             for (int k = 0; k < kRoundsPerCheck; ++k, ++r) {
                 hipLaunchKernelGGL(k_relax, dim3(g), dim3(kBlock), 0, R->stream, R->d_row_ptr, R->d_col, R->d_w,
-                                   R->d_key, R->d_stamp, (long long)R->nn, R->d_fr[r & 1], R->d_fr[(r + 1) & 1],
-                                   R->d_cnt, r, R->d_u64, thr, R->d_fstamp, band, R->d_far[band & 1],
-                                   R->d_cnt + 3 + (band & 1));
+                                   b.key, b.stamp, (long long)R->nn, b.fr[r & 1], b.fr[(r + 1) & 1], b.cnt, r, b.u64,
+                                   thr, b.fstamp, band, b.far[band & 1], b.cnt + 3 + (band & 1));
             }
             RCHECK(R, hipGetLastError());
-            RCHECK(R, hipMemcpyAsync(c, R->d_cnt, sizeof(c), hipMemcpyDeviceToHost, R->stream));
+            RCHECK(R, hipMemcpyAsync(c, b.cnt, sizeof(c), hipMemcpyDeviceToHost, R->stream));
             RCHECK(R, hipStreamSynchronize(R->stream));
             launched += kRoundsPerCheck;
             if (c[r % 3] == 0) break;  // the frontier the next round would read
@@ -501,32 +529,108 @@ int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
         }
         if (c[3 + (band & 1)] == 0) break;  // nothing waits: every label is final
         // next band: far labels below the new threshold start the next round
-        RCHECK(R, hipMemsetAsync(R->d_cnt + 3 + ((band + 1) & 1), 0, sizeof(unsigned), R->stream));
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kWave), 0, R->stream, b.cnt + 3 + ((band + 1) & 1));
         thr += (unsigned long long)delta;
-        hipLaunchKernelGGL(k_split, dim3(grid_for(c[3 + (band & 1)])), dim3(kBlock), 0, R->stream, R->d_key,
-                           R->d_stamp, R->d_fstamp, R->d_far[band & 1], R->d_cnt + 3 + (band & 1), thr, band + 1,
-                           R->d_fr[r & 1], R->d_cnt, r, R->d_far[(band + 1) & 1], R->d_cnt + 3 + ((band + 1) & 1));
+        hipLaunchKernelGGL(k_split, dim3(grid_for(c[3 + (band & 1)])), dim3(kBlock), 0, R->stream, b.key, b.stamp,
+                           b.fstamp, b.far[band & 1], b.cnt + 3 + (band & 1), thr, band + 1, b.fr[r & 1], b.cnt, r,
+                           b.far[(band + 1) & 1], b.cnt + 3 + ((band + 1) & 1));
         RCHECK(R, hipGetLastError());
         est = c[3 + (band & 1)];  // the new frontier is part of the far list
         ++band;
     }
     unsigned long long w = 0;
-    RCHECK(R, hipMemcpyAsync(&w, R->d_u64, sizeof(w), hipMemcpyDeviceToHost, R->stream));
+    RCHECK(R, hipMemcpyAsync(&w, b.u64, sizeof(w), hipMemcpyDeviceToHost, R->stream));
     RCHECK(R, hipStreamSynchronize(R->stream));
     *relax += w;
     return SIM_OK;
 }
 
-int check_weight_sum(rt_t* R) {
-    RCHECK(R, hipMemsetAsync(R->d_u64 + 1, 0, sizeof(unsigned long long), R->stream));
-    hipLaunchKernelGGL(k_weight_sum, dim3(grid_for(R->ne)), dim3(kBlock), 0, R->stream, R->d_w, R->ne, R->d_u64 + 1);
+// shortest-path labels of origins[0..B) (host) in the handle's batch buffers
+int search(rt_t* R, const int* origins, int B, unsigned long long* relax) {
+    int rc = ensure_batch(R, B);
+    if (rc) return rc;
+    if ((rc = rh2d(R, R->d_origins, origins, (size_t)B))) return rc;
+    return search_in(R, handle_bufs(R), B, relax);
+}
+
+int check_weight_sum(rt_t* R, unsigned long long* word) {
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(kWave), 0, R->stream, nullptr, word);
+    hipLaunchKernelGGL(k_weight_sum, dim3(grid_for(R->ne)), dim3(kBlock), 0, R->stream, R->d_w, R->ne, word);
     RCHECK(R, hipGetLastError());
     unsigned long long s = 0;
-    RCHECK(R, hipMemcpyAsync(&s, R->d_u64 + 1, sizeof(s), hipMemcpyDeviceToHost, R->stream));
+    RCHECK(R, hipMemcpyAsync(&s, word, sizeof(s), hipMemcpyDeviceToHost, R->stream));
     RCHECK(R, hipStreamSynchronize(R->stream));
     if (s >= (1ull << (64 - kEdgeBits))) return rfail(R, SIM_EINVAL, "weights sum to 2^40 ms or more");
     R->wsum = (long long)s;
     return SIM_OK;
+}
+
+// Search scratch of rt_tree_static: one array per GPU, in the code object,
+// so that the call allocates nothing.  Host code never uses the array's name
+// as an address (it stands for a host-side shadow); every call on a device
+// first looks up the device address of that device's copy.
+static __device__ __align__(256) unsigned char scratch[RT_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// byte layout of the static scratch for a network of nn nodes (one origin):
+// counters, relaxation word, origin, then the per-node arrays; returns the
+// bytes needed
+size_t static_layout(long long nn, SearchBufs* b, unsigned char* base) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return base + at;
+    };
+    unsigned char* cnt = take(5 * sizeof(unsigned));
+    unsigned char* u64 = take(2 * sizeof(unsigned long long));
+    unsigned char* org = take(sizeof(int));
+    unsigned char* key = take(sizeof(unsigned long long) * nn);
+    unsigned char* st = take(sizeof(unsigned) * nn);
+    unsigned char* fst = take(sizeof(unsigned) * nn);
+    unsigned char* f0 = take(sizeof(unsigned) * nn);
+    unsigned char* f1 = take(sizeof(unsigned) * nn);
+    unsigned char* r0 = take(sizeof(unsigned) * nn);
+    unsigned char* r1 = take(sizeof(unsigned) * nn);
+    if (b) {
+        b->cnt = reinterpret_cast<unsigned*>(cnt);
+        b->u64 = reinterpret_cast<unsigned long long*>(u64);
+        b->origins = reinterpret_cast<int*>(org);
+        b->key = reinterpret_cast<unsigned long long*>(key);
+        b->stamp = reinterpret_cast<unsigned*>(st);
+        b->fstamp = reinterpret_cast<unsigned*>(fst);
+        b->fr[0] = reinterpret_cast<unsigned*>(f0);
+        b->fr[1] = reinterpret_cast<unsigned*>(f1);
+        b->far[0] = reinterpret_cast<unsigned*>(r0);
+        b->far[1] = reinterpret_cast<unsigned*>(r1);
+    }
+    return o;
+}
+
+// device address of the current device's static scratch (looked up once per
+// device); nullptr with the HIP error in *he on failure
+unsigned char* static_scratch(int dev, hipError_t* he) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        *he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*he != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *he = hipSuccess;
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_set_origin(int* o, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *o = v;
 }
 
 }  // namespace
@@ -549,6 +653,11 @@ int rt_create(const sim_network* net, void* hip_stream, sim_alloc_fn alloc, sim_
             !(net->length_m[e] >= 0) || !std::isfinite(net->length_m[e]) || !std::isfinite(net->speed_mps[e]))
             return SIM_EINVAL;
     rt_t* R = new rt_t();
+    if (hipGetDevice(&R->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete R;
+        return SIM_EHIP;
+    }
     R->stream = static_cast<hipStream_t>(hip_stream);
     R->alloc = alloc;
     R->free_fn = free_fn;
@@ -661,7 +770,7 @@ int rt_plan(rt_t* R, const uint8_t* select, int64_t* total_route_edges) {
     if (!R || !total_route_edges) return SIM_EINVAL;
     if (R->nsrc == 0) return rfail(R, SIM_ESTATE, "no trips set");
     if (select && !R->have_routes) return rfail(R, SIM_ESTATE, "a partial plan needs current routes");
-    int rc = check_weight_sum(R);
+    int rc = check_weight_sum(R, R->d_u64 + 1);
     if (rc) return rc;
     const int n = R->ntrips;
     // origins with a selected trip
@@ -750,7 +859,7 @@ int rt_read_routes(rt_t* R, int64_t* route_ptr, int32_t* route_edges) {
 
 int rt_tree(rt_t* R, int32_t src_node, int64_t* dist, int32_t* pred) {
     if (!R || src_node < 0 || src_node >= R->nn) return SIM_EINVAL;
-    int rc = check_weight_sum(R);
+    int rc = check_weight_sum(R, R->d_u64 + 1);
     if (rc) return rc;
     unsigned long long relax = 0;
     if ((rc = search(R, &src_node, 1, &relax))) return rc;
@@ -774,6 +883,38 @@ int rt_tree(rt_t* R, int32_t src_node, int64_t* dist, int32_t* pred) {
         (void)hipGetLastError();
         return rfail(R, SIM_EHIP, std::string("rt_tree: ") + hipGetErrorString(he));
     }
+    return SIM_OK;
+}
+
+int rt_tree_static(rt_t* R, int32_t src_node, int64_t* dist, int32_t* pred) {
+    if (!R || src_node < 0 || src_node >= R->nn) return SIM_EINVAL;
+    const size_t need = static_layout(R->nn, nullptr, nullptr);
+    if (need > (size_t)RT_STATIC_SCRATCH_BYTES)
+        return rfail(R, SIM_EINVAL, "rt_tree_static: a network of " + std::to_string(R->nn) + " nodes needs " +
+                                        std::to_string(need) + " bytes of search scratch, the static buffer holds " +
+                                        std::to_string((size_t)RT_STATIC_SCRATCH_BYTES));
+    int dev = -1;
+    RCHECK(R, hipGetDevice(&dev));
+    if (dev != R->device || dev < 0 || dev >= kMaxDevices)
+        return rfail(R, SIM_EINVAL, "rt_tree_static: call it with the router's device current");
+    hipError_t he = hipSuccess;
+    unsigned char* base = static_scratch(dev, &he);
+    if (!base) return rfail(R, SIM_EHIP, std::string("rt_tree_static: hipGetSymbolAddress: ") + hipGetErrorString(he));
+    SearchBufs b{};
+    static_layout(R->nn, &b, base);
+    int rc = check_weight_sum(R, b.u64 + 1);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_set_origin, dim3(1), dim3(kWave), 0, R->stream, b.origins, (int)src_node);
+    unsigned long long relax = 0;
+    if ((rc = search_in(R, b, 1, &relax))) return rc;
+    if (dist)
+        hipLaunchKernelGGL(k_dists, dim3(grid_for(R->nn)), dim3(kBlock), 0, R->stream, b.key, (long long)R->nn,
+                           (long long*)dist);
+    if (pred)
+        hipLaunchKernelGGL(k_preds, dim3(grid_for(R->nn)), dim3(kBlock), 0, R->stream, b.key, (long long)R->nn,
+                           (int*)pred);
+    RCHECK(R, hipGetLastError());
+    RCHECK(R, hipStreamSynchronize(R->stream));
     return SIM_OK;
 }
 

@@ -43,6 +43,8 @@ def _bind(lib):
     lib.rt_read_routes.restype = ctypes.c_int
     lib.rt_tree.argtypes = [P, i32, P, P]
     lib.rt_tree.restype = ctypes.c_int
+    lib.rt_tree_static.argtypes = [P, i32, P, P]
+    lib.rt_tree_static.restype = ctypes.c_int
     lib.rt_last_work.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
     lib.rt_last_work.restype = ctypes.c_int
     lib.rt_set_batch.argtypes = [P, i32]
@@ -147,6 +149,21 @@ class Router:
         pred = np.empty(self.num_nodes, np.int32)
         self._check(self.lib.rt_tree(self.h, int(src_node), _p(dist), _p(pred)))
         return dist, pred
+
+    def tree_static(self, src_node: int, dist, pred):
+        """rt_tree_static: the tree into the caller's DEVICE tensors dist
+        (int64 [num_nodes]) and pred (int32 [num_nodes]); allocates nothing."""
+        import torch
+        for t, dt in ((dist, torch.int64), (pred, torch.int32)):
+            if t is not None and (t.dtype != dt or not t.is_cuda or t.numel() != self.num_nodes or
+                                  not t.is_contiguous()):
+                raise ValueError("dist / pred must be contiguous %s device tensors of %d elements"
+                                 % (dt, self.num_nodes))
+        self.stream.synchronize()  # the tensors' memory is ready before the library's stream writes it
+        with torch.cuda.device(self.device):
+            self._check(self.lib.rt_tree_static(self.h, int(src_node),
+                                                None if dist is None else ctypes.c_void_p(dist.data_ptr()),
+                                                None if pred is None else ctypes.c_void_p(pred.data_ptr())))
 
     def last_work(self):
         r, s = ctypes.c_int64(0), ctypes.c_int32(0)
