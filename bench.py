@@ -53,7 +53,7 @@ def log(*a):
 
 KERNEL_SOURCES = ("paper_1807_01148_amd/csrc/common.h", "paper_1807_01148_amd/csrc/step_kernels.h")
 TRAFFIC_SUMMARY = "profiles/step_traffic_metro1M.md"
-STEP_KERNELS = ("k_decide", "k_change", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
+STEP_KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 def kernel_sources_sha():

@@ -213,11 +213,11 @@ int sim_set_control(sim_t* sim, const int32_t* node_control, int32_t signal_gree
 
 /* Per-kernel timing with HIP events on the handle's stream: when every > 0,
  * every `every`-th subsequent step launches each of its SIM_NUM_KERNELS
- * kernels (decide, change, resolve, scan, scatter, place, lanes) with a start
+ * kernels (decide, resolve, scan, scatter, place, lanes) with a start
  * and a stop event of its own (hipExtLaunchKernelGGL), which take that
  * kernel's begin and end timestamps; 0 disables.  Timing adds no
  * synchronisation to sim_step. */
-#define SIM_NUM_KERNELS 7
+#define SIM_NUM_KERNELS 6
 int sim_set_timing(sim_t* sim, int32_t every);
 
 /* Synchronise, then add the elapsed milliseconds of every sampled launch to

@@ -26,7 +26,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
             "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
-KERNELS = ("k_decide", "k_change", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
+KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
 class SimError(RuntimeError):

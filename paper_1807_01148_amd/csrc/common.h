@@ -189,12 +189,7 @@ __device__ __forceinline__ bool lane_rear(const LaneIx* __restrict__ lanes, int 
 }
 
 struct Scratch {
-    // vehicles listed for the lane-change evaluation: entry index, bit 31 set
-    // when the vehicle's movement at the link end is held this step
-    int* lc;      // kSeg segments of lc_seg entries
-    int* lcnt;    // their counters, kSegStride ints apart
-    int lc_seg;
-    int* ccnt;    // counters of the kSeg segments of the claim list (cl_*)
+    int* ccnt;    // counters of the kSeg segments of the claim list (cl_*), kSegStride ints apart
     int cl_seg;   // entries per claim segment
     unsigned long long* sstat;  // kSeg lines of per-XCD statistics
     float* xs;

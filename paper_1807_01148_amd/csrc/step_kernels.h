@@ -28,6 +28,32 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
+// A block takes the sorted entries in tiles of kBlock.  The tile and one entry
+// on either side sit in LDS, slot s holding entry b0 - 1 + s: the vehicle
+// ahead of an entry in its lane, the one behind it, and the run of a
+// neighbouring lane (the lanes of a link are consecutive keys, so their runs
+// are usually in the same tile) are then LDS reads.  A slot before the first
+// entry holds key -1 and a slot past the last entry key INT_MAX, so the keys
+// stay sorted over the whole window.
+struct Tile {
+    int key[kBlock + 2];
+    float x[kBlock + 2];
+    float v[kBlock + 2];
+    int ty[kBlock + 2];
+};
+constexpr int kKeyPast = 0x7FFFFFFF;
+
+// What the lane-change evaluation of a vehicle takes over from its step
+// decision: its entry, link records, own leader and own-lane acceleration.
+struct Own {
+    int i, k, e, nx, ty, vid, l;
+    float x, v, lme, ac;
+    bool held, front;
+    DrvRec D;
+    EdgeRec E2;  // next link's record: read by front vehicles only
+    Lead L;
+};
+
 // Own leader: the next entry if it is in the same lane (ka, xa, va, tya), else
 // the stop line if the movement at the link end is held, else the rearmost
 // vehicle of the mapped lane of the next link of the route (E2), if any.
@@ -57,32 +83,31 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
     return L;
 }
 
-__device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in,
-                               const Scratch& s, const Tape& tp, int N, int t, unsigned ep, unsigned long long tag,
-                               int i, int seg, int& clamps, int& arrivals, int& lc_listed) {
-    // Every read that does not depend on another is issued here, before the
-    // first branch: the own entry and the entry after it (its leader if it is
-    // in the same lane: same cache lines), then the records of the own link,
-    // the own type and the next link (the latter needed by the front vehicle
-    // of a lane and by a crossing).
-    const int k = in.key[i];
-    const float x = in.x[i];
-    const float v = in.v[i];
-    const int e = in.edge[i];
-    const int nx = in.next[i];
-    const int ty = in.ty[i];
-    const int vid = in.vid[i];
-    const int lcs = in.lc[i];
-    const int ia = i + 1 < N ? i + 1 : i;
-    const int ka = in.key[ia];
-    const float xa = in.x[ia], va = in.v[ia];
-    const int tya = in.ty[ia];
+// The step decision of entry i (tile slot t + 1): leader, IDM, move, crossing
+// claim or arrival.  Returns true when the vehicle is to be evaluated for a
+// lane change, with what that needs in o.
+__device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in, const Scratch& s,
+                               const Tape& tp, const Tile& T, int t_slot, int N, int t, unsigned ep,
+                               unsigned long long tag, int i, int seg, int e, int nx, int vid, int lcs, int& clamps,
+                               int& arrivals, Own& o) {
+    // the own entry and the one after it from the tile; the records of the
+    // own link and type, and for the front vehicle of a lane the next link's,
+    // issued before the first branch
+    const int k = T.key[t_slot];
+    const float x = T.x[t_slot];
+    const float v = T.v[t_slot];
+    const int ty = T.ty[t_slot];
+    const int ka = T.key[t_slot + 1];
+    const float xa = T.x[t_slot + 1], va = T.v[t_slot + 1];
+    const int tya = T.ty[t_slot + 1];
     const int nt = P.nt;
+    const bool front = !(i + 1 < N && ka == k);
     const DrvRec D = net.drv[e * nt + ty];
-    const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
+    EdgeRec E2 = {0.0f, 0, 1, 0};
+    if (front) E2 = net.er[nx >= 0 ? nx : e];
     const float len = D.len;
     const float lme = by_type(P.tlen, ty);  // own length
-    const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
+    const float iv = D.iv, A = D.A, Tg = D.T, kab = D.kab;
     const int lb = D.lane_base;
     const int nlanes = D.lanes_m & 0xFFFF;
     const int l = k - lb;
@@ -90,7 +115,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
     Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
     int own_fl = lead_flags(L);
-    const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
+    const float ac = idm_acc_fl(P, A, Tg, kab, iv, v, L, own_fl);
     float dx, vn;
     kin_move_fl(P, v, ac, dx, vn, own_fl);
     clamps += clamp_to_leader_fl(L, dx, vn, own_fl);
@@ -99,9 +124,9 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     if (s.samp_every > 0 && t % s.samp_every == 0) {
         const int g = (t / s.samp_every) / s.samp_group;
         if (g < s.samp_max) {
-            const size_t o = (size_t)g * (size_t)net.ne + (size_t)e;
-            atomicAdd(s.samp_cnt + o, 1ull);
-            atomicAdd(s.samp_spd + o, (unsigned long long)(long long)rintf(v * 1e6f));
+            const size_t so = (size_t)g * (size_t)net.ne + (size_t)e;
+            atomicAdd(s.samp_cnt + so, 1ull);
+            atomicAdd(s.samp_spd + so, (unsigned long long)(long long)rintf(v * 1e6f));
         }
     }
     if (tp.on) {
@@ -116,7 +141,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         tp.mode[i] = kModeStay;
     }
 
-    if (xs > len) {  // the front passes the link end strictly
+    if (xs > len) {  // the front passes the link end strictly (only a lane's front vehicle can)
         float fq = (len - x) / dx;
         if (!(fq < 1.0f)) own_fl |= kFFOne;
         float f = dx > 0.0f ? fmn(fq, 1.0f) : 0.0f;
@@ -133,7 +158,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             tr.arrive_step[vid] = t + 1;
             s.stay[i] = 0;
             arrivals += 1;
-            return;
+            return false;
         }
         int nl2 = E2.lanes;
         int tl = l < nl2 - 1 ? l : nl2 - 1;
@@ -145,7 +170,7 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
         push_claim(s, C2, E2.lane_base, seg, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
-        return;
+        return false;
     }
     s.xs[i] = xs;
     s.vs[i] = vn;
@@ -153,54 +178,65 @@ __device__ void decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     if (tp.on) tp.flags[i] = (unsigned short)own_fl;
 
     // lane change (Sec. 6.3.2): a vehicle past the cool-down on a multi-lane
-    // link is listed for k_change, which evaluates the listed vehicles in
-    // dense waves
-    if (nlanes < 2 || (t - lcs) < P.lc_cool || x < lme) return;
-    lc_listed += 1;
-    s.lc[(size_t)seg * s.lc_seg + wave_slot(s.lcnt + seg * kSegStride)] = (int)((unsigned)i | (held ? 0x80000000u : 0u));
+    // link that is not on its entry cells
+    if (nlanes < 2 || (t - lcs) < P.lc_cool || x < lme) return false;
+    o.i = i; o.k = k; o.e = e; o.nx = nx; o.ty = ty; o.vid = vid; o.l = l;
+    o.x = x; o.v = v; o.lme = lme; o.ac = ac;
+    o.held = held; o.front = front;
+    o.D = D; o.E2 = E2; o.L = L;
+    return true;
 }
 
-// Lane-change evaluation of one listed vehicle (Sec. 6.3.2): candidate lanes
-// (the mandatory one when the vehicle is outside its turn band near the link
+// Run of lane kt in the sorted arrays, from the tile when the tile decides it
+// (the slots before and after the lane's slots in the window are known to
+// hold other lanes or the array's ends): in [lo, hi] (tile slots) with
+// *empty when the lane has no vehicle.  Returns false when the run may reach
+// beyond the window.
+__device__ __forceinline__ bool tile_run(const Tile& T, int kt, int& lo, int& hi) {
+    int a = 0, b = kBlock + 2;  // first slot with key >= kt
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (T.key[mid] < kt) a = mid + 1;
+        else b = mid;
+    }
+    int c = a, d = kBlock + 2;  // first slot with key > kt
+    while (c < d) {
+        const int mid = (c + d) >> 1;
+        if (T.key[mid] <= kt) c = mid + 1;
+        else d = mid;
+    }
+    lo = a;
+    hi = c - 1;
+    return a > 0 && c < kBlock + 2;
+}
+
+// Lane-change evaluation of a vehicle (Sec. 6.3.2): candidate lanes (the
+// mandatory one when the vehicle is outside its turn band near the link
 // end, else the neighbours inside the band), gap acceptance, the safety
 // criterion for the new follower, the incentive criterion; the best candidate
-// claims its cells in the target lane.
+// claims its cells in the target lane.  The follower, and the leader and lag
+// in a target lane whose run the tile holds, come from LDS; other runs from
+// the lane index and the sorted arrays.
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               int N, unsigned ep, unsigned long long tag, int rec, int seg) {
-    // independent reads first (as in decide_vehicle): the own entry and the
-    // ones behind and ahead of it (follower and leader if in the same lane),
-    // then the records of the own link, the types involved and the next link
-    const int i = rec & 0x7FFFFFFF;
-    const bool held = rec < 0;
-    const int k = in.key[i];
-    const float x = in.x[i];
-    const float v = in.v[i];
-    const int e = in.edge[i];
-    const int nx = in.next[i];
-    const int ty = in.ty[i];
-    const int vid = in.vid[i];
-    const int ib = i > 0 ? i - 1 : i;
-    const int kb = in.key[ib];
-    const float xb = in.x[ib], vb = in.v[ib];
-    const int tyb = in.ty[ib];
-    const int ia = i + 1 < N ? i + 1 : i;
-    const int ka = in.key[ia];
-    const float xa = in.x[ia], va = in.v[ia];
-    const int tya = in.ty[ia];
+                               const Tile& T, int t_slot, int b0, unsigned ep, unsigned long long tag, int seg,
+                               const Own& o) {
+    const int i = o.i, k = o.k, e = o.e, nx = o.nx, ty = o.ty, vid = o.vid, l = o.l;
+    const float x = o.x, v = o.v, lme = o.lme, ac = o.ac;
+    const bool held = o.held;
+    const DrvRec& D = o.D;
+    const Lead& L = o.L;
     const int nt = P.nt;
-    const DrvRec D = net.drv[e * nt + ty];
-    const DrvRec Db = net.drv[e * nt + tyb];
+    const int kb = T.key[t_slot - 1];
+    const float xb = T.x[t_slot - 1], vb = T.v[t_slot - 1];
+    const int tyb = T.ty[t_slot - 1];
+    const bool hasF = i > 0 && kb == k;
+    // the follower's driver constants: the own record when the types agree
+    DrvRec Db = D;
+    if (hasF && tyb != ty) Db = net.drv[e * nt + tyb];
     const int m = D.lanes_m >> 16;
-    const EdgeRec E2 = net.er[nx >= 0 ? nx : e];
     const float len = D.len;
-    const float lme = by_type(P.tlen, ty);
-    const float iv = D.iv, A = D.A, T = D.T, kab = D.kab;
+    const float iv = D.iv, A = D.A, Tg = D.T, kab = D.kab;
     const int lb = D.lane_base;
-    const int l = k - lb;
-    // the own leader and own-lane acceleration, as k_decide found them
-    const Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
-    int own_fl = lead_flags(L);
-    const float ac = idm_acc_fl(P, A, T, kab, iv, v, L, own_fl);
     const int n = D.lanes_m & 0xFFFF;
     int blo = 0, bhi = n - 1;
     if (nx >= 0) {
@@ -224,50 +260,76 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             cand[nc++] = sd;
         }
     }
-    const bool hasF = i > 0 && kb == k;
     const float xF = hasF ? xb : 0.0f;
     const float vF = hasF ? vb : 0.0f;
+    EdgeRec E2 = o.E2;
+    bool haveE2 = o.front;
 
     int best = -1, best_fl = 0, best_lead = -1;
     float best_inc = 0.0f, best_X = 0.0f, best_v = 0.0f;
     for (int ci = 0; ci < nc; ++ci) {
         const int lt = cand[ci];
         const int kt = lb + lt;
-        // first vehicle of the target lane strictly ahead; the one before it
-        // (position <= x) is the lag
-        int tlo, thi;
-        const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
-        int j = occ ? ub_x(in.x, tlo, thi + 1, x) : -1;
+        // first vehicle of the target lane strictly ahead (position > x) and
+        // the one before it, the lag
+        bool hasLead = false, hasFt = false;
+        int jl = -1;
+        float xl = 0.0f, vl = 0.0f, xFt = 0.0f, vFt = 0.0f;
+        int tyl = 0, tyFt = 0;
+        int ra, rb;
+        if (tile_run(T, kt, ra, rb)) {
+            int a = ra, c = rb + 1;  // first slot in the run with x > own x
+            while (a < c) {
+                const int mid = (a + c) >> 1;
+                if (T.x[mid] <= x) a = mid + 1;
+                else c = mid;
+            }
+            hasLead = a <= rb;
+            hasFt = a - 1 >= ra;
+            const int sl = hasLead ? a : t_slot, sf = hasFt ? a - 1 : t_slot;
+            jl = b0 - 1 + a;
+            xl = T.x[sl]; vl = T.v[sl]; tyl = T.ty[sl];
+            xFt = T.x[sf]; vFt = T.v[sf]; tyFt = T.ty[sf];
+        } else {
+            int tlo, thi;
+            const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
+            const int j = occ ? ub_x(in.x, tlo, thi + 1, x) : -1;
+            hasLead = occ && j <= thi;
+            hasFt = occ && j - 1 >= tlo;
+            jl = j;
+            if (hasLead) { xl = in.x[j]; vl = in.v[j]; tyl = in.ty[j]; }
+            if (hasFt) { xFt = in.x[j - 1]; vFt = in.v[j - 1]; tyFt = in.ty[j - 1]; }
+        }
         Lead Lt = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
-        if (occ && j <= thi) {
-            float xl = in.x[j];
-            Lt.kind = 1; Lt.xl = xl; Lt.vl = in.v[j]; Lt.ll = by_type(P.tlen, in.ty[j]); Lt.s = (xl - Lt.ll) - x;
-            Lt.idx = j;
+        if (hasLead) {
+            Lt.kind = 1; Lt.xl = xl; Lt.vl = vl; Lt.ll = by_type(P.tlen, tyl); Lt.s = (xl - Lt.ll) - x;
+            Lt.idx = jl;
         } else if (held) {
             Lt = stop_line_lead(len, x);
         } else if (nx >= 0) {
+            if (!haveE2) {
+                E2 = net.er[nx];
+                haveE2 = true;
+            }
             int nl2 = E2.lanes;
             int k2 = E2.lane_base + (lt < nl2 - 1 ? lt : nl2 - 1);
             int j2, tyr;
-            float xl, vr;
-            const bool ok = lane_rear(s.lanes, k2, ep, j2, xl, vr, tyr);
+            float xr, vr;
+            const bool ok = lane_rear(s.lanes, k2, ep, j2, xr, vr, tyr);
             const float ll = by_type(P.tlen, tyr);
             Lt.kind = ok ? 2 : 0;
-            Lt.xl = ok ? xl : 0.0f;
+            Lt.xl = ok ? xr : 0.0f;
             Lt.vl = ok ? vr : 0.0f;
             Lt.ll = ok ? ll : 0.0f;
-            Lt.s = ok ? (len - x) + (xl - ll) : 0.0f;
+            Lt.s = ok ? (len - x) + (xr - ll) : 0.0f;
             Lt.idx = ok ? j2 : -1;
         }
-        const bool hasFt = occ && j - 1 >= tlo;
-        const float xFt = hasFt ? in.x[j - 1] : 0.0f;
-        const float vFt = hasFt ? in.v[j - 1] : 0.0f;
-        const int tyFt = hasFt ? in.ty[j - 1] : 0;
+        if (!hasFt) { xFt = 0.0f; vFt = 0.0f; tyFt = 0; }
         // gap acceptance (Sec. 6.3.2)
         if (Lt.kind != 0 && Lt.s < P.s0) continue;
         if (hasFt && ((x - lme) - xFt) < P.s0) continue;
         int tfl = lead_flags(Lt);
-        const float at = idm_acc_fl(P, A, T, kab, iv, v, Lt, tfl);
+        const float at = idm_acc_fl(P, A, Tg, kab, iv, v, Lt, tfl);
         if (at < -P.bsafe) continue;
         float dxt, vt;
         kin_move_fl(P, v, at, dxt, vt, tfl);
@@ -276,14 +338,15 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         if (Xt >= len) continue;
         float an = 0.0f, ant = 0.0f;
         if (hasFt) {  // the lag follows with its own type's constants
-            const DrvRec Df = net.drv[e * nt + tyFt];
+            DrvRec Df = D;
+            if (tyFt != ty) Df = net.drv[e * nt + tyFt];
             const float Af = Df.A, kf = Df.kab, ivf = Df.iv;
-            an = idm_acc(P, Af, T, kf, ivf, vFt, relead(len, Lt, xFt));
+            an = idm_acc(P, Af, Tg, kf, ivf, vFt, relead(len, Lt, xFt));
             Lead Li = {1, (x - lme) - xFt, v, x, i, lme};
-            ant = idm_acc(P, Af, T, kf, ivf, vFt, Li);
+            ant = idm_acc(P, Af, Tg, kf, ivf, vFt, Li);
             if (ant < -P.bsafe) continue;
             Lead none = {0, 0.0f, 0.0f, 0.0f, -1, 0.0f};
-            float afree = idm_acc(P, Af, T, kf, ivf, vFt, none);
+            float afree = idm_acc(P, Af, Tg, kf, ivf, vFt, none);
             float dxF, vF2;
             kin_move(P, vFt, afree, dxF, vF2);
             if (((Xt - lme) - xFt) < dxF) continue;
@@ -296,8 +359,8 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             if (hasF) {
                 const float Af = Db.A, kf = Db.kab, ivf = Db.iv;
                 Lead Lo = {1, (x - lme) - xF, v, x, i, lme};
-                float ao = idm_acc(P, Af, T, kf, ivf, vF, Lo);
-                float aot = idm_acc(P, Af, T, kf, ivf, vF, relead(len, L, xF));
+                float ao = idm_acc(P, Af, Tg, kf, ivf, vF, Lo);
+                float aot = idm_acc(P, Af, Tg, kf, ivf, vF, relead(len, L, xF));
                 d3 = aot - ao;
             }
             inc = d1 + P.pol * (d2 + d3);
@@ -364,9 +427,11 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
 
 // The first qblocks blocks (a multiple of kSeg) take the departure queues, one
 // thread per queue; the others the vehicles on the road, one thread per
-// vehicle.  The two parts share nothing but the claim list.
-__global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                                   Counters* ctr, int qblocks) {
+// vehicle: the step decision of every vehicle of a tile, then, for the
+// vehicles it lists, the lane-change evaluation in the same thread.  The two
+// parts share nothing but the claim list.  7 waves per SIMD (no spills).
+__global__ __launch_bounds__(kBlock) void k_decide(
+    Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp, Counters* ctr, int qblocks) {
     const int t = ctr->t;
     const int N = ctr->n;
     const unsigned ep = *s.epoch;
@@ -384,50 +449,77 @@ __global__ __launch_bounds__(kBlock) void k_decide(Params P, Net net, Trips tr, 
         }
         return;
     }
+    __shared__ Tile T;
     // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
-    // the q-th eighth of the sorted entries, 256-entry chunks in order, so
-    // that the link and lane records of neighbouring vehicles are shared in
-    // that XCD's L2; q is also the segment of every list entry they append
+    // the q-th eighth of the sorted entries, tiles in order, so that the link
+    // and lane records of neighbouring vehicles are shared in that XCD's L2;
+    // q is also the segment of every claim they append
     const int vb = blockIdx.x - qblocks;
     const int per = (gridDim.x - qblocks) / kSeg;
     const int q = vb & (kSeg - 1);
     const int nch = (N + kBlock - 1) / kBlock;
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
-    int clamps = 0, arrivals = 0, listed = 0;
+    const int ts = threadIdx.x + 1;  // this thread's slot in the tile
+    int clamps = 0, arrivals = 0, listed = 0, claims = 0;
     if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
     for (int c = (int)(((long long)nch * q) / kSeg) + vb / kSeg; c < c_end; c += per) {
-        const int i = c * kBlock + threadIdx.x;
-        if (i < N) decide_vehicle(P, net, tr, in, s, tp, N, t, ep, tag, i, q, clamps, arrivals, listed);
+        const int b0 = c * kBlock;
+        const int i = b0 + threadIdx.x;
+        // the tile and its two neighbours into LDS; the rest of the own entry
+        // into registers
+        int e = 0, nx = -1, vid = 0, lcs = 0;
+        if (i < N) {
+            T.key[ts] = in.key[i];
+            T.x[ts] = in.x[i];
+            T.v[ts] = in.v[i];
+            T.ty[ts] = in.ty[i];
+            e = in.edge[i];
+            nx = in.next[i];
+            vid = in.vid[i];
+            lcs = in.lc[i];
+        } else {
+            T.key[ts] = kKeyPast;
+            T.x[ts] = 0.0f;
+            T.v[ts] = 0.0f;
+            T.ty[ts] = 0;
+        }
+        if (threadIdx.x == 0) {
+            const bool has = b0 > 0;
+            T.key[0] = has ? in.key[b0 - 1] : -1;
+            T.x[0] = has ? in.x[b0 - 1] : 0.0f;
+            T.v[0] = has ? in.v[b0 - 1] : 0.0f;
+            T.ty[0] = has ? (int)in.ty[b0 - 1] : 0;
+        }
+        if (threadIdx.x == kBlock - 1) {
+            const int j = b0 + kBlock;
+            const bool has = j < N;
+            T.key[kBlock + 1] = has ? in.key[j] : kKeyPast;
+            T.x[kBlock + 1] = has ? in.x[j] : 0.0f;
+            T.v[kBlock + 1] = has ? in.v[j] : 0.0f;
+            T.ty[kBlock + 1] = has ? (int)in.ty[j] : 0;
+        }
+        __syncthreads();
+        if (i < N) {
+            Own o;
+            if (decide_vehicle(P, net, tr, in, s, tp, T, ts, N, t, ep, tag, i, q, e, nx, vid, lcs, clamps, arrivals,
+                               o)) {
+                listed += 1;
+                claims += change_vehicle(P, net, in, s, tp, T, ts, b0, ep, tag, q, o) ? 1 : 0;
+            }
+        }
+        __syncthreads();  // the tile is overwritten next
     }
     if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
     unsigned long long lw = wave_sum_u64((unsigned long long)listed);
+    unsigned long long mw = wave_sum_u64((unsigned long long)claims);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         seg_stat(s, kStClamps, cw);
         seg_stat(s, kStArrived, aw);
         seg_stat(s, kStLcEval, lw);
+        seg_stat(s, kStLcClaims, mw);
     }
-}
-
-// lane changes: one thread per listed vehicle; the grid is a multiple of kSeg
-// and block b reads segment b % kSeg.  7 waves per SIMD instead of the 6 its
-// registers would otherwise allow (no spills): more evaluations in flight to
-// cover the gathers.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_change(
-    Params P, Net net, Veh in, Scratch s, Tape tp, Counters* ctr) {
-    const int N = ctr->n;
-    const int q = blockIdx.x & (kSeg - 1);
-    const int M = s.lcnt[q * kSegStride];
-    const int* list = s.lc + (size_t)q * s.lc_seg;
-    const int nb = gridDim.x / kSeg;
-    const unsigned ep = *s.epoch;
-    const unsigned long long tag = epoch_tag(ep);
-    int claims = 0;
-    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock)
-        claims += change_vehicle(P, net, in, s, tp, N, ep, tag, list[j], q) ? 1 : 0;
-    const unsigned long long cw = wave_sum_u64((unsigned long long)claims);
-    if ((threadIdx.x & (kWave - 1)) == 0) seg_stat(s, kStLcClaims, cw);
 }
 
 
@@ -822,7 +914,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             v[kStDeparted + 1] = (unsigned long long)s.ccnt[q * kSegStride];
             for (int w = 0; w < kStatStride; ++w) st[w] = 0;
             s.ccnt[q * kSegStride] = 0;
-            s.lcnt[q * kSegStride] = 0;
             s.mvcnt[q * kSegStride] = 0;
         }
         for (int w = 0; w < kStDeparted + 2; ++w) v[w] = wave_sum_u64(v[w]);

@@ -7,10 +7,12 @@
 //              Other blocks, per vehicle: leader search, IDM acceleration
 //              (Sec. 6.3.2, car-following equation), ballistic update,
 //              link-end crossing (claim) or arrival (Sec. 6.3.1 routes);
-//              vehicles that may change lanes are listed.
-//   k_change   per listed vehicle: lane-change candidates, gap acceptance,
-//              safety and incentive (Sec. 6.3.2 lane changing); the best
-//              candidate claims.  Claims take one-metre cells of their target
+//              then, in the same thread, for a vehicle that may change
+//              lanes: candidates, gap acceptance, safety and incentive
+//              (Sec. 6.3.2 lane changing); the best candidate claims.  The
+//              block's tile of the sorted arrays sits in LDS, so the vehicles
+//              around a vehicle, in its lane and the neighbouring ones, are
+//              mostly LDS reads.  Claims take one-metre cells of their target
 //              lane with a 64-bit atomicMin of (epoch, vehicle id).
 //   k_resolve  per claim: it wins iff it still owns all its cells (no
 //              overlapping claim with a lower id); winners find their gap in
@@ -104,7 +106,6 @@ struct sim_t {
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
     int grid_small = 1;  // k_scan's persistent blocks
-    int change_res = 0;  // k_change blocks resident on the whole device at once (a multiple of kSeg; 0 unknown)
     int grid_q = 1;      // k_decide's departure-queue blocks: one thread per queue
     std::vector<int> h_rbeg;
     int timing_every = 0;
@@ -271,29 +272,19 @@ int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
             hipLaunchKernelGGL(kern, grid, b, 0, S->stream, __VA_ARGS__);                               \
     } while (0)
 
-// k_change's grid: the whole number of device-wide waves of resident blocks
-// nearest to the other kernels' grid, so that no partly filled wave trails
-// the launch (the others keep theirs: measured, only k_change gains)
-int change_grid(int g8, int res) {
-    if (res <= 0 || g8 < res) return g8;
-    return (g8 + res / 2) / res * res;
-}
-
 int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
     const dim3 g(S->grid), gs(S->grid_small), b(kBlock);
     // kernels that read the per-XCD segments run a multiple of kSeg blocks
     const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg);
-    const dim3 gc(change_grid((int)g8.x, S->change_res));
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
     STEP_LAUNCH(0, k_decide, dim3(qb + g8.x), S->P, S->net, tr, in, sc, tp, ctr, qb);
-    STEP_LAUNCH(1, k_change, gc, S->P, S->net, in, sc, tp, ctr);
-    STEP_LAUNCH(2, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
-    STEP_LAUNCH(3, k_scan, gs, sc, ctr);
-    STEP_LAUNCH(4, k_scatter, g8, S->P, in, out, sc, tp, ctr);
-    STEP_LAUNCH(5, k_place, g8, S->P, tr, in, out, sc, tp, kLcNone, ctr);
-    STEP_LAUNCH(6, k_lanes, g, S->P, S->net, out, sc, ctr, 1);
+    STEP_LAUNCH(1, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
+    STEP_LAUNCH(2, k_scan, gs, sc, ctr);
+    STEP_LAUNCH(3, k_scatter, g8, S->P, in, out, sc, tp, ctr);
+    STEP_LAUNCH(4, k_place, g8, S->P, tr, in, out, sc, tp, kLcNone, ctr);
+    STEP_LAUNCH(5, k_lanes, g, S->P, S->net, out, sc, ctr, 1);
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
 }
@@ -432,14 +423,6 @@ int sim_create(const sim_network* net, const sim_params* prm, void* hip_stream, 
 
     sim_t* S = new sim_t();
     S->stream = static_cast<hipStream_t>(hip_stream);
-    {
-        int dev = 0, cus = 0, nb = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_change, kBlock, 0) == hipSuccess && cus > 0 && nb > 0)
-            S->change_res = (cus * nb + kSeg - 1) / kSeg * kSeg;
-        (void)hipGetLastError();
-    }
     S->alloc = alloc;
     S->free_fn = free_fn;
     S->ctx = alloc_ctx;
@@ -755,12 +738,13 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
              dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap) && dalloc(S, V.ty, cap);
     }
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
-    // segment q holds the candidates of one eighth of the chunks of kBlock entries
-    s.lc_seg = (int)(((size_t)(cap + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
-    // a claim segment also takes the departures of queue chunks q, q + kSeg, ...
-    s.cl_seg = s.lc_seg + (int)(((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
+    // claim segment q takes the claims of one eighth of the tiles of kBlock
+    // entries (at most one per vehicle) and the departures of queue chunks
+    // q, q + kSeg, ...
+    const size_t vseg = ((size_t)(cap + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock;
+    s.cl_seg = (int)(vseg + ((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
     const size_t ncl = (size_t)kSeg * s.cl_seg;
-    ok = ok && dalloc(S, s.lc, (size_t)kSeg * s.lc_seg) && dalloc(S, s.lcnt, (size_t)3 * kSeg * kSegStride) &&
+    ok = ok && dalloc(S, s.ccnt, (size_t)2 * kSeg * kSegStride) &&
          dalloc(S, s.sstat, (size_t)kSeg * kStatStride) &&
          dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
          dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && dalloc(S, s.cl_vid, ncl) &&
@@ -783,9 +767,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     std::vector<int> da(cap, init_x ? t0 : -1);
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
     HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
-    s.ccnt = s.lcnt + kSeg * kSegStride;
-    s.mvcnt = s.lcnt + 2 * kSeg * kSegStride;
-    HIPCHECK(S, hipMemsetAsync(s.lcnt, 0, sizeof(int) * 3 * kSeg * kSegStride, S->stream));
+    s.mvcnt = s.ccnt + kSeg * kSegStride;
+    HIPCHECK(S, hipMemsetAsync(s.ccnt, 0, sizeof(int) * 2 * kSeg * kSegStride, S->stream));
     HIPCHECK(S, hipMemsetAsync(s.sstat, 0, sizeof(unsigned long long) * kSeg * kStatStride, S->stream));
     if (nq) HIPCHECK(S, hipMemsetAsync(S->qstate, 0, sizeof(int) * 2 * (size_t)nq, S->stream));
     HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));

@@ -33,7 +33,7 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
     write_summary(tmp_path / "summary.md", sha)
     tr = bench.measured_traffic()
     assert sorted(tr) == sorted(bench.STEP_KERNELS)
-    assert tr["k_decide"] == (1000.0, 24.0) and tr["k_lanes"] == (1000.0, 6.0)
+    assert tr["k_decide"] == (1000.0, 24.0) and tr["k_lanes"] == (1000.0, float(bench.STEP_KERNELS.index("k_lanes")))
     assert bench.measured_traffic("metro", 18300) == tr
     # counters of another window or workload do not describe this one
     assert bench.measured_traffic("metro", 7205) is None
