@@ -188,20 +188,22 @@ def ensemble_scenarios(seed=1811, n=64, steps=3600):
     return out
 
 
-def bench_ensemble(args):
-    """Batched ensemble (one simulation, graph-captured 60-step chunks, tuned
-    launch shape) against the plain loop (each scenario its own simulation,
-    plain launches), same steps; per-scenario results compared bit for bit."""
+def ensemble_speedup(args, n=64, log_prefix="[ensemble]"):
+    """Batched ensemble (one simulation of all scenarios, graph-captured
+    chunks, tuned launch shape) against the per-scenario GPU loops (each
+    scenario its own simulation, same steps): once with plain launches and
+    once with the same graph-captured chunks; every scenario's link statistics
+    and trip outcomes compared bit for bit with its own run."""
     import numpy as np
     import torch
     import paper_1807_01148_amd as P
     from paper_1807_01148_amd import ensemble as E
     steps = 3600
-    log("[ensemble] generating %d scenarios" % args.scenarios)
+    log("%s generating %d scenarios" % (log_prefix, n))
     t = time.perf_counter()
-    scens = ensemble_scenarios(n=args.scenarios, steps=steps)
-    log("[ensemble] generated in %.1f s, %d trips" % (time.perf_counter() - t,
-                                                      sum(s["demand"]["depart_step"].size for s in scens)))
+    scens = ensemble_scenarios(n=n, steps=steps)
+    log("%s generated in %.1f s, %d trips" % (log_prefix, time.perf_counter() - t,
+                                              sum(s["demand"]["depart_step"].size for s in scens)))
     ens = E.Ensemble(scens)
     E.step_graph(ens, 60, args.chunk)
     tune = E.autotune(ens, steps_per_trial=60)
@@ -212,114 +214,179 @@ def bench_ensemble(args):
     t_batch = time.perf_counter() - t0
     cb = ens.counters()
     est, etr = ens.edge_stats(), ens.trips()
-    log("[ensemble] batched: %.3f s, %d vehicle-updates" % (t_batch, cb["vehicle_updates"]))
-    t_loop = 0.0
-    upd_loop = 0
+    log("%s batched: %.3f s, %d vehicle-updates" % (log_prefix, t_batch, cb["vehicle_updates"]))
+    loops = {}
     same = True
-    for q, sc in enumerate(scens):
-        one = P.Sim(sc)
-        one.step(60)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        one.step(steps - 60)
-        torch.cuda.synchronize()
-        t_loop += time.perf_counter() - t0
-        upd_loop += one.counters()["vehicle_updates"]
-        a, b = ens.scenario_edge_stats(q, est), one.edge_stats()
-        same &= all(np.array_equal(a[k], b[k]) for k in b)
-        vid = E.vehicle_ids(sc["demand"]["depart_step"])
-        ta, tb = ens.scenario_trips(q, etr), one.trips()
-        same &= all(np.array_equal(ta[k], tb[k][vid]) for k in tb)
-        one.close()
-        if q % 8 == 7:
-            log("[ensemble] plain loop: %d / %d scenarios" % (q + 1, len(scens)))
-    out = {"metric": "ensemble speed-up over the plain per-scenario GPU loop", "value": t_loop / t_batch,
-           "unit": "x", "n_gpus": 1, "steps": steps - 60, "warmup": 60, "higher_is_better": True,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "%d grid scenarios, side 20-120, 1e4-3e5 trips each, per-scenario IDM, "
-                                  "3,600 steps" % len(scens), "launch": tune},
-           "batched_s": t_batch, "plain_loop_s": t_loop,
-           "batched_vehicle_updates_per_s": (cb["vehicle_updates"]) / t_batch,
-           "plain_loop_vehicle_updates_per_s": upd_loop / t_loop,
-           "bitwise_identical_per_scenario": bool(same)}
+    for mode in ("plain", "graphs"):
+        t_loop, upd_loop = 0.0, 0
+        for q, sc in enumerate(scens):
+            one = P.Sim(sc)
+            if mode == "graphs":
+                E.step_graph(one, 60, args.chunk)
+            else:
+                one.step(60)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "graphs":
+                E.step_graph(one, steps - 60, args.chunk)
+            else:
+                one.step(steps - 60)
+            torch.cuda.synchronize()
+            t_loop += time.perf_counter() - t0
+            upd_loop += one.counters()["vehicle_updates"]
+            a, b = ens.scenario_edge_stats(q, est), one.edge_stats()
+            same &= all(np.array_equal(a[k], b[k]) for k in b)
+            vid = E.vehicle_ids(sc["demand"]["depart_step"])
+            ta, tb = ens.scenario_trips(q, etr), one.trips()
+            same &= all(np.array_equal(ta[k], tb[k][vid]) for k in tb)
+            one.close()
+        loops[mode] = (t_loop, upd_loop)
+        log("%s per-scenario loop (%s launches): %.3f s" % (log_prefix, mode, t_loop))
+    ens.close()
+    return {"workload": "%d grid scenarios, side 20-120, 1e4-3e5 trips each, per-scenario IDM, 3,600 steps" % n,
+            "launch": tune, "batched_s": t_batch, "plain_loop_s": loops["plain"][0],
+            "graph_loop_s": loops["graphs"][0],
+            "speedup_over_plain_loop": loops["plain"][0] / t_batch,
+            "speedup_over_graph_loop": loops["graphs"][0] / t_batch,
+            "batched_vehicle_updates_per_s": cb["vehicle_updates"] / t_batch,
+            "plain_loop_vehicle_updates_per_s": loops["plain"][1] / loops["plain"][0],
+            "graph_loop_vehicle_updates_per_s": loops["graphs"][1] / loops["graphs"][0],
+            "bitwise_identical_per_scenario": bool(same)}
+
+
+def bench_ensemble(args):
+    r = ensemble_speedup(args, n=args.scenarios)
+    out = {"metric": "ensemble speed-up over the per-scenario GPU loop (graph-captured launches)",
+           "value": r["speedup_over_graph_loop"], "unit": "x", "n_gpus": 1, "steps": 3540, "warmup": 60,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": r["workload"], "launch": r["launch"]}, "detail": r}
     print(json.dumps(out), flush=True)
 
 
-def bench_adjoint(args):
+def adjoint_speedup(seed=1812, log_prefix="[adjoint]"):
     """Gradient of the link travel-time MSE w.r.t. 16 IDM parameters (4 link
-    classes) on the differentiation workload: adjoint (one taped forward + one
-    backward) against central finite differences with 32 plain GPU runs;
-    both compared with the FP64 CPU adjoint linearized at the same trajectory."""
+    classes, (v0_scale, T, a, b)) on the differentiation workload, three ways:
+      * adjoint: one taped forward (checkpoint every 60 steps) + sim_grad;
+      * the per-parameter loop at equal accuracy: central differences
+        (h = 1e-3) of the frozen-event replay, 32 replays of the recorded
+        window plus the forward that records it;
+      * the plain per-scenario loop: central differences over 32 plain GPU
+        runs (the events move with the parameters).
+    Accuracy of each against the FP64 CPU adjoint of the FP32 oracle's tape
+    (the oracle's forward is bit-identical to the GPU's), linearized at the
+    recorded states and along the FP64-replayed states."""
     import numpy as np
     import torch
     import oracle
     import paper_1807_01148_amd as P
     import scenarios as S
-    scen = S.diff_scenario()
+    scen = S.diff_scenario(seed=seed)
     steps = scen["steps"]
-    log("[adjoint] generated")
+    dt = float(np.float32(scen["params"]["dt"]))
 
-    def run(idm, tape=False):
+    def run(idm, every=0):
         sc = dict(scen)
         sc["params"] = dict(scen["params"])
         sc["params"]["idm"] = np.asarray(idm, np.float32)
         sim = P.Sim(sc)
-        if tape:
-            sim.tape_begin(60)
+        if every:
+            sim.tape_begin(every)
         sim.step(steps)
         return sim
 
     hid = run(scen["hidden_idm"])
-    tgt, cnt_t = hid.mean_travel_times()
+    tgt, _ = hid.mean_travel_times()
     hid.close()
-    theta = scen["params"]["idm"].astype(np.float64)
+    theta = scen["params"]["idm"].astype(np.float32)
 
-    def loss_of(sim):
+    def loss_terms(sim):
         tb, cnt = sim.mean_travel_times()
         m = cnt > 0
-        return tb, m, float(((tb - tgt)[m] ** 2).mean())
+        return tb, cnt, m, float(((tb - tgt)[m] ** 2).mean())
 
+    # warm-up (first launches, allocator)
+    w = run(theta)
+    w.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim = run(theta, tape=True)
-    tb, m, L = loss_of(sim)
+    sim = run(theta, every=60)
+    tb, cnt, m, L = loss_terms(sim)
     dL = torch.where(m, 2.0 * (tb - tgt) / int(m.sum()), torch.zeros_like(tb))
     g_adj = sim.grad(dL).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     sim.close()
-    log("[adjoint] adjoint gradient in %.3f s" % t_adj)
-    h = 1e-3
-    g_fd = np.zeros_like(theta)
+    log("%s adjoint gradient in %.3f s" % (log_prefix, t_adj))
+
+    tgt_np = tgt.double().cpu().numpy()
+    # central differences of the frozen-event replay (double, h = 1e-6): the
+    # window recorded as one segment, then 32 replays
+    hr = 1e-6
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    rs = run(theta, every=steps)
+    tb0, cnt0, m0, _ = loss_terms(rs)
+    tb0 = tb0.double().cpu().numpy()
+    c0 = np.maximum(cnt0.cpu().numpy(), 1)
+    mk = m0.cpu().numpy()
+    th0 = theta.astype(np.float64)
+    F0 = rs.replay(th0, fp64=True)
+    g_rep = np.zeros(theta.shape, np.float64)
     for c in range(theta.shape[0]):
         for j in range(4):
-            a, b = theta.copy(), theta.copy()
+            lv = []
+            for sgn in (1.0, -1.0):
+                th = th0.copy()
+                th[c, j] += sgn * hr
+                tbp = tb0 + dt * (rs.replay(th, fp64=True) - F0) / c0
+                lv.append(float(((tbp - tgt_np)[mk] ** 2).mean()))
+            g_rep[c, j] = (lv[0] - lv[1]) / (2 * hr)
+    torch.cuda.synchronize()
+    t_rep = time.perf_counter() - t0
+    rs.close()
+    log("%s frozen-event replay differences in %.3f s" % (log_prefix, t_rep))
+    h = 1e-3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_free = np.zeros(theta.shape, np.float64)
+    for c in range(theta.shape[0]):
+        for j in range(4):
+            a, b = theta.astype(np.float64).copy(), theta.astype(np.float64).copy()
             a[c, j] += h
             b[c, j] -= h
             sa, sb = run(a), run(b)
-            g_fd[c, j] = (loss_of(sa)[2] - loss_of(sb)[2]) / (2 * h)
+            g_free[c, j] = (loss_terms(sa)[3] - loss_terms(sb)[3]) / (2 * h)
             sa.close()
             sb.close()
     torch.cuda.synchronize()
-    t_fd = time.perf_counter() - t0
-    log("[adjoint] finite differences in %.3f s; FP64 CPU reference" % t_fd)
+    t_free = time.perf_counter() - t0
+    log("%s plain-run central differences in %.3f s; FP64 CPU references" % (log_prefix, t_free))
     o = oracle.Oracle(scen, "f32", tape=True)
     o.step(steps)
-    es = o.edge_stats()
-    mask = es["count"] > 0
-    tgt_np = tgt.cpu().numpy().astype(np.float64)
-    _, g_ref, _, _, _ = oracle.replay(o.tape(), scen, theta, tgt_np, mask, at_tape_states=True)
-    scale = np.abs(g_ref).max()
-    out = {"metric": "adjoint gradient speed-up over the plain per-scenario GPU loop (central differences)",
-           "value": t_fd / t_adj, "unit": "x", "n_gpus": 1, "steps": steps, "higher_is_better": True,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "50x50 grid, 100,000 trips, 1,800 steps, 4 link classes x (v0_scale, T, a, b)",
-                      "fd_step": h, "checkpoint_every": 60},
-           "adjoint_s": t_adj, "fd_32_runs_s": t_fd, "loss": L,
-           "adjoint_rel_err_vs_fp64": float(np.abs(g_adj - g_ref).max() / scale),
-           "fd_rel_err_vs_fp64": float(np.abs(g_fd - g_ref).max() / scale)}
+    mask = o.edge_stats()["count"] > 0
+    th64 = theta.astype(np.float64)
+    _, g_c, _, _, _ = oracle.replay(o.tape(), scen, th64, tgt_np, mask, at_tape_states=True)
+    _, g_r, _, _, _ = oracle.replay(o.tape(), scen, th64, tgt_np, mask, at_tape_states=False)
+    del o
+
+    def err(g, ref):
+        return float(np.abs(g - ref).max() / np.abs(ref).max())
+
+    acc = {k: {"vs_fp64_at_recorded_states": err(v, g_c), "vs_fp64_replayed_states": err(v, g_r)}
+           for k, v in (("adjoint", g_adj), ("replay_fd", g_rep), ("plain_runs_fd", g_free))}
+    return {"workload": "50x50 grid, 100,000 trips, 1,800 steps, 4 link classes x (v0_scale, T, a, b)",
+            "parameters": int(theta.size), "replay_fd_step": hr, "plain_fd_step": h, "checkpoint_every": 60,
+            "loss": L, "adjoint_s": t_adj, "replay_fd_s": t_rep, "plain_runs_fd_s": t_free, "accuracy": acc}
+
+
+def bench_adjoint(args):
+    """The adjoint against the per-parameter loops (see adjoint_speedup)."""
+    r = adjoint_speedup()
+    out = {"metric": "adjoint gradient speed-up over the per-parameter GPU loop at equal accuracy",
+           "value": r["replay_fd_s"] / r["adjoint_s"], "unit": "x", "n_gpus": 1, "steps": 1800,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": r["workload"], "checkpoint_every": 60},
+           "speedup_over_plain_runs_fd": r["plain_runs_fd_s"] / r["adjoint_s"], "detail": r}
     print(json.dumps(out), flush=True)
 
 
@@ -451,6 +518,8 @@ def main():
     ap.add_argument("--no-kernel-timing", dest="kernel_timing", action="store_false",
                     help="skip the per-kernel replay of the timed window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-training-patterns", dest="training_patterns", action="store_false",
+                    help="skip the adjoint and ensemble speed-ups that follow the plain-step measurement")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
     ap.add_argument("--tune-at", type=int, default=0,
@@ -500,6 +569,8 @@ def main():
         except (OSError, ValueError):
             db = {}
         db["%s|%s" % (res["device"], args.workload)] = {"grid": res["grid"], "grid_small": res["grid_small"],
+                                                         "decide_block": res["decide_block"],
+                                                         "decide_per_thread": res["decide_per_thread"],
                                                          "ms_per_step": res["ms_per_step"], "step": args.tune_at}
         with open(cache, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
@@ -510,12 +581,13 @@ def main():
         with open(cache) as f:
             hit = json.load(f).get("%s|%s" % (torch.cuda.get_device_name(0), args.workload))
         if hit:
-            E.set_launch(sim, hit["grid"], hit["grid_small"])
+            E.apply_shape(sim, hit)
             shape = "autotuned"
     except (OSError, ValueError):
         pass
-    launch = E.get_launch(sim)
-    log("[bench] launch shape %s: grid %d, small grid %d" % (shape, launch[0], launch[1]))
+    launch = E.get_launch(sim) + E.get_decide_shape(sim)
+    log("[bench] launch shape %s: grid %d, small grid %d, decide blocks of %d x %d entries"
+        % (shape, launch[0], launch[1], launch[2], launch[3]))
 
     # the timed window sits at the load the workload is quoted on: the run is
     # advanced there untimed (graph replays), or its state there is loaded
@@ -648,7 +720,8 @@ def main():
         "kernel_avg_us": {k: v * 1e3 for k, v in avg.items()} or None,
         "kernel_replay_identical": replay_same,
         "run_to_window": approach,
-        "launch": {"grid": launch[0], "grid_small": launch[1], "shape": shape, "graph_chunk": args.chunk},
+        "launch": {"grid": launch[0], "grid_small": launch[1], "decide_block": launch[2],
+                   "decide_per_thread": launch[3], "shape": shape, "graph_chunk": args.chunk},
     }
     sim.close()
     del sim
@@ -657,6 +730,25 @@ def main():
     if host_state is not None:
         log("[bench] timing the CPU oracle baseline on the same state")
         out["cpu_baseline"] = cpu_baseline(scen, host_state, args.cpu_seconds)
+    del scen, host_state
+    # the metric's second half: the adjoint and the batched ensemble against
+    # the plain per-scenario GPU loops, each with its accuracy
+    if args.training_patterns:
+        r = adjoint_speedup()
+        acc = r["accuracy"]
+        out["adjoint"] = {
+            "speedup_at_equal_accuracy": r["replay_fd_s"] / r["adjoint_s"],
+            "equal_accuracy_loop": "the recording forward + 32 frozen-event replays (double), central "
+                                   "differences h = 1e-6",
+            "speedup_over_plain_runs_fd": r["plain_runs_fd_s"] / r["adjoint_s"],
+            "adjoint_s": r["adjoint_s"], "replay_fd_s": r["replay_fd_s"], "plain_runs_fd_s": r["plain_runs_fd_s"],
+            "accuracy": acc, "workload": r["workload"]}
+        e = ensemble_speedup(args, n=args.scenarios)
+        out["ensemble"] = {"speedup_over_graph_loop": e["speedup_over_graph_loop"],
+                           "speedup_over_plain_loop": e["speedup_over_plain_loop"],
+                           "bitwise_identical_per_scenario": e["bitwise_identical_per_scenario"],
+                           "batched_s": e["batched_s"], "graph_loop_s": e["graph_loop_s"],
+                           "plain_loop_s": e["plain_loop_s"], "workload": e["workload"], "launch": e["launch"]}
     print(json.dumps(out), flush=True)
 
 

@@ -284,6 +284,31 @@ int sim_tape_begin(sim_t* sim, int32_t checkpoint_every);
  * are left as they were.  Errors: SIM_ESTATE (no window), SIM_ENOMEM, SIM_EHIP. */
 int sim_grad(sim_t* sim, const float* dL_dmeanTT, float* dL_dtheta);
 
+/* Frozen-event replay of the differentiation window at other IDM parameters,
+ * for finite-difference checks of sim_grad at the same accuracy: every
+ * vehicle moves exactly as recorded (who follows whom, lanes, links, crossing
+ * steps, the branch of every min/max/stop/clamp), only positions and speeds
+ * are recomputed, from the recorded state at the window start, with
+ *   idm [num_classes * 4]  HOST double: (v0_scale, T, a, b) per class
+ * in the step's own expressions: in float (fp64 = 0; the parameters rounded
+ * to float, the constants computed as the simulator's), where at the recorded
+ * parameters the replay reproduces the recorded trajectory bit for bit, or in
+ * double throughout (fp64 != 0), from the recorded float state.  With every
+ * branch held, a parameter far from the recorded one can make a held branch
+ * meaningless (a gap forced positive that closes, a stop with a positive
+ * acceleration), and the replay then yields non-finite sums; differences of
+ * about 1e-6 stay clear of that.  Writes, per link, the sum
+ * over the window's completed traversals of (exit fraction - entry fraction):
+ *   frac_sum [num_edges]   HOST double
+ * so the mean travel time at idm is the recorded one plus
+ * dt * (frac_sum(idm) - frac_sum(recorded)) / count.  Needs a window recorded
+ * as one segment (sim_tape_begin with a checkpoint interval at least its
+ * length); the first replay (or sim_grad) recomputes the window from its
+ * checkpoint with the event tape on, later replays reuse that tape.
+ * Synchronises; the live parameters and state are left as they were.
+ * Errors: SIM_EINVAL (parameters out of range), SIM_ESTATE, SIM_ENOMEM, SIM_EHIP. */
+int sim_replay(sim_t* sim, const double* idm, int32_t fp64, double* frac_sum);
+
 /* Batched ensemble: n scenarios simulated as one (their networks side by side:
  * node, edge, lane and class ids of scenario q are offset by the totals of
  * scenarios 0..q-1).  Every field of params[q] except idm/num_classes must
@@ -300,13 +325,20 @@ int sim_load_demand_batch(sim_t* sim, int32_t n, const int32_t* num_trips, const
                           const int32_t* const* trip_route, const int32_t* num_routes,
                           const int64_t* const* route_ptr, const int32_t* const* route_edges);
 
-/* Launch shape: blocks of 256 threads for the per-vehicle, per-claim and
- * per-mover kernels (grid) and for the persistent blocks of the step's scan
- * (grid_small).  The lane-change kernel runs the whole number of device-wide
- * waves of its resident blocks nearest to grid (grid itself when smaller
- * than one wave).  Results do not depend on the shape. */
+/* Launch shape: blocks for the per-vehicle, per-claim and per-mover kernels
+ * (grid; 256 threads each except the decide kernel, see below) and for the
+ * persistent blocks of the step's scan (grid_small).  Results do not depend
+ * on the shape. */
 int sim_set_launch(sim_t* sim, int32_t grid, int32_t grid_small);
 int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
+
+/* The decide kernel's shape: threads per block and sorted vehicle entries per
+ * thread (a block takes tiles of block x per_thread entries, staged in LDS).
+ * Supported: (256, 1) the default, (256, 2), (128, 1), (128, 2), (512, 1),
+ * (256, 4).  Results do not depend on the shape.  Errors: SIM_EINVAL (not
+ * supported), SIM_ESTATE (after the adjoint buffers were sized). */
+int sim_set_decide_shape(sim_t* sim, int32_t block, int32_t per_thread);
+int sim_get_decide_shape(sim_t* sim, int32_t* block, int32_t* per_thread);
 
 /* As sim_step, with runs of `chunk` consecutive steps replayed from captured
  * HIP graphs (captured on first use per run length and step parity).  With
@@ -315,10 +347,14 @@ int sim_get_launch(sim_t* sim, int32_t* grid, int32_t* grid_small);
 int sim_step_graph(sim_t* sim, int32_t num_steps, int32_t chunk);
 
 /* Time `steps_per_trial` steps for each candidate launch shape, all from the
- * current state (every candidate twice), then restore that state (vehicles,
- * counters, statistics, per-trip outcomes) and keep the fastest shape.
- * Outputs the shape and its time per step (ms).  Allocates a copy of the
- * state.  Synchronises. */
+ * current state (every candidate twice): grid counts and the scan's share of
+ * them, then every decide shape with the best grid, half and twice it.  Then
+ * restore that state (vehicles, counters, statistics, per-trip outcomes, the
+ * sampler setting) and keep the fastest shape (read the decide shape with
+ * sim_get_decide_shape).  Outputs the grids and the time per step (ms).  The
+ * copy of the state it allocates is freed before it returns; on an error the
+ * state is restored as far as possible and some shape is kept.
+ * Synchronises. */
 int sim_autotune(sim_t* sim, int32_t steps_per_trial, int32_t* best_grid, int32_t* best_small, float* best_ms);
 
 /* Route subsequent work to another HIP stream. */

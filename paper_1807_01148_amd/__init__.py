@@ -25,7 +25,8 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_grad", "sim_read_emissions", "sim_set_sampler", "sim_read_samples", "sim_create_batch",
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
-            "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror")
+            "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror", "sim_replay",
+            "sim_set_decide_shape", "sim_get_decide_shape")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -72,6 +73,9 @@ def library(path: str = LIB_PATH):
     """Load libtrafficsim.so; raises if it has not been built."""
     global _LIB
     if _LIB is None:
+        # torch first: the library then binds to the HIP runtime torch loaded
+        # (the same soname), whose device memory and streams it is handed
+        import torch  # noqa: F401
         if not os.path.exists(path):
             raise ImportError("libtrafficsim.so is not built (run __graft_entry__.build())")
         lib = ctypes.CDLL(path)
@@ -105,6 +109,8 @@ def library(path: str = LIB_PATH):
         lib.sim_tape_begin.restype = ctypes.c_int
         lib.sim_grad.argtypes = [P, P, P]
         lib.sim_grad.restype = ctypes.c_int
+        lib.sim_replay.argtypes = [P, P, i32, P]
+        lib.sim_replay.restype = ctypes.c_int
         lib.sim_set_vehicle_types.argtypes = [P, i32, P, i32, P]
         lib.sim_set_vehicle_types.restype = ctypes.c_int
         lib.sim_set_control.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
@@ -369,6 +375,17 @@ class Sim:
         with torch.cuda.stream(self.stream):
             self._check(self.lib.sim_grad(self.h, ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out.view(self.num_classes, 4)
+
+    def replay(self, idm, fp64: bool = False) -> np.ndarray:
+        """Frozen-event replay of the differentiation window at ``idm``
+        [num_classes, 4], in float or double: per link, the sum over the
+        window's completed traversals of (exit fraction - entry fraction),
+        float64 [num_edges]."""
+        idm = np.ascontiguousarray(idm, np.float64).reshape(self.num_classes, 4)
+        out = np.zeros(self.num_edges, np.float64)
+        self.stream.synchronize()
+        self._check(self.lib.sim_replay(self.h, _p(idm), 1 if fp64 else 0, _p(out)))
+        return out
 
     def set_idm(self, idm):
         idm = np.ascontiguousarray(idm, np.float32).reshape(self.num_classes, 4)

@@ -108,6 +108,139 @@ __device__ void motion_rev(const Params& P, float A, float T, float kab, float i
     }
 }
 
+// One applied motion with every branch forced to the recorded one (fl): the
+// same expressions, in the same order, as the step's IDM, ballistic update and
+// clamp, so in float at the recorded parameters it reproduces the recorded
+// motion bit for bit.  dx before the crossing shift, vn the new speed.
+template <class R>
+__device__ __forceinline__ void motion_frozen(const Params& P, R A, R T, R kab, R iv, int fl, R len, R x, R v, R xL,
+                                              R vL, R lL, R& dx, R& vn) {
+    const bool lead = fl & kFHasLead;
+    const R s0 = (R)P.s0, dt = (R)P.dt, h = (R)P.h;
+    R s = 0;
+    if (lead) s = (fl & kFVirtual) ? len - x : (fl & kFLeadCross) ? (len - x) + (xL - lL) : (xL - lL) - x;
+    const R r = v * iv;
+    const R r2 = r * r;
+    const R r4 = r2 * r2;
+    const R fr = (R)1 - r4;
+    R acc;
+    if (!lead) {
+        acc = A * fr;
+    } else {
+        const R dv = v - vL;
+        const R dyn = v * T + (v * dv) * kab;
+        const R ss = (fl & kFDynFloor) ? s0 + (R)0 : s0 + dyn;
+        const R q = ss / ((fl & kFSFloor) ? (R)P.s_eps : s);
+        acc = A * (fr - q * q);
+    }
+    if (fl & kFAccFloor) acc = -(R)P.b_max;
+    if (fl & kFStop) {
+        dx = (v * v) / ((R)-2 * acc);
+        vn = 0;
+    } else {
+        dx = v * dt + acc * h;
+        vn = v + acc * dt;
+    }
+    if (fl & kFDxFloor) dx = 0;
+    if (fl & kFClamp) {
+        dx = (fl & kFClampZero) ? (R)0 : s;
+        if (fl & kFClampV) vn = vL;
+    }
+}
+
+// Frozen-event replay of one recorded step at the parameters in net, in
+// precision R: every entry moves as recorded (leader, lane, link, crossing,
+// branches) from the replayed state (rx, rv by entry at this step) into ox,
+// ov (by entry at the next step, pre-filled with the recorded next state,
+// which stands for the vehicles that enter the road).  A completed traversal
+// adds its fraction difference f - phin to its link's sum F; phin (by vehicle
+// id) is the fraction of the vehicle's last link entry.
+// The IDM constants of a replay in precision R: per (class, type) a and
+// 1/(2 sqrt(ab)), per class T, per (link, type) 1/v0.
+template <class R>
+struct ReplayCon {
+    const R* A;
+    const R* T;
+    const R* kab;
+    const R* iv;
+};
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_replay(Params P, Net net, ReplayCon<R> K, Tape tp, const R* rx,
+                                                   const R* rv, R* ox, R* ov, R* phin, double* F,
+                                                   const unsigned char* vtype) {
+    const int N = *tp.n;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        const int mode = tp.mode[i];
+        const int nxt = tp.next[i];
+        const int e = tp.edge[i];
+        const R len = (R)net.len[e];
+        if (mode == kModeYield) {  // waits at the link end
+            ox[nxt] = len;
+            ov[nxt] = 0;
+            continue;
+        }
+        const int vid = tp.vid[i];
+        const int fl = mode == kModeChange ? tp.cflags[i] : tp.flags[i];
+        const int lead = mode == kModeChange ? tp.clead[i] : tp.lead[i];
+        const R x = rx[i], v = rv[i];
+        const R xL = lead >= 0 ? rx[lead] : (R)0;
+        const R vL = lead >= 0 ? rv[lead] : (R)0;
+        const R lL = lead >= 0 ? (R)by_type(P.tlen, vtype[tp.vid[lead]]) : (R)0;
+        const int c = net.cls[e];
+        const int ty = vtype[vid], nt = P.nt;
+        R dx, vn;
+        motion_frozen<R>(P, K.A[c * nt + ty], K.T[c], K.kab[c * nt + ty], K.iv[e * nt + ty], fl, len, x, v, xL, vL,
+                         lL, dx, vn);
+        const R xs = x + dx;
+        if (mode == kModeCross || mode == kModeArrive) {
+            const R fq = (len - x) / dx;
+            const R f = dx > (R)0 ? ((fl & kFFOne) ? (R)1 : fq) : (R)0;
+            atomicAdd(F + e, (double)f - (double)phin[vid]);
+            if (mode == kModeCross) {
+                phin[vid] = f;
+                ox[nxt] = xs - len;
+                ov[nxt] = vn;
+            }
+        } else {
+            ox[nxt] = xs;
+            ov[nxt] = vn;
+        }
+    }
+}
+
+// replay start: the recorded state of the first step, and the entry fraction
+// of every vehicle id (1 for a vehicle not on the road yet: a departure
+// enters with fraction 1)
+template <class R>
+__global__ void k_replay_init(Tape tp, R* rx, R* rv, R* phin, long long cap) {
+    const long long n = (long long)*tp.n;
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < cap; i += (long long)gridDim.x * kBlock) {
+        phin[i] = 1;
+        if (i < n) {
+            rx[i] = (R)tp.x[i];
+            rv[i] = (R)tp.v[i];
+        }
+    }
+}
+
+// entry fractions of the vehicles on the road at the window start
+template <class R>
+__global__ void k_replay_phin(const Veh ck, const Counters* ckctr, R* phin) {
+    const int n = ckctr->n;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) phin[ck.vid[i]] = (R)ck.phin[i];
+}
+
+// the recorded state of a step (stands for the vehicles entering the road)
+template <class R>
+__global__ void k_replay_seed(Tape tp, R* ox, R* ov) {
+    const int N = *tp.n;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        ox[i] = (R)tp.x[i];
+        ov[i] = (R)tp.v[i];
+    }
+}
+
 // own adjoint of every entry, its term for the vehicle ahead, theta partials
 __global__ __launch_bounds__(kBlock) void k_adj_own(Params P, Net net, Tape tp, AdjState a) {
     const int N = *tp.n;

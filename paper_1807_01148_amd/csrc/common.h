@@ -14,6 +14,9 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kLcNone = -(1 << 30);
 constexpr int kMaxGrid = 2048;
+// k_decide's largest tile of sorted entries (block size x entries per thread);
+// a claim segment holds one eighth of the tiles of this size
+constexpr int kMaxTile = 1024;
 // A list that every wave of a step may append to (lane-change candidates,
 // claims) is split into kSeg segments with one counter each, in lines of their
 // own.  Blocks are dispatched to the XCDs in turn, so block b runs on XCD
@@ -204,6 +207,7 @@ struct Scratch {
     int* cl_src;
     int* cl_kind;
     int* cl_tedge;
+    long long* cl_cell;  // first claim cell of the claim's target lane
     float* cl_X;
     float* cl_v;
     float* cl_f;
@@ -485,7 +489,8 @@ __device__ __forceinline__ void seg_stat(const Scratch& s, int what, unsigned lo
 __device__ __forceinline__ void push_claim(const Scratch& s, const ClaimRec& C, int lane_base, int seg,
                                            unsigned long long tag, int vid, int kind, int src, int tedge, int tlane,
                                            float X, float vc, float f, int lo, int hi) {
-    unsigned long long* cell = s.cells + C.cbase + (long long)tlane * C.ncell;
+    const long long cb = C.cbase + (long long)tlane * C.ncell;
+    unsigned long long* cell = s.cells + cb;
     const unsigned long long mine = tag | (unsigned)vid;
     for (int c = lo; c <= hi; ++c) atomicMin(cell + c, mine);
     const int ci = seg * s.cl_seg + wave_slot(s.ccnt + seg * kSegStride);
@@ -496,6 +501,7 @@ __device__ __forceinline__ void push_claim(const Scratch& s, const ClaimRec& C, 
     s.cl_src[ci] = src;
     s.cl_kind[ci] = kind;
     s.cl_tedge[ci] = tedge;
+    s.cl_cell[ci] = cb;
     s.cl_X[ci] = X;
     s.cl_v[ci] = vc;
     s.cl_f[ci] = f;

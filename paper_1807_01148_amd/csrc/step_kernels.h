@@ -28,18 +28,21 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 // ---------------------------------------------------------------------------
 // k_decide
 // ---------------------------------------------------------------------------
-// A block takes the sorted entries in tiles of kBlock.  The tile and one entry
-// on either side sit in LDS, slot s holding entry b0 - 1 + s: the vehicle
+// A block takes the sorted entries in tiles (of its threads times the entries
+// per thread).  The tile and one entry on either side sit in LDS, slot s
+// holding entry b0 - 1 + s: the vehicle
 // ahead of an entry in its lane, the one behind it, and the run of a
 // neighbouring lane (the lanes of a link are consecutive keys, so their runs
 // are usually in the same tile) are then LDS reads.  A slot before the first
 // entry holds key -1 and a slot past the last entry key INT_MAX, so the keys
 // stay sorted over the whole window.
+template <int NS>
 struct Tile {
-    int key[kBlock + 2];
-    float x[kBlock + 2];
-    float v[kBlock + 2];
-    int ty[kBlock + 2];
+    static constexpr int kSlots = NS;
+    int key[NS];
+    float x[NS];
+    float v[NS];
+    int ty[NS];
 };
 constexpr int kKeyPast = 0x7FFFFFFF;
 
@@ -86,8 +89,9 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
 // The step decision of entry i (tile slot t + 1): leader, IDM, move, crossing
 // claim or arrival.  Returns true when the vehicle is to be evaluated for a
 // lane change, with what that needs in o.
+template <class TileT>
 __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in, const Scratch& s,
-                               const Tape& tp, const Tile& T, int t_slot, int N, int t, unsigned ep,
+                               const Tape& tp, const TileT& T, int t_slot, int N, int t, unsigned ep,
                                unsigned long long tag, int i, int seg, int e, int nx, int vid, int lcs, int& clamps,
                                int& arrivals, Own& o) {
     // the own entry and the one after it from the tile; the records of the
@@ -192,14 +196,16 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // hold other lanes or the array's ends): in [lo, hi] (tile slots) with
 // *empty when the lane has no vehicle.  Returns false when the run may reach
 // beyond the window.
-__device__ __forceinline__ bool tile_run(const Tile& T, int kt, int& lo, int& hi) {
-    int a = 0, b = kBlock + 2;  // first slot with key >= kt
+template <class TileT>
+__device__ __forceinline__ bool tile_run(const TileT& T, int kt, int& lo, int& hi) {
+    constexpr int NS = TileT::kSlots;
+    int a = 0, b = NS;  // first slot with key >= kt
     while (a < b) {
         const int mid = (a + b) >> 1;
         if (T.key[mid] < kt) a = mid + 1;
         else b = mid;
     }
-    int c = a, d = kBlock + 2;  // first slot with key > kt
+    int c = a, d = NS;  // first slot with key > kt
     while (c < d) {
         const int mid = (c + d) >> 1;
         if (T.key[mid] <= kt) c = mid + 1;
@@ -207,7 +213,7 @@ __device__ __forceinline__ bool tile_run(const Tile& T, int kt, int& lo, int& hi
     }
     lo = a;
     hi = c - 1;
-    return a > 0 && c < kBlock + 2;
+    return a > 0 && c < NS;
 }
 
 // Lane-change evaluation of a vehicle (Sec. 6.3.2): candidate lanes (the
@@ -217,8 +223,9 @@ __device__ __forceinline__ bool tile_run(const Tile& T, int kt, int& lo, int& hi
 // claims its cells in the target lane.  The follower, and the leader and lag
 // in a target lane whose run the tile holds, come from LDS; other runs from
 // the lane index and the sorted arrays.
+template <class TileT>
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               const Tile& T, int t_slot, int b0, unsigned ep, unsigned long long tag, int seg,
+                               const TileT& T, int t_slot, int b0, unsigned ep, unsigned long long tag, int seg,
                                const Own& o) {
     const int i = o.i, k = o.k, e = o.e, nx = o.nx, ty = o.ty, vid = o.vid, l = o.l;
     const float x = o.x, v = o.v, lme = o.lme, ac = o.ac;
@@ -426,19 +433,22 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
 }
 
 // The first qblocks blocks (a multiple of kSeg) take the departure queues, one
-// thread per queue; the others the vehicles on the road, one thread per
-// vehicle: the step decision of every vehicle of a tile, then, for the
-// vehicles it lists, the lane-change evaluation in the same thread.  The two
-// parts share nothing but the claim list.  7 waves per SIMD (no spills).
-__global__ __launch_bounds__(kBlock) void k_decide(
-    Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp, Counters* ctr, int qblocks) {
+// thread per queue; the others the vehicles on the road in tiles of BS x R
+// entries, R per thread: the step decision of every vehicle of a tile, then,
+// for the vehicles it lists, the lane-change evaluation in the same thread.
+// The two parts share nothing but the claim list.  (BS, R) is a launch shape
+// the autotuner picks; results do not depend on it.
+template <int BS, int R>
+__global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
+                                               Counters* ctr, int qblocks) {
+    constexpr int kTile = BS * R;
     const int t = ctr->t;
     const int N = ctr->n;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
     if ((int)blockIdx.x < qblocks) {
         int ghost = 0, issued = 0;
-        for (int q = blockIdx.x * kBlock + threadIdx.x; q < tr.nq; q += qblocks * kBlock)
+        for (int q = blockIdx.x * BS + threadIdx.x; q < tr.nq; q += qblocks * BS)
             decide_queue(P, net, tr, s, ep, tag, t, q, ghost, issued);
         const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
         const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(
         }
         return;
     }
-    __shared__ Tile T;
+    __shared__ Tile<kTile + 2> T;
     // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
     // the q-th eighth of the sorted entries, tiles in order, so that the link
     // and lane records of neighbouring vehicles are shared in that XCD's L2;
@@ -457,31 +467,35 @@ __global__ __launch_bounds__(kBlock) void k_decide(
     const int vb = blockIdx.x - qblocks;
     const int per = (gridDim.x - qblocks) / kSeg;
     const int q = vb & (kSeg - 1);
-    const int nch = (N + kBlock - 1) / kBlock;
+    const int nch = (N + kTile - 1) / kTile;
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
-    const int ts = threadIdx.x + 1;  // this thread's slot in the tile
     int clamps = 0, arrivals = 0, listed = 0, claims = 0;
     if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
     for (int c = (int)(((long long)nch * q) / kSeg) + vb / kSeg; c < c_end; c += per) {
-        const int b0 = c * kBlock;
-        const int i = b0 + threadIdx.x;
-        // the tile and its two neighbours into LDS; the rest of the own entry
-        // into registers
-        int e = 0, nx = -1, vid = 0, lcs = 0;
-        if (i < N) {
-            T.key[ts] = in.key[i];
-            T.x[ts] = in.x[i];
-            T.v[ts] = in.v[i];
-            T.ty[ts] = in.ty[i];
-            e = in.edge[i];
-            nx = in.next[i];
-            vid = in.vid[i];
-            lcs = in.lc[i];
-        } else {
-            T.key[ts] = kKeyPast;
-            T.x[ts] = 0.0f;
-            T.v[ts] = 0.0f;
-            T.ty[ts] = 0;
+        const int b0 = c * kTile;
+        // the tile and its two neighbours into LDS; the rest of the own
+        // entries into registers
+        int e[R], nx[R], vid[R], lcs[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = b0 + r * BS + threadIdx.x;
+            const int ts = r * BS + threadIdx.x + 1;
+            e[r] = 0; nx[r] = -1; vid[r] = 0; lcs[r] = 0;
+            if (i < N) {
+                T.key[ts] = in.key[i];
+                T.x[ts] = in.x[i];
+                T.v[ts] = in.v[i];
+                T.ty[ts] = in.ty[i];
+                e[r] = in.edge[i];
+                nx[r] = in.next[i];
+                vid[r] = in.vid[i];
+                lcs[r] = in.lc[i];
+            } else {
+                T.key[ts] = kKeyPast;
+                T.x[ts] = 0.0f;
+                T.v[ts] = 0.0f;
+                T.ty[ts] = 0;
+            }
         }
         if (threadIdx.x == 0) {
             const bool has = b0 > 0;
@@ -490,21 +504,26 @@ __global__ __launch_bounds__(kBlock) void k_decide(
             T.v[0] = has ? in.v[b0 - 1] : 0.0f;
             T.ty[0] = has ? (int)in.ty[b0 - 1] : 0;
         }
-        if (threadIdx.x == kBlock - 1) {
-            const int j = b0 + kBlock;
+        if (threadIdx.x == BS - 1) {
+            const int j = b0 + kTile;
             const bool has = j < N;
-            T.key[kBlock + 1] = has ? in.key[j] : kKeyPast;
-            T.x[kBlock + 1] = has ? in.x[j] : 0.0f;
-            T.v[kBlock + 1] = has ? in.v[j] : 0.0f;
-            T.ty[kBlock + 1] = has ? (int)in.ty[j] : 0;
+            T.key[kTile + 1] = has ? in.key[j] : kKeyPast;
+            T.x[kTile + 1] = has ? in.x[j] : 0.0f;
+            T.v[kTile + 1] = has ? in.v[j] : 0.0f;
+            T.ty[kTile + 1] = has ? (int)in.ty[j] : 0;
         }
         __syncthreads();
-        if (i < N) {
-            Own o;
-            if (decide_vehicle(P, net, tr, in, s, tp, T, ts, N, t, ep, tag, i, q, e, nx, vid, lcs, clamps, arrivals,
-                               o)) {
-                listed += 1;
-                claims += change_vehicle(P, net, in, s, tp, T, ts, b0, ep, tag, q, o) ? 1 : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = b0 + r * BS + threadIdx.x;
+            const int ts = r * BS + threadIdx.x + 1;
+            if (i < N) {
+                Own o;
+                if (decide_vehicle(P, net, tr, in, s, tp, T, ts, N, t, ep, tag, i, q, e[r], nx[r], vid[r], lcs[r],
+                                   clamps, arrivals, o)) {
+                    listed += 1;
+                    claims += change_vehicle(P, net, in, s, tp, T, ts, b0, ep, tag, q, o) ? 1 : 0;
+                }
             }
         }
         __syncthreads();  // the tile is overwritten next
@@ -521,7 +540,6 @@ __global__ __launch_bounds__(kBlock) void k_decide(
         seg_stat(s, kStLcClaims, mw);
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // k_resolve
@@ -542,17 +560,15 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
     for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
         const int ci = seg * s.cl_seg + j;
         // the claim's fields, then everything they point to, before any branch:
-        // the target link's records, the target lane's index record and key
-        // block bounds (for the gap), the source vehicle's link and entry time
+        // the target lane's index record and key block bounds (for the gap),
+        // the claimed cells, the source vehicle's link and entry time
         const int vid = s.cl_vid[ci];
-        const int tedge = s.cl_tedge[ci];
         const int key = s.cl_key[ci];
         const int clo = s.cl_lo[ci], chi = s.cl_hi[ci];
+        const long long cb = s.cl_cell[ci];
         const int kind = s.cl_kind[ci];
         const int src = s.cl_src[ci];
         const float cX = s.cl_X[ci], cf = s.cl_f[ci];
-        const int tl = key - net.er[tedge].lane_base;
-        const ClaimRec C = net.cr[tedge];
         int lo, hi;
         const bool occ = lane_range(s.lanes, key, ep, lo, hi);
         const int kb0 = s.lblk[key >> kLaneBlkLog], kb1 = s.lblk[(key >> kLaneBlkLog) + 1];
@@ -560,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
         const int se = in.edge[sx], skin = in.kin[sx];
         const float sphin = in.phin[sx];
         // ownership of every claimed cell (all read at once: no early exit)
-        const unsigned long long* cell = s.cells + C.cbase + (long long)tl * C.ncell;
+        const unsigned long long* cell = s.cells + cb;
         const unsigned long long mine = tag | (unsigned)vid;
         bool win = true;
         for (int c = clo; c <= chi; ++c) win &= cell[c] == mine;
@@ -876,11 +892,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     const int N = finalize ? ctr->n_next : ctr->n;
     const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
+    // few vehicles on a large network: every lane block finds its first entry
+    // by a binary search over the (short) sorted keys; otherwise each entry
+    // writes the lane blocks that begin at it
+    const bool sparse = N < (s.nlblk >> 5);
+    if (sparse)
+        for (int b = blockIdx.x * kBlock + threadIdx.x; b <= s.nlblk; b += gridDim.x * kBlock)
+            s.lblk[b] = lb_key(buf.key, 0, N, b << kLaneBlkLog);
     for (int j = blockIdx.x * kBlock + threadIdx.x; j <= N; j += gridDim.x * kBlock) {
-        // lane blocks from the one after entry j-1's to entry j's begin at j
-        const int b0 = j == 0 ? 0 : (buf.key[j - 1] >> kLaneBlkLog) + 1;
-        const int b1 = j == N ? s.nlblk : (buf.key[j] >> kLaneBlkLog);
-        for (int b = b0; b <= b1; ++b) s.lblk[b] = j;
+        // lane blocks from the one after entry j-1's to entry j's begin at j;
+        // a long run of them (empty lanes) is written by the whole wave, so no
+        // single thread serialises it
+        const int b0 = sparse ? 1 : (j == 0 ? 0 : (buf.key[j - 1] >> kLaneBlkLog) + 1);
+        const int b1 = sparse ? 0 : (j == N ? s.nlblk : (buf.key[j] >> kLaneBlkLog));
+        const bool longrun = b1 - b0 >= kWave / 2;
+        if (!longrun)
+            for (int b = b0; b <= b1; ++b) s.lblk[b] = j;
+        {
+            const unsigned long long act = __ballot(1);
+            unsigned long long lm = __ballot(longrun);
+            const int lane = (int)__lane_id();
+            const int rank = __popcll(act & ((1ull << lane) - 1ull)), nact = __popcll(act);
+            while (lm) {
+                const int src = __ffsll((long long)lm) - 1;
+                lm &= lm - 1ull;
+                const int rb0 = __shfl(b0, src, kWave), rb1 = __shfl(b1, src, kWave), rj = __shfl(j, src, kWave);
+                for (int b = rb0 + rank; b <= rb1; b += nact) s.lblk[b] = rj;
+            }
+        }
         if (j == N) continue;
         // the entry and its neighbours' lanes, read before any branch
         const int k = buf.key[j];

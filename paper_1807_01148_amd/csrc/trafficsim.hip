@@ -107,6 +107,7 @@ struct sim_t {
     int grid = 1;
     int grid_small = 1;  // k_scan's persistent blocks
     int grid_q = 1;      // k_decide's departure-queue blocks: one thread per queue
+    int dshape = 0;      // k_decide's launch shape (kDecideShapes)
     std::vector<int> h_rbeg;
     int timing_every = 0;
     std::vector<hipEvent_t> ev_free;
@@ -127,6 +128,10 @@ struct sim_t {
     std::vector<Ckpt> ckpt_pool;
     // recompute state and adjoint work arrays (allocated at the first sim_grad)
     bool adj_ready = false;
+    long long tape_full_t = -1;  // the tape slices hold the whole window [tape_t0, tape_full_t)
+    double* d_rF = nullptr;      // replay: per-link sums of the traversals' fraction differences
+    double* d_r64 = nullptr;     // FP64 replay: state (two buffers of x, v) and entry fractions, 5 x cap
+    double* d_r64c = nullptr;    // FP64 replay: its IDM constants
     Veh rbuf[2]{};
     int* rqstate = nullptr;  // queue heads and tails of the recompute pass
     Counters* rctr = nullptr;
@@ -264,13 +269,27 @@ int32_t tail_node(const sim_t* S, int32_t e) { return S->tail[e]; }
 
 // With events (a sampled step), kernel q carries start event ev[2q] and stop
 // event ev[2q + 1], which take that kernel's own begin and end timestamps.
-#define STEP_LAUNCH(q, kern, grid, ...)                                                                   \
+#define STEP_LAUNCH_B(q, kern, grid, blk, ...)                                                            \
     do {                                                                                                 \
         if (ev)                                                                                          \
-            hipExtLaunchKernelGGL(kern, grid, b, 0, S->stream, ev[2 * (q)], ev[2 * (q) + 1], 0u, __VA_ARGS__); \
+            hipExtLaunchKernelGGL(kern, grid, blk, 0, S->stream, ev[2 * (q)], ev[2 * (q) + 1], 0u, __VA_ARGS__); \
         else                                                                                             \
-            hipLaunchKernelGGL(kern, grid, b, 0, S->stream, __VA_ARGS__);                               \
+            hipLaunchKernelGGL(kern, grid, blk, 0, S->stream, __VA_ARGS__);                             \
     } while (0)
+#define STEP_LAUNCH(q, kern, grid, ...) STEP_LAUNCH_B(q, kern, grid, b, __VA_ARGS__)
+
+// k_decide's launch shapes: threads per block and sorted entries per thread
+struct DecideShape {
+    int block, per;
+};
+constexpr DecideShape kDecideShapes[] = {{256, 1}, {256, 2}, {128, 1}, {128, 2}, {512, 1}, {256, 4}};
+constexpr int kNumDecideShapes = (int)(sizeof(kDecideShapes) / sizeof(kDecideShapes[0]));
+
+int decide_shape_index(int block, int per) {
+    for (int k = 0; k < kNumDecideShapes; ++k)
+        if (kDecideShapes[k].block == block && kDecideShapes[k].per == per) return k;
+    return -1;
+}
 
 int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const Scratch& sc, const Tape& tp,
                 Counters* ctr, hipEvent_t* ev) {
@@ -279,7 +298,15 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
     const dim3 g8((S->grid + kSeg - 1) / kSeg * kSeg);
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
-    STEP_LAUNCH(0, k_decide, dim3(qb + g8.x), S->P, S->net, tr, in, sc, tp, ctr, qb);
+    const dim3 gd(qb + g8.x);
+    switch (S->dshape) {
+        case 1: STEP_LAUNCH_B(0, (k_decide<256, 2>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+        case 2: STEP_LAUNCH_B(0, (k_decide<128, 1>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+        case 3: STEP_LAUNCH_B(0, (k_decide<128, 2>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+        case 4: STEP_LAUNCH_B(0, (k_decide<512, 1>), gd, dim3(512), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+        case 5: STEP_LAUNCH_B(0, (k_decide<256, 4>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+        default: STEP_LAUNCH_B(0, (k_decide<256, 1>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+    }
     STEP_LAUNCH(1, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
     STEP_LAUNCH(2, k_scan, gs, sc, ctr);
     STEP_LAUNCH(3, k_scatter, g8, S->P, in, out, sc, tp, ctr);
@@ -364,6 +391,22 @@ int graph_stream(sim_t* S) {
     return SIM_OK;
 }
 
+template <class R>
+void replay_window(sim_t* S, const ReplayCon<R>& con, int K, R* cx, R* cv, R* nx, R* nv, R* phin) {
+    const dim3 g(S->adj_grid), b(kBlock);
+    const sim_t::Ckpt& ck = S->ckpt_pool[0];
+    hipLaunchKernelGGL(k_replay_init<R>, g, b, 0, S->stream, slice(S, 0), cx, cv, phin, (long long)S->cap);
+    hipLaunchKernelGGL(k_replay_phin<R>, g, b, 0, S->stream, ck.v, ck.ctr, phin);
+    hipLaunchKernelGGL(k_zero_f64, g, b, 0, S->stream, S->d_rF, (long long)S->ne);
+    for (int k = 0; k < K; ++k) {
+        if (k + 1 < K) hipLaunchKernelGGL(k_replay_seed<R>, g, b, 0, S->stream, slice(S, k + 1), nx, nv);
+        hipLaunchKernelGGL(k_replay<R>, g, b, 0, S->stream, S->P, S->net, con, slice(S, k), cx, cv, nx, nv, phin,
+                           S->d_rF, S->tr.vtype);
+        std::swap(cx, nx);
+        std::swap(cv, nv);
+    }
+}
+
 int alloc_adjoint(sim_t* S) {
     if (S->adj_ready) return SIM_OK;
     const size_t cap = (size_t)S->cap, K = (size_t)S->tape_every, n = cap * K;
@@ -379,7 +422,7 @@ int alloc_adjoint(sim_t* S) {
               dalloc(S, S->L1v, cap) && dalloc(S, a.cgx, cap) && dalloc(S, a.cgv, cap) && dalloc(S, a.cl, cap) &&
               dalloc(S, a.accx, cap) && dalloc(S, a.accv, cap) && dalloc(S, a.maxbits, 1) &&
               dalloc(S, a.scale, 1) && dalloc(S, a.lp, cap) && dalloc(S, a.gpart, nthreads * S->ncls * 4) &&
-              dalloc(S, S->sink, 3 * (size_t)S->ne) && dalloc(S, S->d_rholder, S->nn);
+              dalloc(S, S->sink, 3 * (size_t)S->ne) && dalloc(S, S->d_rholder, S->nn) && dalloc(S, S->d_rF, S->ne);
     if (!ok) return fail(S, SIM_ENOMEM, "adjoint allocation failed");
     a.ncls = S->ncls;
     S->adj_k = S->tape_every;
@@ -738,10 +781,10 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
              dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap) && dalloc(S, V.ty, cap);
     }
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
-    // claim segment q takes the claims of one eighth of the tiles of kBlock
-    // entries (at most one per vehicle) and the departures of queue chunks
-    // q, q + kSeg, ...
-    const size_t vseg = ((size_t)(cap + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock;
+    // claim segment q takes the claims of one eighth of k_decide's tiles (at
+    // most one per vehicle; sized for the largest tile) and the departures of
+    // queue chunks q, q + kSeg, ...
+    const size_t vseg = ((size_t)(cap + kMaxTile - 1) / kMaxTile + kSeg - 1) / kSeg * kMaxTile;
     s.cl_seg = (int)(vseg + ((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
     const size_t ncl = (size_t)kSeg * s.cl_seg;
     ok = ok && dalloc(S, s.ccnt, (size_t)2 * kSeg * kSegStride) &&
@@ -749,7 +792,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
          dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
          dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && dalloc(S, s.cl_vid, ncl) &&
          dalloc(S, s.cl_key, ncl) && dalloc(S, s.cl_lo, ncl) && dalloc(S, s.cl_hi, ncl) &&
-         dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) && dalloc(S, s.cl_tedge, ncl) &&
+         dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) && dalloc(S, s.cl_tedge, ncl) && dalloc(S, s.cl_cell, ncl) &&
          dalloc(S, s.cl_X, ncl) && dalloc(S, s.cl_v, ncl) && dalloc(S, s.cl_f, ncl) &&
          dalloc(S, s.mv_claim, ncl) && dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) &&
          dalloc(S, s.mv_g, ncl) && dalloc(S, s.grp_key, cap) && dalloc(S, s.grp_X, cap) &&
@@ -861,10 +904,57 @@ int sim_tape_begin(sim_t* S, int32_t checkpoint_every) {
     if (S->adj_ready && checkpoint_every > S->adj_k)
         return fail(S, SIM_EINVAL, "checkpoint interval larger than the one the adjoint buffers were sized for");
     S->tape_on = true;
+    S->tape_full_t = -1;
     S->tape_t0 = S->host_t;
     S->tape_every = checkpoint_every;
     S->nckpt = 0;
     return SIM_OK;
+}
+
+// The recompute pass of a differentiation window: statistics into a sink, no
+// samples, stop-node admissions and departure queues on their own copies, so
+// the live state is untouched.
+Scratch recompute_scratch(sim_t* S) {
+    Scratch rs = S->s;
+    rs.samp_every = 0;
+    rs.st_cnt = S->sink;
+    rs.st_steps = S->sink + S->ne;
+    rs.st_us = S->sink + 2 * (size_t)S->ne;
+    rs.holder = S->d_rholder;
+    return rs;
+}
+
+Trips recompute_trips(sim_t* S) {
+    Trips rtr = S->tr;
+    rtr.qhead = S->rqstate;
+    rtr.qtail = S->rqstate + S->tr.nq;
+    return rtr;
+}
+
+// segment c of the window recomputed from its checkpoint with the event tape on
+int recompute_segment(sim_t* S, size_t c, const Scratch& rs, const Trips& rtr, int* K_out) {
+    const sim_t::Ckpt& ck = S->ckpt_pool[c];
+    const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
+    const int K = (int)(t_end - ck.t);
+    int rc;
+    if ((rc = copy_state(S, S->rbuf[0], S->rqstate, S->rctr, S->d_rholder, ck.v, ck.qstate, ck.ctr, ck.holder)))
+        return rc;
+    if ((rc = reindex(S, S->rbuf[0], rs, S->rctr))) return rc;
+    for (int k = 0; k < K; ++k)
+        if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], rtr, rs, slice(S, k), S->rctr, nullptr)))
+            return rc;
+    *K_out = K;
+    return SIM_OK;
+}
+
+// a window of one segment: its whole tape into the slices
+int record_window(sim_t* S) {
+    int K = 0;
+    int rc = recompute_segment(S, 0, recompute_scratch(S), recompute_trips(S), &K);
+    if (rc) return rc;
+    S->tape_full_t = S->host_t;
+    // the recompute pass re-indexed the lanes: index the live state again
+    return reindex(S, S->buf[S->host_t & 1], S->s, S->ctr);
 }
 
 int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
@@ -884,33 +974,16 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
     hipLaunchKernelGGL(k_zero_i64, g, b, 0, S->stream, S->adj.accv, (long long)S->cap);
     HIPCHECK(S, hipMemsetAsync(S->adj.maxbits, 0, sizeof(unsigned), S->stream));
     HIPCHECK(S, hipGetLastError());
-    // the recompute pass must not add to the live statistics
-    Scratch rs = S->s;
-    rs.samp_every = 0;  // and it takes no samples
-    rs.st_cnt = S->sink;
-    rs.st_steps = S->sink + S->ne;
-    rs.st_us = S->sink + 2 * (size_t)S->ne;
-    rs.holder = S->d_rholder;  // stop-node admissions replay on their own copy
-    Trips rtr = S->tr;         // and so do the departure queues
-    rtr.qhead = S->rqstate;
-    rtr.qtail = S->rqstate + S->tr.nq;
+    const Scratch rs = recompute_scratch(S);
+    const Trips rtr = recompute_trips(S);
     AdjState a = S->adj;
     a.vtype = S->tr.vtype;
     a.dLdT = dL_dmeanTT;
     a.cnt = S->s.st_cnt;
     float *L0x = S->L0x, *L0v = S->L0v, *L1x = S->L1x, *L1v = S->L1v;
     for (size_t c = S->nckpt; c-- > 0;) {
-        const sim_t::Ckpt& ck = S->ckpt_pool[c];
-        const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
-        const int K = (int)(t_end - ck.t);
-        if ((rc = copy_state(S, S->rbuf[0], S->rqstate, S->rctr, S->d_rholder, ck.v, ck.qstate, ck.ctr, ck.holder)))
-            return rc;
-        if ((rc = reindex(S, S->rbuf[0], rs, S->rctr))) return rc;
-        for (int k = 0; k < K; ++k) {
-            if ((rc = launch_step(S, S->rbuf[k & 1], S->rbuf[(k + 1) & 1], rtr,
-                                  rs, slice(S, k), S->rctr, nullptr)))
-                return rc;
-        }
+        int K = 0;
+        if ((rc = recompute_segment(S, c, rs, rtr, &K))) return rc;
         for (int k = K - 1; k >= 0; --k) {
             const Tape tk = slice(S, k);
             a.L1x = L1x;
@@ -925,6 +998,8 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
             std::swap(L0v, L1v);
         }
     }
+    // one segment: its tape, now in the slices, covers the whole window
+    S->tape_full_t = S->nckpt == 1 ? S->host_t : -1;
     // the recompute pass re-indexed the lanes: index the live state again
     if ((rc = reindex(S, S->buf[S->host_t & 1], S->s, S->ctr))) return rc;
     double* out64 = nullptr;
@@ -932,6 +1007,73 @@ int sim_grad(sim_t* S, const float* dL_dmeanTT, float* dL_dtheta) {
                        nvals, dL_dtheta, out64);
     HIPCHECK(S, hipGetLastError());
     return SIM_OK;
+}
+
+int sim_replay(sim_t* S, const double* idm, int32_t fp64, double* frac_sum) {
+    if (!S || !idm || !frac_sum) return SIM_EINVAL;
+    if (!S->tape_on || S->nckpt != 1)
+        return fail(S, SIM_ESTATE, "sim_replay needs a window recorded as one segment (sim_tape_begin with a "
+                                   "checkpoint interval at least its length)");
+    const int nt = S->P.nt, nc = S->ncls;
+    for (int c = 0; c < nc; ++c) {
+        const double s0 = idm[4 * c + 0], t = idm[4 * c + 1], a = idm[4 * c + 2], b = idm[4 * c + 3];
+        if (!(s0 > 0) || !(t >= 0) || !(a > 0) || !(b > 0) || !std::isfinite(s0 * t * a * b))
+            return fail(S, SIM_EINVAL, "idm parameters of class " + std::to_string(c) + " out of range");
+    }
+    int rc = alloc_adjoint(S);
+    if (rc) return rc;
+    const int K = (int)(S->host_t - S->ckpt_pool[0].t);
+    if (K > S->adj_k) return fail(S, SIM_ESTATE, "window longer than the tape buffers");
+    if (S->tape_full_t != S->host_t && (rc = record_window(S))) return rc;
+    if (fp64) {
+        // the constants in double from the parameters, in the expressions the
+        // float ones are rounded from
+        const size_t ncon = (size_t)nc * nt * 2 + nc + (size_t)S->ne * nt;
+        if (!S->d_r64 && !(dalloc(S, S->d_r64, 5 * (size_t)S->cap) && dalloc(S, S->d_r64c, ncon)))
+            return fail(S, SIM_ENOMEM, "replay buffers");
+        std::vector<double> con(ncon);
+        double *A = con.data(), *Kb = A + (size_t)nc * nt, *T = Kb + (size_t)nc * nt, *iv = T + nc;
+        for (int c = 0; c < nc; ++c) {
+            const double a = idm[4 * c + 2], b = idm[4 * c + 3];
+            T[c] = idm[4 * c + 1];
+            for (int k = 0; k < nt; ++k) {
+                const double ak = a < S->tamax[k] ? a : S->tamax[k];
+                A[(size_t)c * nt + k] = ak;
+                Kb[(size_t)c * nt + k] = 1.0 / (2.0 * std::sqrt(ak * b));
+            }
+        }
+        for (int e = 0; e < S->ne; ++e) {
+            const double v0 = idm[4 * S->cls[e] + 0] * (double)S->speed[e];
+            for (int k = 0; k < nt; ++k) iv[(size_t)e * nt + k] = 1.0 / (v0 < S->tvmax[k] ? v0 : S->tvmax[k]);
+        }
+        HIPCHECK(S, hipMemcpyAsync(S->d_r64c, con.data(), sizeof(double) * ncon, hipMemcpyHostToDevice, S->stream));
+        double* dc = S->d_r64c;
+        const ReplayCon<double> rc64{dc, dc + 2 * (size_t)nc * nt, dc + (size_t)nc * nt, dc + 2 * (size_t)nc * nt + nc};
+        double* r = S->d_r64;
+        const size_t c = (size_t)S->cap;
+        replay_window<double>(S, rc64, K, r, r + c, r + 2 * c, r + 3 * c, r + 4 * c);
+        HIPCHECK(S, hipGetLastError());
+        HIPCHECK(S, hipMemcpyAsync(frac_sum, S->d_rF, sizeof(double) * S->ne, hipMemcpyDeviceToHost, S->stream));
+        HIPCHECK(S, hipStreamSynchronize(S->stream));  // also keeps the host constants alive for their copy
+        return SIM_OK;
+    }
+    // in float: the simulator's own constants at these parameters, then the
+    // live ones back
+    const std::vector<float> keep = S->idm_in;
+    std::vector<float> f32(idm, idm + 4 * (size_t)nc);
+    if ((rc = upload_idm(S, f32.data()))) return rc;
+    const ReplayCon<float> rc32{S->net.cA, S->net.cT, S->net.cKab, S->net.inv_v0};
+    replay_window<float>(S, rc32, K, S->L0x, S->L0v, S->L1x, S->L1v, S->adj.lp);
+    hipError_t he = hipGetLastError();
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(frac_sum, S->d_rF, sizeof(double) * S->ne, hipMemcpyDeviceToHost, S->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(S->stream);
+    const int rc2 = upload_idm(S, keep.data());
+    if (he != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(S, SIM_EHIP, std::string("sim_replay: ") + hipGetErrorString(he));
+    }
+    return rc2;
 }
 
 int sim_stats(sim_t* S, sim_stats_t* host_out, int64_t* edge_count, int64_t* edge_tt_steps, int64_t* edge_tt_us) {
@@ -1395,6 +1537,23 @@ int sim_get_launch(sim_t* S, int32_t* grid, int32_t* grid_small) {
     return SIM_OK;
 }
 
+int sim_set_decide_shape(sim_t* S, int32_t block, int32_t per_thread) {
+    if (!S) return SIM_EINVAL;
+    const int k = decide_shape_index(block, per_thread);
+    if (k < 0) return fail(S, SIM_EINVAL, "no such decide shape");
+    if (S->adj_ready) return fail(S, SIM_ESTATE, "launch shape is fixed once the adjoint buffers exist");
+    if (k != S->dshape) drop_graphs(S);
+    S->dshape = k;
+    return SIM_OK;
+}
+
+int sim_get_decide_shape(sim_t* S, int32_t* block, int32_t* per_thread) {
+    if (!S || !block || !per_thread) return SIM_EINVAL;
+    *block = kDecideShapes[S->dshape].block;
+    *per_thread = kDecideShapes[S->dshape].per;
+    return SIM_OK;
+}
+
 int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
     if (!S || num_steps < 0 || chunk <= 0) return SIM_EINVAL;
     if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
@@ -1474,90 +1633,163 @@ int sim_step_graph(sim_t* S, int32_t num_steps, int32_t chunk) {
     return sim_step(S, num_steps - done);
 }
 
+void release_from(sim_t* S, size_t mark) {
+    if (S->allocs.size() <= mark) return;
+    (void)hipStreamSynchronize(S->stream);
+    for (size_t k = mark; k < S->allocs.size(); ++k) {
+        if (S->free_fn) S->free_fn(S->ctx, S->allocs[k]);
+        else (void)hipFree(S->allocs[k]);
+    }
+    S->allocs.resize(mark);
+}
+
 int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t* best_small, float* best_ms) {
     if (!S || steps_per_trial <= 0 || !best_grid || !best_small || !best_ms) return SIM_EINVAL;
     if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
     if (S->tape_on || S->adj_ready) return fail(S, SIM_ESTATE, "no tuning inside a differentiation window");
     // save the state and the statistics, try every candidate from the same
-    // state, restore; the step's results do not depend on the launch shape
+    // state, restore; the step's results do not depend on the launch shape.
+    // The saved copy is freed on return, and every exit, error or not, puts
+    // back the state, the statistics, the sampler and a launch shape.
+    const size_t mark = S->allocs.size();
     sim_t::Ckpt save;
     const int p = (int)(S->host_t & 1);
     unsigned long long* st_save = nullptr;
     int* trip_save = nullptr;
     if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.qstate, 2 * (size_t)S->tr.nq) || !dalloc(S, save.ctr, 1) ||
         !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap) ||
-        !dalloc(S, save.holder, S->nn))
+        !dalloc(S, save.holder, S->nn)) {
+        release_from(S, mark);
         return fail(S, SIM_ENOMEM, "autotune allocation failed");
+    }
     const size_t tb = sizeof(int) * (size_t)S->cap;
-    HIPCHECK(S, hipMemcpyAsync(trip_save, S->tr.depart_actual, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
-    int rc = copy_state(S, save.v, save.qstate, save.ctr, save.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
-    if (rc) return rc;
     const size_t eb = sizeof(unsigned long long) * (size_t)S->ne;
-    HIPCHECK(S, hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(st_save + S->ne, S->s.st_steps, eb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(st_save + 2 * (size_t)S->ne, S->s.st_us, eb, hipMemcpyDeviceToDevice, S->stream));
     const long long t_save = S->host_t;
+    const int samp_every = S->s.samp_every;
+    int bg = S->grid, bs = S->grid_small, bd = S->dshape;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool saved = false;
+    // put the saved state back (after every trial, and at the end)
+    auto restore_state = [&]() -> int {
+        S->host_t = t_save;
+        int r = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder);
+        if (r) return r;
+        return reindex(S, S->buf[p], S->s, S->ctr);
+    };
+    auto finish = [&](int rc) -> int {
+        S->s.samp_every = samp_every;
+        S->grid = bg;
+        S->grid_small = bs;
+        S->dshape = bd;
+        drop_graphs(S);
+        if (saved) {
+            int r = restore_state();
+            hipError_t he = hipSuccess;
+            he = hipMemcpyAsync(S->s.st_cnt, st_save, eb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->s.st_steps, st_save + S->ne, eb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->tr.depart_actual, trip_save, tb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->tr.arrive_step, trip_save + S->cap, tb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->tr.fuel_total, trip_save + 2 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipMemcpyAsync(S->tr.co_total, trip_save + 3 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream);
+            if (he == hipSuccess) he = hipStreamSynchronize(S->stream);
+            if (he != hipSuccess) {
+                (void)hipGetLastError();
+                if (!rc) rc = fail(S, SIM_EHIP, std::string("autotune restore: ") + hipGetErrorString(he));
+            }
+            if (!rc) rc = r;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        release_from(S, mark);
+        return rc;
+    };
+#define TUNE_CHECK(call)                                                                            \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            (void)hipGetLastError();                                                                \
+            return finish(fail(S, SIM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)));    \
+        }                                                                                           \
+    } while (0)
+    TUNE_CHECK(hipMemcpyAsync(trip_save, S->tr.depart_actual, tb, hipMemcpyDeviceToDevice, S->stream));
+    TUNE_CHECK(hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
+    TUNE_CHECK(hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
+    TUNE_CHECK(hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
+    int rc = copy_state(S, save.v, save.qstate, save.ctr, save.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
+    if (rc) return finish(rc);
+    TUNE_CHECK(hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
+    TUNE_CHECK(hipMemcpyAsync(st_save + S->ne, S->s.st_steps, eb, hipMemcpyDeviceToDevice, S->stream));
+    TUNE_CHECK(hipMemcpyAsync(st_save + 2 * (size_t)S->ne, S->s.st_us, eb, hipMemcpyDeviceToDevice, S->stream));
+    saved = true;
+    TUNE_CHECK(hipEventCreate(&e0));
+    TUNE_CHECK(hipEventCreate(&e1));
+    S->s.samp_every = 0;  // trials take no samples
+    const Tape off{};
+    float best = 1e30f;
+    // one trial: steps_per_trial steps of the given shape from the saved state
+    auto trial = [&](int gc, int gs, int ds, float* ms) -> int {
+        S->grid = gc;
+        S->grid_small = gs;
+        S->dshape = ds;
+        int r = restore_state();
+        if (r) return r;
+        hipError_t he = hipEventRecord(e0, S->stream);
+        for (int k = 0; k < steps_per_trial && r == SIM_OK && he == hipSuccess; ++k) {
+            const int q = (int)(S->host_t & 1);
+            r = launch_step(S, S->buf[q], S->buf[q ^ 1], S->tr, S->s, off, S->ctr, nullptr);
+            S->host_t += 1;
+        }
+        if (r) return r;
+        if (he == hipSuccess) he = hipEventRecord(e1, S->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(ms, e0, e1);
+        if (he != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(S, SIM_EHIP, std::string("autotune trial: ") + hipGetErrorString(he));
+        }
+        return SIM_OK;
+    };
+    // grid counts and k_scan's share of them with the current decide shape,
+    // then the decide shapes with the best grids; each candidate twice, a
+    // shape's time is the faster of its trials
     const int g0 = S->grid;
     const int gcand[] = {g0 / 4, g0 / 2, g0 * 3 / 4, g0, g0 * 3 / 2, g0 * 2};
     const int scand[] = {2, 4, 8};
-    hipEvent_t e0, e1;
-    HIPCHECK(S, hipEventCreate(&e0));
-    HIPCHECK(S, hipEventCreate(&e1));
-    const int samp_every = S->s.samp_every;
-    S->s.samp_every = 0;  // trials take no samples
-    float best = 1e30f;
-    int bg = S->grid, bs = S->grid_small;
-    const Tape off{};
-    // two passes over the candidates; a shape's time is the faster of its two
-    // trials (the fastest over all trials wins)
     for (int pass = 0; pass < 2; ++pass)
-    for (int gc : gcand) {
-        if (gc < 1) continue;
-        for (int sd : scand) {
-            const int gs = std::max(1, gc / sd);
-            S->grid = gc;
-            S->grid_small = gs;
-            S->host_t = t_save;
-            if ((rc = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder))) return rc;
-            if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
-            HIPCHECK(S, hipEventRecord(e0, S->stream));
-            for (int k = 0; k < steps_per_trial && rc == SIM_OK; ++k) {
-                const int q = (int)(S->host_t & 1);
-                rc = launch_step(S, S->buf[q], S->buf[q ^ 1], S->tr, S->s, off, S->ctr, nullptr);
-                S->host_t += 1;
-            }
-            if (rc) return rc;
-            HIPCHECK(S, hipEventRecord(e1, S->stream));
-            HIPCHECK(S, hipEventSynchronize(e1));
-            float ms = 0.0f;
-            HIPCHECK(S, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bg = gc;
-                bs = gs;
+        for (int gc : gcand) {
+            if (gc < 1) continue;
+            for (int sd : scand) {
+                const int gs = std::max(1, gc / sd);
+                float ms = 0.0f;
+                if ((rc = trial(gc, gs, bd, &ms))) return finish(rc);
+                if (ms < best) {
+                    best = ms;
+                    bg = gc;
+                    bs = gs;
+                }
             }
         }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    S->s.samp_every = samp_every;
-    S->host_t = t_save;
-    S->grid = bg;
-    S->grid_small = bs;
-    drop_graphs(S);
-    if ((rc = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder))) return rc;
-    HIPCHECK(S, hipMemcpyAsync(S->s.st_cnt, st_save, eb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->s.st_steps, st_save + S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->s.st_us, st_save + 2 * (size_t)S->ne, eb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->tr.depart_actual, trip_save, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->tr.arrive_step, trip_save + S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->tr.fuel_total, trip_save + 2 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(S->tr.co_total, trip_save + 3 * (size_t)S->cap, tb, hipMemcpyDeviceToDevice, S->stream));
-    if ((rc = reindex(S, S->buf[p], S->s, S->ctr))) return rc;
-    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    const int dcur = bd, g1 = bg, s1 = bs;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int ds = 0; ds < kNumDecideShapes; ++ds) {
+            if (ds == dcur) continue;
+            for (int gc : {g1 / 2, g1, g1 * 2}) {
+                if (gc < 1) continue;
+                const int gs = std::max(1, (int)((long long)s1 * gc / g1));
+                float ms = 0.0f;
+                if ((rc = trial(gc, gs, ds, &ms))) return finish(rc);
+                if (ms < best) {
+                    best = ms;
+                    bd = ds;
+                    bg = gc;
+                    bs = gs;
+                }
+            }
+        }
+#undef TUNE_CHECK
+    rc = finish(SIM_OK);
+    if (rc) return rc;
     *best_grid = bg;
     *best_small = bs;
     *best_ms = best / (float)steps_per_trial;

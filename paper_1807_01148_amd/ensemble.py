@@ -33,6 +33,10 @@ def _bind(lib):
     lib.sim_set_launch.restype = ctypes.c_int
     lib.sim_get_launch.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.sim_get_launch.restype = ctypes.c_int
+    lib.sim_set_decide_shape.argtypes = [P, i32, i32]
+    lib.sim_set_decide_shape.restype = ctypes.c_int
+    lib.sim_get_decide_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sim_get_decide_shape.restype = ctypes.c_int
     lib.sim_step_graph.argtypes = [P, i32, i32]
     lib.sim_step_graph.restype = ctypes.c_int
     lib.sim_autotune.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
@@ -68,6 +72,25 @@ def get_launch(sim: Sim):
     return g.value, s.value
 
 
+def set_decide_shape(sim: Sim, block: int, per_thread: int):
+    lib = _bind(library())
+    sim._check(lib.sim_set_decide_shape(sim.h, int(block), int(per_thread)))
+
+
+def get_decide_shape(sim: Sim):
+    lib = _bind(library())
+    b, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    sim._check(lib.sim_get_decide_shape(sim.h, ctypes.byref(b), ctypes.byref(r)))
+    return b.value, r.value
+
+
+def apply_shape(sim: Sim, shape: dict):
+    """Set a launch shape as autotune returns it (grids, decide shape)."""
+    set_launch(sim, shape["grid"], shape["grid_small"])
+    if "decide_block" in shape:
+        set_decide_shape(sim, shape["decide_block"], shape["decide_per_thread"])
+
+
 def autotune(sim: Sim, steps_per_trial: int = 60, cache_key: str | None = None, cache_path: str | None = None):
     """Pick the fastest launch shape from the current state (the state is
     restored).  With ``cache_key``, a result stored in the JSON cache (keyed by
@@ -84,11 +107,13 @@ def autotune(sim: Sim, steps_per_trial: int = 60, cache_key: str | None = None, 
         except (OSError, ValueError):
             hit = None
         if hit:
-            set_launch(sim, hit["grid"], hit["grid_small"])
+            apply_shape(sim, hit)
             return dict(hit, cached=True)
     g, s, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
     sim._check(lib.sim_autotune(sim.h, int(steps_per_trial), ctypes.byref(g), ctypes.byref(s), ctypes.byref(ms)))
-    res = {"grid": g.value, "grid_small": s.value, "ms_per_step": ms.value}
+    db_, dr_ = get_decide_shape(sim)
+    res = {"grid": g.value, "grid_small": s.value, "decide_block": db_, "decide_per_thread": dr_,
+           "ms_per_step": ms.value}
     if key is not None:
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)

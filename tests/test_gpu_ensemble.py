@@ -110,6 +110,40 @@ def test_launch_shape_does_not_change_results(shape):
         assert np.array_equal(v, alt.vehicles()[k])
 
 
+@pytest.mark.parametrize("dshape", [(256, 2), (128, 1), (128, 2), (512, 1), (256, 4)])
+def test_decide_shape_does_not_change_results(dshape):
+    """Every decide-kernel shape (threads per block, entries per thread: the
+    tile of sorted entries staged in LDS) gives the default shape's results,
+    with a small grid too (tiles looped over per block)."""
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import get_decide_shape, set_decide_shape, set_launch
+    sc = S.mid_grid(n_trips=20000)
+    ref, alt, few = P.Sim(sc), P.Sim(sc), P.Sim(sc)
+    set_decide_shape(alt, *dshape)
+    set_decide_shape(few, *dshape)
+    set_launch(few, 16, 2)
+    assert get_decide_shape(alt) == dshape
+    ref.step(1500)
+    alt.step(1500)
+    few.step(1500)
+    assert ref.counters() == alt.counters() == few.counters()
+    for k, v in ref.vehicles().items():
+        assert np.array_equal(v, alt.vehicles()[k]), k
+        assert np.array_equal(v, few.vehicles()[k]), k
+    for k, v in ref.edge_stats().items():
+        assert np.array_equal(v, alt.edge_stats()[k]), k
+
+
+def test_decide_shape_errors():
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd import SIM_EINVAL, SimError
+    from paper_1807_01148_amd.ensemble import set_decide_shape
+    sim = P.Sim(S.small_grid(n_trips=50, steps=10))
+    with pytest.raises(SimError) as ei:
+        set_decide_shape(sim, 192, 1)
+    assert ei.value.code == SIM_EINVAL
+
+
 def test_autotune_restores_state():
     import paper_1807_01148_amd as P
     from paper_1807_01148_amd.ensemble import autotune, get_launch
@@ -121,6 +155,8 @@ def test_autotune_restores_state():
     res = autotune(tun, steps_per_trial=30)
     assert tun.counters() == before
     assert get_launch(tun) == (res["grid"], res["grid_small"])
+    from paper_1807_01148_amd.ensemble import get_decide_shape
+    assert get_decide_shape(tun) == (res["decide_block"], res["decide_per_thread"])
     ref.step(900)
     tun.step(900)
     assert ref.counters() == tun.counters()
