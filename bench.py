@@ -65,12 +65,13 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload="metro", start_step=None):
+def measured_traffic(workload="metro", start_step=None, launch=None):
     """HBM bytes per launch of every step kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), as
     {kernel: (fetch, write)}, or None when there is none, the kernel sources
-    changed since it was taken, or it was taken on another workload or window
-    (its first step)."""
+    changed since it was taken, or it was taken on another workload, window
+    (its first step) or launch shape (grid, small grid, decide block, decide
+    entries per thread)."""
     try:
         with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as f:
             kv = dict(line.strip()[2:].split(": ", 1) for line in f if line.startswith("- ") and ": " in line)
@@ -78,6 +79,8 @@ def measured_traffic(workload="metro", start_step=None):
             return None
         if kv.get("workload") != workload or (start_step is not None and
                                               int(kv.get("window_start_step", -1)) != start_step):
+            return None
+        if launch is not None and tuple(int(v) for v in kv.get("launch", "").split(",")) != tuple(launch):
             return None
         out = {}
         for k in STEP_KERNELS:
@@ -319,18 +322,18 @@ def adjoint_speedup(seed=1812, log_prefix="[adjoint]"):
     log("%s adjoint gradient in %.3f s" % (log_prefix, t_adj))
 
     tgt_np = tgt.double().cpu().numpy()
-    # central differences of the frozen-event replay (double, h = 1e-6): the
-    # window recorded as one segment, then 32 replays
-    hr = 1e-6
+    # central differences of the frozen-event replay (double, h = 1e-8: far
+    # enough below the steps at which a held branch stops making sense on this
+    # workload; at 1e-6 some do): the window recorded as one segment, then 32
+    # replays
+    hr = 1e-8
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rs = run(theta, every=steps)
-    tb0, cnt0, m0, _ = loss_terms(rs)
-    tb0 = tb0.double().cpu().numpy()
-    c0 = np.maximum(cnt0.cpu().numpy(), 1)
-    mk = m0.cpu().numpy()
+    es = rs.edge_stats()
+    c0 = np.maximum(es["count"], 1)
+    mk = es["count"] > 0
     th0 = theta.astype(np.float64)
-    F0 = rs.replay(th0, fp64=True)
     g_rep = np.zeros(theta.shape, np.float64)
     for c in range(theta.shape[0]):
         for j in range(4):
@@ -338,7 +341,8 @@ def adjoint_speedup(seed=1812, log_prefix="[adjoint]"):
             for sgn in (1.0, -1.0):
                 th = th0.copy()
                 th[c, j] += sgn * hr
-                tbp = tb0 + dt * (rs.replay(th, fp64=True) - F0) / c0
+                # the replay's own mean link times: recorded whole steps plus replayed fractions
+                tbp = dt * (es["tt_steps"] + rs.replay(th, fp64=True)) / c0
                 lv.append(float(((tbp - tgt_np)[mk] ** 2).mean()))
             g_rep[c, j] = (lv[0] - lv[1]) / (2 * hr)
     torch.cuda.synchronize()
@@ -562,7 +566,7 @@ def main():
         E.step_graph(sim, args.tune_at, args.chunk)
         torch.cuda.synchronize()
         res = E.autotune(sim, steps_per_trial=60)
-        res.update({"workload": args.workload, "step": args.tune_at, "device": torch.cuda.get_device_name(0)})
+        res.update({"workload": args.workload, "step": args.tune_at, "device": E.device_key(0)})
         try:
             with open(cache) as f:
                 db = json.load(f)
@@ -579,7 +583,7 @@ def main():
     shape = "default"
     try:
         with open(cache) as f:
-            hit = json.load(f).get("%s|%s" % (torch.cuda.get_device_name(0), args.workload))
+            hit = json.load(f).get("%s|%s" % (E.device_key(0), args.workload))
         if hit:
             E.apply_shape(sim, hit)
             shape = "autotuned"
@@ -669,7 +673,7 @@ def main():
     del img
 
     roofline = None
-    traffic = measured_traffic(args.workload, c0["step"]) if samples else None
+    traffic = measured_traffic(args.workload, c0["step"], launch) if samples else None
     if samples:
         dom = max(avg, key=avg.get)
         per_launch_units = upd / args.steps
@@ -739,7 +743,7 @@ def main():
         out["adjoint"] = {
             "speedup_at_equal_accuracy": r["replay_fd_s"] / r["adjoint_s"],
             "equal_accuracy_loop": "the recording forward + 32 frozen-event replays (double), central "
-                                   "differences h = 1e-6",
+                                   "differences h = 1e-8",
             "speedup_over_plain_runs_fd": r["plain_runs_fd_s"] / r["adjoint_s"],
             "adjoint_s": r["adjoint_s"], "replay_fd_s": r["replay_fd_s"], "plain_runs_fd_s": r["plain_runs_fd_s"],
             "accuracy": acc, "workload": r["workload"]}

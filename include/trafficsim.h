@@ -346,6 +346,18 @@ int sim_get_decide_shape(sim_t* sim, int32_t* block, int32_t* per_thread);
  * at it.  Falls back to sim_step while a differentiation window is active. */
 int sim_step_graph(sim_t* sim, int32_t num_steps, int32_t chunk);
 
+/* The same steps as sim_step in one persistent launch (up to 600 steps per
+ * launch): the device's resident blocks (a cooperative launch) take the
+ * step's phases in turn with a device-wide barrier between phases, each phase
+ * over the virtual grid of its own launch, so results are identical to
+ * sim_step.  Needs a decide shape of 256 threads and 1 or 2 entries per
+ * thread.  With a differentiation window or per-kernel timing active, falls
+ * back to sim_step.  Synchronises at the end and checks the barriers: a
+ * barrier that gave up waiting (the launch could not keep every block
+ * resident) makes the call fail with SIM_EHIP, and the state is then void.
+ * Errors: SIM_EINVAL, SIM_ESTATE, SIM_ENOMEM, SIM_EHIP. */
+int sim_step_persistent(sim_t* sim, int32_t num_steps);
+
 /* Time `steps_per_trial` steps for each candidate launch shape, all from the
  * current state (every candidate twice): grid counts and the scan's share of
  * them, then every decide shape with the best grid, half and twice it.  Then

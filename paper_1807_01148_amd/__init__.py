@@ -26,7 +26,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
             "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror", "sim_replay",
-            "sim_set_decide_shape", "sim_get_decide_shape")
+            "sim_set_decide_shape", "sim_get_decide_shape", "sim_step_persistent")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -87,6 +87,8 @@ def library(path: str = LIB_PATH):
         lib.sim_load_demand.restype = ctypes.c_int
         lib.sim_step.argtypes = [P, i32]
         lib.sim_step.restype = ctypes.c_int
+        lib.sim_step_persistent.argtypes = [P, i32]
+        lib.sim_step_persistent.restype = ctypes.c_int
         lib.sim_stats.argtypes = [P, ctypes.POINTER(SimStats), P, P, P]
         lib.sim_stats.restype = ctypes.c_int
         lib.sim_read_vehicles.argtypes = [P, i32, ctypes.POINTER(i32), P, P, P, P, P, P, P, P, P, P, P]
@@ -254,6 +256,11 @@ class Sim:
 
     def step(self, n: int = 1):
         self._check(self.lib.sim_step(self.h, int(n)))
+
+    def step_persistent(self, n: int = 1):
+        """n steps in persistent launches (one cooperative launch per up to
+        600 steps, device-wide barriers between the phases); synchronises."""
+        self._check(self.lib.sim_step_persistent(self.h, int(n)))
 
     def counters(self) -> dict:
         st = SimStats()

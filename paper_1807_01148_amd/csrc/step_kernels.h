@@ -439,16 +439,17 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
 // The two parts share nothing but the claim list.  (BS, R) is a launch shape
 // the autotuner picks; results do not depend on it.
 template <int BS, int R>
-__global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                               Counters* ctr, int qblocks) {
+__device__ __forceinline__ void decide_body(const Params& P, const Net& net, const Trips& tr, const Veh& in,
+                                            const Scratch& s, const Tape& tp, Counters* ctr, int qblocks, int bid,
+                                            int nblk) {
     constexpr int kTile = BS * R;
     const int t = ctr->t;
     const int N = ctr->n;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
-    if ((int)blockIdx.x < qblocks) {
+    if (bid < qblocks) {
         int ghost = 0, issued = 0;
-        for (int q = blockIdx.x * BS + threadIdx.x; q < tr.nq; q += qblocks * BS)
+        for (int q = bid * BS + threadIdx.x; q < tr.nq; q += qblocks * BS)
             decide_queue(P, net, tr, s, ep, tag, t, q, ghost, issued);
         const unsigned long long gw = wave_sum_u64((unsigned long long)ghost);
         const unsigned long long iw = wave_sum_u64((unsigned long long)issued);
@@ -464,8 +465,8 @@ __global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh 
     // the q-th eighth of the sorted entries, tiles in order, so that the link
     // and lane records of neighbouring vehicles are shared in that XCD's L2;
     // q is also the segment of every claim they append
-    const int vb = blockIdx.x - qblocks;
-    const int per = (gridDim.x - qblocks) / kSeg;
+    const int vb = bid - qblocks;
+    const int per = (nblk - qblocks) / kSeg;
     const int q = vb & (kSeg - 1);
     const int nch = (N + kTile - 1) / kTile;
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
@@ -541,23 +542,29 @@ __global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh 
     }
 }
 
+template <int BS, int R>
+__global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
+                                               Counters* ctr, int qblocks) {
+    decide_body<BS, R>(P, net, tr, in, s, tp, ctr, qblocks, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_resolve
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
-                                                    Counters* ctr) {
+__device__ __forceinline__ void resolve_body(const Params& P, const Net& net, const Trips& tr, const Veh& in,
+                                             const Scratch& s, const Tape& tp, Counters* ctr, int bid, int nblk) {
     const int t = ctr->t;
-    const int seg = blockIdx.x & (kSeg - 1);  // the grid is a multiple of kSeg
+    const int seg = bid & (kSeg - 1);  // the grid is a multiple of kSeg
     const int M = s.ccnt[seg * kSegStride];
-    const int nb = gridDim.x / kSeg;
+    const int nb = nblk / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         ctr->scan_tile = 0;
         ctr->epoch_next = ep + 1u;
     }
     int lost = 0, departed = 0;
-    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
+    for (int j = (bid / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
         const int ci = seg * s.cl_seg + j;
         // the claim's fields, then everything they point to, before any branch:
         // the target lane's index record and key block bounds (for the gap),
@@ -617,6 +624,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
+                                                    Counters* ctr) {
+    resolve_body(P, net, tr, in, s, tp, ctr, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_scan: exclusive scan of w[i] = stay[i] + mcnt[i], i in [0, N], single pass
 // with decoupled look-back; tiles are handed out in order by an atomic counter
@@ -649,7 +661,7 @@ __device__ __forceinline__ unsigned long long pack_status(unsigned ep, unsigned 
     return ((unsigned long long)ep << 34) | (flag << 32) | (unsigned)val;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
+__device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
     const int N = ctr->n;
     const int total = N + 1;
     const int ntiles = (total + kScanTile - 1) / kScanTile;
@@ -762,13 +774,16 @@ __global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) {
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_scan(Scratch s, Counters* ctr) { scan_body(s, ctr); }
+
 // ---------------------------------------------------------------------------
 // k_scatter: survivors to their new slot; movers stage their sort keys
 // ---------------------------------------------------------------------------
 // (the grid is a multiple of kSeg: block b stages the movers of segment b % kSeg)
-__global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
+__device__ __forceinline__ void scatter_body(const Params& P, const Veh& in, const Veh& out, const Scratch& s,
+                                             const Tape& tp, Counters* ctr, int bid, int nblk) {
     const int N = ctr->n;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    for (int i = bid * kBlock + threadIdx.x; i < N; i += nblk * kBlock) {
         // every field read before the branch (almost every entry stays)
         const bool st = s.stay[i] != 0;
         const int j = s.cscan[i] + s.mcnt[i];
@@ -794,10 +809,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, S
         out.fuel[j] = fu;
         out.co[j] = co;
     }
-    const int seg = blockIdx.x & (kSeg - 1);
+    const int seg = bid & (kSeg - 1);
     const int M = s.mvcnt[seg * kSegStride];
-    const int nb = gridDim.x / kSeg;
-    for (int j = (blockIdx.x / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
+    const int nb = nblk / kSeg;
+    for (int j = (bid / kSeg) * kBlock + threadIdx.x; j < M; j += nb * kBlock) {
         const int m = seg * s.cl_seg + j;
         const int p = s.mv_p[m];
         const int ci = s.mv_claim[m];
@@ -808,16 +823,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Params P, Veh in, Veh out, S
     }
 }
 
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scatter(
+    Params P, Veh in, Veh out, Scratch s, Tape tp, Counters* ctr) {
+    scatter_body(P, in, out, s, tp, ctr, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_place: movers take their rank inside their gap
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Veh out, Scratch s, Tape tp,
-                                                  int lc_none, Counters* ctr) {
+__device__ __forceinline__ void place_body(const Params& P, const Trips& tr, const Veh& in, const Veh& out,
+                                           const Scratch& s, const Tape& tp, int lc_none, Counters* ctr, int bid,
+                                           int nblk) {
     const int t = ctr->t;
-    const int seg = blockIdx.x & (kSeg - 1);  // the grid is a multiple of kSeg
+    const int seg = bid & (kSeg - 1);  // the grid is a multiple of kSeg
     const int M = s.mvcnt[seg * kSegStride];
-    const int nb = gridDim.x / kSeg;
-    for (int jm = (blockIdx.x / kSeg) * kBlock + threadIdx.x; jm < M; jm += nb * kBlock) {
+    const int nb = nblk / kSeg;
+    for (int jm = (bid / kSeg) * kBlock + threadIdx.x; jm < M; jm += nb * kBlock) {
         const int m = seg * s.cl_seg + jm;
         const int ci = s.mv_claim[m];
         const int p = s.mv_p[m];
@@ -881,14 +902,19 @@ __global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Ve
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_place(Params P, Trips tr, Veh in, Veh out, Scratch s, Tape tp,
+                                                  int lc_none, Counters* ctr) {
+    place_body(P, tr, in, out, s, tp, lc_none, ctr, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // k_lanes: index the lanes of the new sorted arrays (first and last entry per
 // lane, tagged with the next step's epoch).  With `finalize` it also commits
 // the step: the kernels of the step are the only readers of the counters it
 // advances, and they have all completed.  8 waves per SIMD (no spills).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_lanes(
-    Params P, Net net, Veh buf, Scratch s, Counters* ctr, int finalize) {
+__device__ __forceinline__ void lanes_body(const Params& P, const Net& net, const Veh& buf, const Scratch& s,
+                                           Counters* ctr, int finalize, int bid, int nblk) {
     const int N = finalize ? ctr->n_next : ctr->n;
     const unsigned ep = finalize ? ctr->epoch_next : *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
@@ -897,9 +923,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     // writes the lane blocks that begin at it
     const bool sparse = N < (s.nlblk >> 5);
     if (sparse)
-        for (int b = blockIdx.x * kBlock + threadIdx.x; b <= s.nlblk; b += gridDim.x * kBlock)
+        for (int b = bid * kBlock + threadIdx.x; b <= s.nlblk; b += nblk * kBlock)
             s.lblk[b] = lb_key(buf.key, 0, N, b << kLaneBlkLog);
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j <= N; j += gridDim.x * kBlock) {
+    for (int j = bid * kBlock + threadIdx.x; j <= N; j += nblk * kBlock) {
         // lane blocks from the one after entry j-1's to entry j's begin at j;
         // a long run of them (empty lanes) is written by the whole wave, so no
         // single thread serialises it
@@ -942,7 +968,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
         if (j == N - 1 || kn != k) lx->hi = j;
     }
-    if (finalize && blockIdx.x == 0 && threadIdx.x < kWave) {
+    if (finalize && bid == 0 && threadIdx.x < kWave) {
         // fold the per-XCD lines into the counters (lane q reads line q) and
         // clear them for the next step
         const int q = threadIdx.x;
@@ -971,6 +997,89 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             ctr->t = ctr->t + 1;
             *s.epoch = ep;
         }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_lanes(
+    Params P, Net net, Veh buf, Scratch s, Counters* ctr, int finalize) {
+    lanes_body(P, net, buf, s, ctr, finalize, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// The whole step in one persistent launch: the resident blocks (a
+// cooperative launch guarantees they run together) take the phases in turn,
+// each phase's blocks as virtual blocks in a loop, with a device-wide barrier
+// between phases; several steps per launch.  Same phases, same virtual
+// launch shapes, same results as the six launches.
+// ---------------------------------------------------------------------------
+struct GridSync {
+    unsigned count;  // blocks arrived at the current barrier
+    unsigned gen;    // barriers completed
+    unsigned fail;   // set when a wait gave up (the launch's results are then void)
+};
+
+// Every block waits here until all nblocks have arrived.  Each block's
+// arrival is a release (its writes reach memory past its XCD's L2) and its
+// departure one acquire (stale lines of its XCD's L2 and its CU's L1
+// dropped), so each phase sees the writes of the one before on every XCD; the
+// wait itself polls relaxed.  A wait that outlasts spin_limit polls, or finds
+// another block's wait given up, flags the failure; the caller then ends the
+// launch (returns true), so a launch always ends.
+__device__ __forceinline__ bool grid_sync(GridSync* g, unsigned nblocks, unsigned spin_limit) {
+    __shared__ int failed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&g->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(&g->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            // every other block's release is in the count this block read
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            __hip_atomic_store(&g->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&g->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&g->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > spin_limit ||
+                    __hip_atomic_load(&g->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    __hip_atomic_fetch_or(&g->fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        }
+        failed = __hip_atomic_load(&g->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    }
+    __syncthreads();
+    return failed != 0;
+}
+
+// nsteps steps from buffer `parity` (b[parity] holds the state); the virtual
+// grids are those of the six launches: qb + g8 decide blocks, g8 blocks for
+// the claim, mover and scatter phases, g blocks for the lane index, and the
+// scan's tiles handed out to every resident block
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_steps(Params P, Net net, Trips tr, Veh b0, Veh b1, Scratch s,
+                                                  Counters* ctr, GridSync* gs, int nsteps, int parity, int qb, int g8,
+                                                  int g, int lc_none, unsigned spin_limit) {
+    const Tape off{};
+    const unsigned nb = gridDim.x;
+    for (int k = 0; k < nsteps; ++k) {
+        const bool odd = ((parity + k) & 1) != 0;
+        const Veh& in = odd ? b1 : b0;
+        const Veh& out = odd ? b0 : b1;
+        for (int vb = blockIdx.x; vb < qb + g8; vb += nb) decide_body<kBlock, R>(P, net, tr, in, s, off, ctr, qb, vb, qb + g8);
+        if (grid_sync(gs, nb, spin_limit)) return;
+        for (int vb = blockIdx.x; vb < g8; vb += nb) resolve_body(P, net, tr, in, s, off, ctr, vb, g8);
+        if (grid_sync(gs, nb, spin_limit)) return;
+        scan_body(s, ctr);
+        if (grid_sync(gs, nb, spin_limit)) return;
+        for (int vb = blockIdx.x; vb < g8; vb += nb) scatter_body(P, in, out, s, off, ctr, vb, g8);
+        if (grid_sync(gs, nb, spin_limit)) return;
+        for (int vb = blockIdx.x; vb < g8; vb += nb) place_body(P, tr, in, out, s, off, lc_none, ctr, vb, g8);
+        if (grid_sync(gs, nb, spin_limit)) return;
+        for (int vb = blockIdx.x; vb < g; vb += nb) lanes_body(P, net, out, s, ctr, 1, vb, g);
+        if (grid_sync(gs, nb, spin_limit)) return;
     }
 }
 

@@ -94,6 +94,8 @@ struct sim_t {
     float* d_cVs = nullptr;
     float* d_cB = nullptr;
     unsigned* d_epoch = nullptr;
+    GridSync* d_gsync = nullptr;  // the persistent step's barrier state
+    int persist_res[2] = {0, 0};  // resident blocks of k_steps<1>, k_steps<2> on the device (0 unknown)
     // intersection control: per node kind, per edge inbound rank, per node inbound degree
     int* d_ctrl = nullptr;
     int* d_in_rank = nullptr;
@@ -405,6 +407,51 @@ void replay_window(sim_t* S, const ReplayCon<R>& con, int K, R* cx, R* cv, R* nx
         std::swap(cx, nx);
         std::swap(cv, nv);
     }
+}
+
+// k_steps<R>: blocks of the whole device that run at once
+template <int R>
+int persistent_blocks(sim_t* S, int* out) {
+    int& res = S->persist_res[R - 1];
+    if (res == 0) {
+        int dev = 0, cus = 0, nb = 0;
+        HIPCHECK(S, hipGetDevice(&dev));
+        HIPCHECK(S, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIPCHECK(S, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_steps<R>, kBlock, 0));
+        if (cus <= 0 || nb <= 0) return fail(S, SIM_EHIP, "the persistent step kernel cannot be resident");
+        res = cus * nb;
+    }
+    *out = res;
+    return SIM_OK;
+}
+
+// n steps in one cooperative launch of k_steps<R>
+template <int R>
+int launch_persistent(sim_t* S, int n) {
+    int res = 0;
+    int rc = persistent_blocks<R>(S, &res);
+    if (rc) return rc;
+    int g8 = (S->grid + kSeg - 1) / kSeg * kSeg;
+    int qb = S->tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
+    int g = S->grid;
+    const int grid = std::max(1, std::min(res, std::max(qb + g8, g)));
+    int parity = (int)(S->host_t & 1);
+    int lc_none = kLcNone;
+    unsigned spin_limit = 1u << 20;  // about 0.05 s of polling: far above any phase
+    Params P = S->P;
+    Net net = S->net;
+    Trips tr = S->tr;
+    Veh b0 = S->buf[0], b1 = S->buf[1];
+    Scratch sc = S->s;
+    Counters* ctr = S->ctr;
+    GridSync* gs = S->d_gsync;
+    void* args[] = {&P, &net, &tr, &b0, &b1, &sc, &ctr, &gs, &n, &parity, &qb, &g8, &g, &lc_none, &spin_limit};
+    // a fresh barrier count and generation (the failure flag stays until read)
+    HIPCHECK(S, hipMemsetAsync(S->d_gsync, 0, 2 * sizeof(unsigned), S->stream));
+    HIPCHECK(S, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_steps<R>), dim3(grid), dim3(kBlock),
+                                           args, 0, S->stream));
+    S->host_t += n;
+    return SIM_OK;
 }
 
 int alloc_adjoint(sim_t* S) {
@@ -894,6 +941,31 @@ int sim_step(sim_t* S, int32_t num_steps) {
         if (timed) S->ev_steps.emplace_back(ev, ev + 2 * SIM_NUM_KERNELS);
         S->host_t += 1;
     }
+    return SIM_OK;
+}
+
+int sim_step_persistent(sim_t* S, int32_t num_steps) {
+    if (!S) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (num_steps < 0) return fail(S, SIM_EINVAL, "negative step count");
+    if (S->tape_on || S->timing_every > 0) return sim_step(S, num_steps);  // per-step host work: plain launches
+    if (kDecideShapes[S->dshape].block != kBlock || kDecideShapes[S->dshape].per > 2)
+        return fail(S, SIM_EINVAL, "the persistent step takes decide shapes of 256 threads and 1 or 2 entries each");
+    if (!S->d_gsync) {
+        if (!dalloc(S, S->d_gsync, 1)) return fail(S, SIM_ENOMEM, "barrier state");
+        HIPCHECK(S, hipMemsetAsync(S->d_gsync, 0, sizeof(GridSync), S->stream));
+    }
+    // at most 600 steps per launch
+    for (int done = 0; done < num_steps;) {
+        const int n = std::min(600, num_steps - done);
+        const int rc = kDecideShapes[S->dshape].per == 2 ? launch_persistent<2>(S, n) : launch_persistent<1>(S, n);
+        if (rc) return rc;
+        done += n;
+    }
+    GridSync h{};
+    HIPCHECK(S, hipMemcpyAsync(&h, S->d_gsync, sizeof(GridSync), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    if (h.fail) return fail(S, SIM_EHIP, "a device-wide barrier of the persistent step gave up waiting: state void");
     return SIM_OK;
 }
 

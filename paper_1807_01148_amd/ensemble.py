@@ -91,6 +91,13 @@ def apply_shape(sim: Sim, shape: dict):
         set_decide_shape(sim, shape["decide_block"], shape["decide_per_thread"])
 
 
+def device_key(device: int = 0) -> str:
+    """The GPU's architecture name (e.g. gfx950), the key of tuned launch
+    shapes: stable across drivers and profilers, unlike the marketing name."""
+    import torch
+    return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+
+
 def autotune(sim: Sim, steps_per_trial: int = 60, cache_key: str | None = None, cache_path: str | None = None):
     """Pick the fastest launch shape from the current state (the state is
     restored).  With ``cache_key``, a result stored in the JSON cache (keyed by
@@ -100,7 +107,7 @@ def autotune(sim: Sim, steps_per_trial: int = 60, cache_key: str | None = None, 
     path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "trafficsim_autotune.json")
     key = None
     if cache_key is not None:
-        key = "%s|%s" % (torch.cuda.get_device_name(sim.device), cache_key)
+        key = "%s|%s" % (device_key(sim.device), cache_key)
         try:
             with open(path) as f:
                 hit = json.load(f).get(key)

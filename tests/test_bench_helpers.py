@@ -13,7 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def write_summary(path, sha, fetch="1000", write="24", workload="metro", start=18300):
     with open(path, "w") as f:
         f.write("# summary\n\ntext: not a field\n\n")
-        f.write("- kernel_sources_sha256: %s\n- workload: %s\n- window_start_step: %d\n" % (sha, workload, start))
+        f.write("- kernel_sources_sha256: %s\n- workload: %s\n- window_start_step: %d\n- launch: 1024,256,256,2\n"
+                % (sha, workload, start))
         for i, k in enumerate(bench.STEP_KERNELS):
             f.write("- %s_fetch_bytes_per_launch: %s\n- %s_write_bytes_per_launch: %s\n" % (k, fetch, k, i))
         f.write("- k_decide_write_bytes_per_launch: %s\n" % write)
@@ -35,6 +36,9 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
     assert sorted(tr) == sorted(bench.STEP_KERNELS)
     assert tr["k_decide"] == (1000.0, 24.0) and tr["k_lanes"] == (1000.0, float(bench.STEP_KERNELS.index("k_lanes")))
     assert bench.measured_traffic("metro", 18300) == tr
+    assert bench.measured_traffic("metro", 18300, (1024, 256, 256, 2)) == tr
+    # counters taken with another launch shape do not describe this one
+    assert bench.measured_traffic("metro", 18300, (2048, 512, 256, 1)) is None
     # counters of another window or workload do not describe this one
     assert bench.measured_traffic("metro", 7205) is None
     assert bench.measured_traffic("grid50", 18300) is None

@@ -44,14 +44,17 @@ def loss_and_grad(sim, target):
     return g, tbar.double().cpu().numpy(), cnt.cpu().numpy(), m.cpu().numpy()
 
 
-def fd_gradient(sim, theta, tbar0, cnt, mask, target, dt, h=1e-6):
-    """Central differences of the double replay's loss, the recorded mean
-    times shifted by the replayed fraction sums."""
+def fd_gradient(sim, theta, target, dt, h=1e-6):
+    """Central differences of the double replay's loss: mean link travel
+    times of the replay itself (the recorded whole steps plus the replayed
+    fractions), as the FP64 CPU replay forms them."""
+    es = sim.edge_stats()
+    cnt = es["count"]
+    mask = cnt > 0
     th0 = np.asarray(theta, np.float64)
-    F0 = sim.replay(th0, fp64=True)
 
     def loss(th):
-        tb = tbar0 + dt * (sim.replay(th, fp64=True) - F0) / np.maximum(cnt, 1)
+        tb = dt * (es["tt_steps"] + sim.replay(th, fp64=True)) / np.maximum(cnt, 1)
         return float(((tb - target)[mask] ** 2).mean())
 
     g = np.zeros(th0.shape, np.float64)
@@ -118,7 +121,7 @@ def test_replay_finite_differences_match_the_adjoint():
     g_adj, tbar0, cnt, m = loss_and_grad(sim, tgt)
     theta = scen["params"]["idm"].astype(np.float32)
     dt = float(np.float32(scen["params"]["dt"]))
-    g_fd = fd_gradient(sim, theta, tbar0, cnt, m, tgt, dt)
+    g_fd = fd_gradient(sim, theta, tgt, dt)
     o = oracle.Oracle(scen, "f32", tape=True)
     o.step(scen["steps"])
     mask = o.edge_stats()["count"] > 0
@@ -134,6 +137,7 @@ def test_replay_finite_differences_match_the_adjoint():
     # the differences of the double replay are the derivative along the
     # double-replayed trajectory (the CPU adjoint's g_r); the GPU adjoint
     # linearizes along the float trajectory, which differs from it by rounding
-    # that the dynamics amplify (about 1e-3, as between the two CPU references)
+    # that the dynamics amplify (about 1e-3 here, as between the two CPU
+    # references)
     assert e["fd_vs_fp64_replayed"] <= 1e-4, e
-    assert e["fd_vs_gpu_adjoint"] <= 2e-3, e
+    assert e["fd_vs_gpu_adjoint"] <= 1.5e-3, e
