@@ -171,24 +171,8 @@ def cpu_baseline(scen, state, seconds_budget=20.0):
 
 
 def ensemble_scenarios(seed=1811, n=64, steps=3600):
-    """Uneven grid scenarios: side U{20..120}, trips log-uniform in [1e4, 3e5],
-    IDM parameters per scenario (v0 x U(0.8,1.2), T U(1,2), a U(0.7,1.5),
-    b U(1,2.5)), 100 m links, 2 lanes, 15 m/s, departures U(0, 1800 s)."""
-    import numpy as np
     import scenarios as S
-    rng = np.random.default_rng(seed)
-    out = []
-    for q in range(n):
-        side = int(rng.integers(20, 121))
-        ntr = int(np.exp(rng.uniform(np.log(1e4), np.log(3e5))))
-        net = S.grid(side, seed=seed * 1000 + q, link_len=100.0, lanes=2, speed=15.0)
-        p = S.default_params()
-        p["idm"] = S.draw_idm(rng, 1)
-        o, d = S.uniform_od(rng, side * side, ntr)
-        dep = rng.uniform(0.0, 1800.0, ntr)
-        out.append({"name": "ens%d" % q, "net": net, "params": p,
-                    "demand": S.make_demand(net, o, d, dep, p["dt"]), "steps": steps})
-    return out
+    return S.ensemble_scenarios(seed=seed, n=n, steps=steps)
 
 
 def ensemble_speedup(args, n=64, log_prefix="[ensemble]"):

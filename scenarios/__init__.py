@@ -504,6 +504,26 @@ def draw_idm(rng, num_classes):
     return idm
 
 
+def ensemble_scenarios(seed: int = 1811, n: int = 64, steps: int = 3600):
+    """The batched-ensemble workload: uneven grid scenarios, side U{20..120},
+    trips log-uniform in [1e4, 3e5], IDM parameters per scenario
+    (v0 x U(0.8,1.2), T U(1,2), a U(0.7,1.5), b U(1,2.5)), 100 m links,
+    2 lanes, 15 m/s, departures U(0, 1800 s)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        side = int(rng.integers(20, 121))
+        ntr = int(np.exp(rng.uniform(np.log(1e4), np.log(3e5))))
+        net = grid(side, seed=seed * 1000 + q, link_len=100.0, lanes=2, speed=15.0)
+        p = default_params()
+        p["idm"] = draw_idm(rng, 1)
+        o, d = uniform_od(rng, side * side, ntr)
+        dep = rng.uniform(0.0, 1800.0, ntr)
+        out.append({"name": "ens%d" % q, "net": net, "params": p,
+                    "demand": make_demand(net, o, d, dep, p["dt"]), "steps": steps})
+    return out
+
+
 def diff_scenario(seed: int = 1812, side: int = 50, n_trips: int = 100_000, steps: int = 1800,
                   depart_s: float = 600.0, num_classes: int = 4):
     """Differentiation workload: the 50x50 grid network with link classes drawn

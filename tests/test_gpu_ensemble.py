@@ -164,3 +164,42 @@ def test_autotune_restores_state():
         assert np.array_equal(v, tun.vehicles()[k])
     for k, v in ref.trips().items():
         assert np.array_equal(v, tun.trips()[k])
+
+
+def test_batched_ensemble_workload_at_full_size():
+    """The batched-ensemble workload at full size (64 grid scenarios, side
+    20-120, 1e4-3e5 trips each, per-scenario IDM parameters) as one simulation
+    with graph-captured 60-step chunks and a tuned launch shape, over 1,800
+    steps: every member's link statistics and trip outcomes equal its own
+    simulation's, and the three smallest members equal the FP32 oracle."""
+    import oracle
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.ensemble import Ensemble, autotune, step_graph
+    steps = 1800
+    scens = S.ensemble_scenarios(n=64, steps=steps)
+    ens = Ensemble(scens)
+    step_graph(ens, 60, 60)
+    autotune(ens, steps_per_trial=20)
+    step_graph(ens, steps - 60, 60)
+    est, etr = ens.edge_stats(), ens.trips()
+    upd = 0
+    for q, sc in enumerate(scens):
+        one = P.Sim(sc)
+        one.step(steps)
+        for k, v in one.edge_stats().items():
+            assert np.array_equal(ens.scenario_edge_stats(q, est)[k], v), (q, k)
+        ts, to = ens.scenario_trips(q, etr), per_trip(one, sc["demand"]["depart_step"])
+        for k, v in to.items():
+            assert np.array_equal(ts[k], v), (q, k)
+        upd += one.counters()["vehicle_updates"]
+        one.close()
+    assert ens.counters()["vehicle_updates"] == upd
+    small = sorted(range(len(scens)), key=lambda q: scens[q]["demand"]["depart_step"].size)[:3]
+    for q in small:
+        o = oracle.Oracle(scens[q], "f32")
+        o.step(steps)
+        for k, v in o.edge_stats().items():
+            assert np.array_equal(ens.scenario_edge_stats(q, est)[k], v), (q, k)
+        ts, to = ens.scenario_trips(q, etr), oracle_trips(o, scens[q]["demand"]["depart_step"])
+        for k, v in to.items():
+            assert np.array_equal(ts[k], v), (q, k)
