@@ -226,9 +226,12 @@ __global__ void k_replay_init(Tape tp, R* rx, R* rv, R* phin, long long cap) {
 
 // entry fractions of the vehicles on the road at the window start
 template <class R>
-__global__ void k_replay_phin(const Veh ck, const Counters* ckctr, R* phin) {
+__global__ void k_replay_phin(const Veh ck, const float* ckphin, const Counters* ckctr, R* phin) {
     const int n = ckctr->n;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) phin[ck.vid[i]] = (R)ck.phin[i];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int id = ck.vid[i];
+        phin[id] = (R)ckphin[id];
+    }
 }
 
 // the recorded state of a step (stands for the vehicles entering the road)

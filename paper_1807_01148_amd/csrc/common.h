@@ -141,18 +141,25 @@ struct Trips {
     int* arrive_step;
     float* fuel_total;  // per vehicle id, at arrival
     float* co_total;
+    // The state of a vehicle on the road that changes only when it enters a
+    // link, by vehicle id (the sorted arrays do not carry it, so the
+    // per-step re-sort does not move it): its current link's index in the
+    // route, the step it entered that link and the fraction of the step at
+    // which it did.
+    int* rcur;
+    int* kin;
+    float* phin;
 };
 
+// The vehicles on the road, sorted by (lane key, position): what the step
+// reads or changes every step.
 struct Veh {
     int* key;
     float* x;
     float* v;
     int* edge;
-    int* rcur;
     int* next;
     int* lc;
-    int* kin;
-    float* phin;
     int* vid;
     float* fuel;  // accumulated fuel (mL)
     float* co;    // accumulated CO (g)

@@ -154,7 +154,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             tp.mode[i] = nx < 0 ? kModeArrive : kModeCross;
         }
         if (nx < 0) {  // arrival at the end of the last link
-            record_exit(P, s, e, in.kin[i], in.phin[i], f, t);
+            record_exit(P, s, e, tr.kin[vid], tr.phin[vid], f, t);
             float fu = in.fuel[i], co = in.co[i];
             emissions(P, v, vn, fu, co);
             tr.fuel_total[vid] = fu;
@@ -580,8 +580,8 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
         const bool occ = lane_range(s.lanes, key, ep, lo, hi);
         const int kb0 = s.lblk[key >> kLaneBlkLog], kb1 = s.lblk[(key >> kLaneBlkLog) + 1];
         const int sx = src >= 0 ? src : 0;
-        const int se = in.edge[sx], skin = in.kin[sx];
-        const float sphin = in.phin[sx];
+        const int se = in.edge[sx], skin = tr.kin[vid];
+        const float sphin = tr.phin[vid];
         // ownership of every claimed cell (all read at once: no early exit)
         const unsigned long long* cell = s.cells + cb;
         const unsigned long long mine = tag | (unsigned)vid;
@@ -632,7 +632,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Params P, Net net, Trips tr,
 // ---------------------------------------------------------------------------
 // k_scan: exclusive scan of w[i] = stay[i] + mcnt[i], i in [0, N], single pass
 // with decoupled look-back; tiles are handed out in order by an atomic counter
-// so a tile only ever waits on tiles already being processed.
+// so a tile only ever waits on tiles already being processed.  It writes, per
+// entry, the new position of the entry (its exclusive prefix plus the movers
+// placed before it, those of gap i), complemented (~) when the entry does not
+// stay, so that the re-sort reads one word per entry: cscan[i] ^ (cscan[i] >> 31)
+// is that position, and the gap's first position is it minus mcnt[i].
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int block_excl_scan(int v, int& total) {
     __shared__ int ws[kBlock / kWave];
@@ -677,6 +681,7 @@ __device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
         if (tile >= ntiles) break;
         const int base = tile * kScanTile + threadIdx.x * kScanItems;
         int vals[kScanItems];
+        unsigned stays = 0;  // bit q: entry base + q stays
         int tsum = 0;
         if (base + kScanItems <= total) {
             // a whole run of 16: four 16-byte loads of the counts and one of the
@@ -690,8 +695,10 @@ __device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
                 const int mm[4] = {m.x, m.y, m.z, m.w};
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int w = mm[r] + (int)((sw[h] >> (8 * r)) & 0xFFu);
+                    const int sy = (int)((sw[h] >> (8 * r)) & 0xFFu);
+                    const int w = mm[r] + sy;
                     vals[4 * h + r] = w;
+                    stays |= (unsigned)(sy != 0) << (4 * h + r);
                     tsum += w;
                 }
             }
@@ -699,7 +706,11 @@ __device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
             for (int q = 0; q < kScanItems; ++q) {
                 int idx = base + q;
                 int w = 0;
-                if (idx < total) w = s.mcnt[idx] + (idx < N ? (int)s.stay[idx] : 0);
+                if (idx < total) {
+                    const int sy = idx < N ? (int)s.stay[idx] : 0;
+                    w = s.mcnt[idx] + sy;
+                    stays |= (unsigned)(sy != 0) << q;
+                }
                 vals[q] = w;
                 tsum += w;
             }
@@ -749,25 +760,32 @@ __device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
         }
         __syncthreads();
         int run = s_prefix + excl;
+        // entry q's position: the prefix before it plus its gap's movers
+        // (w - stay), complemented unless it stays
+        auto pos = [&](int q, int r) {
+            const int sy = (int)((stays >> q) & 1u);
+            const int j = r + vals[q] - sy;
+            return sy ? j : ~j;
+        };
         if (base + kScanItems <= total) {
             int4* c4 = reinterpret_cast<int4*>(s.cscan + base);
 #pragma unroll
             for (int h = 0; h < kScanItems / 4; ++h) {
                 int4 o;
-                o.x = run;
+                o.x = pos(4 * h, run);
                 run += vals[4 * h];
-                o.y = run;
+                o.y = pos(4 * h + 1, run);
                 run += vals[4 * h + 1];
-                o.z = run;
+                o.z = pos(4 * h + 2, run);
                 run += vals[4 * h + 2];
-                o.w = run;
+                o.w = pos(4 * h + 3, run);
                 run += vals[4 * h + 3];
                 c4[h] = o;
             }
         } else {
             for (int q = 0; q < kScanItems; ++q) {
                 int idx = base + q;
-                if (idx < total) s.cscan[idx] = run;
+                if (idx < total) s.cscan[idx] = pos(q, run);
                 run += vals[q];
             }
         }
@@ -785,12 +803,12 @@ __device__ __forceinline__ void scatter_body(const Params& P, const Veh& in, con
     const int N = ctr->n;
     for (int i = bid * kBlock + threadIdx.x; i < N; i += nblk * kBlock) {
         // every field read before the branch (almost every entry stays)
-        const bool st = s.stay[i] != 0;
-        const int j = s.cscan[i] + s.mcnt[i];
-        const int key = in.key[i], edge = in.edge[i], rcur = in.rcur[i], next = in.next[i], lc = in.lc[i];
-        const int kin = in.kin[i], vid = in.vid[i];
+        const int j = s.cscan[i];  // the new position, complemented unless it stays
+        const bool st = j >= 0;
+        const int key = in.key[i], edge = in.edge[i], next = in.next[i], lc = in.lc[i];
+        const int vid = in.vid[i];
         const unsigned char ty = in.ty[i];
-        const float xs = s.xs[i], vs = s.vs[i], v = in.v[i], phin = in.phin[i];
+        const float xs = s.xs[i], vs = s.vs[i], v = in.v[i];
         float fu = in.fuel[i], co = in.co[i];
         if (!st) continue;
         if (tp.on) tp.next[i] = j;
@@ -798,11 +816,8 @@ __device__ __forceinline__ void scatter_body(const Params& P, const Veh& in, con
         out.x[j] = xs;
         out.v[j] = vs;
         out.edge[j] = edge;
-        out.rcur[j] = rcur;
         out.next[j] = next;
         out.lc[j] = lc;
-        out.kin[j] = kin;
-        out.phin[j] = phin;
         out.vid[j] = vid;
         out.ty[j] = ty;
         emissions(P, v, vs, fu, co);
@@ -816,8 +831,10 @@ __device__ __forceinline__ void scatter_body(const Params& P, const Veh& in, con
         const int m = seg * s.cl_seg + j;
         const int p = s.mv_p[m];
         const int ci = s.mv_claim[m];
-        const int b = s.cscan[p];
-        s.mv_g[m] = s.mcnt[p];
+        const int g = s.mcnt[p];
+        const int cp = s.cscan[p];
+        const int b = (cp ^ (cp >> 31)) - g;
+        s.mv_g[m] = g;
         s.grp_key[b + s.mv_slot[m]] = s.cl_key[ci];
         s.grp_X[b + s.mv_slot[m]] = s.cl_X[ci];
     }
@@ -846,7 +863,8 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
         // reads in three dependent rounds, each issued before any branch: the
         // claim and its gap; the source vehicle's fields and the trip's; the
         // route's next link
-        const int b = s.cscan[p];
+        const int cp = s.cscan[p];
+        const int b = (cp ^ (cp >> 31)) - g;
         const int key = s.cl_key[ci];
         const float X = s.cl_X[ci];
         const int kind = s.cl_kind[ci];
@@ -857,8 +875,8 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
         const float cf = s.cl_f[ci];
         const int sx = src >= 0 ? src : 0;
         const float sfu = in.fuel[sx], sco = in.co[sx], sv = in.v[sx];
-        const int srcur = in.rcur[sx], snext = in.next[sx], slc = in.lc[sx], skin = in.kin[sx];
-        const float sphin = in.phin[sx];
+        const int snext = in.next[sx], slc = in.lc[sx];
+        const int srcur = tr.rcur[vid];
         const int vty = tr.vtype[vid], rend = tr.rend[vid], rbeg = tr.rbeg[vid];
         int r = 0;
         if (g > 1) {
@@ -884,19 +902,16 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
             out.fuel[j] = 0.0f;
             out.co[j] = 0.0f;
         }
-        if (kind == kChange) {
-            out.rcur[j] = srcur;
+        if (kind == kChange) {  // same link: the trip state stays
             out.next[j] = snext;
             out.lc[j] = t;
-            out.kin[j] = skin;
-            out.phin[j] = sphin;
         } else {  // a crossing enters the next link of its route, a departure the first
             const int rc = kind == kCross ? srcur + 1 : rbeg;
-            out.rcur[j] = rc;
             out.next[j] = (rc + 1 < rend) ? tr.route_edges[rc + 1] : -1;
             out.lc[j] = kind == kCross ? slc : lc_none;
-            out.kin[j] = t + 1;
-            out.phin[j] = kind == kCross ? cf : 1.0f;
+            tr.rcur[vid] = rc;
+            tr.kin[vid] = t + 1;
+            tr.phin[vid] = kind == kCross ? cf : 1.0f;
         }
         s.mcnt[p] = 0;
     }

@@ -57,6 +57,22 @@ using namespace tsim;
 // ===========================================================================
 // host side
 // ===========================================================================
+
+// a trip state (the arrays of Trips that change as vehicles enter links)
+struct Cold {
+    int* rcur = nullptr;
+    int* kin = nullptr;
+    float* phin = nullptr;
+};
+
+static Cold cold_of(const Trips& t) {
+    Cold c;
+    c.rcur = t.rcur;
+    c.kin = t.kin;
+    c.phin = t.phin;
+    return c;
+}
+
 struct sim_t {
     hipStream_t stream = nullptr;
     sim_alloc_fn alloc = nullptr;
@@ -119,6 +135,7 @@ struct sim_t {
     struct Ckpt {
         long long t = 0;
         Veh v{};
+        Cold c{};
         int* qstate = nullptr;
         Counters* ctr = nullptr;
         int* holder = nullptr;
@@ -135,6 +152,7 @@ struct sim_t {
     double* d_r64 = nullptr;     // FP64 replay: state (two buffers of x, v) and entry fractions, 5 x cap
     double* d_r64c = nullptr;    // FP64 replay: its IDM constants
     Veh rbuf[2]{};
+    Cold rcold{};            // trip state of the recompute pass
     int* rqstate = nullptr;  // queue heads and tails of the recompute pass
     Counters* rctr = nullptr;
     Tape slab{};  // tape_every slices of cap entries
@@ -329,25 +347,30 @@ int reindex(sim_t* S, const Veh& buf, const Scratch& sc, Counters* ctr) {
 
 bool alloc_veh(sim_t* S, Veh& V, size_t n) {
     return dalloc(S, V.key, n) && dalloc(S, V.x, n) && dalloc(S, V.v, n) && dalloc(S, V.edge, n) &&
-           dalloc(S, V.rcur, n) && dalloc(S, V.next, n) && dalloc(S, V.lc, n) && dalloc(S, V.kin, n) &&
-           dalloc(S, V.phin, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) && dalloc(S, V.co, n) &&
-           dalloc(S, V.ty, n);
+           dalloc(S, V.next, n) && dalloc(S, V.lc, n) && dalloc(S, V.vid, n) && dalloc(S, V.fuel, n) &&
+           dalloc(S, V.co, n) && dalloc(S, V.ty, n);
 }
 
-int copy_state(sim_t* S, const Veh& dv, int* dq, Counters* dctr, int* dhold, const Veh& sv, const int* sq,
-               const Counters* sctr, const int* shold) {
+bool alloc_cold(sim_t* S, Cold& c, size_t n) {
+    return dalloc(S, c.rcur, n) && dalloc(S, c.kin, n) && dalloc(S, c.phin, n);
+}
+
+// the step's state: the sorted vehicles (dv <- sv), their trip state by
+// vehicle id (dc <- sc), departure queues, counters, stop-node holders
+int copy_state(sim_t* S, const Veh& dv, const Cold& dc, int* dq, Counters* dctr, int* dhold, const Veh& sv,
+               const Cold& sc, const int* sq, const Counters* sctr, const int* shold) {
     const size_t n = (size_t)S->cap;
     const hipMemcpyKind k = hipMemcpyDeviceToDevice;
     HIPCHECK(S, hipMemcpyAsync(dv.key, sv.key, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.x, sv.x, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.v, sv.v, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.edge, sv.edge, sizeof(int) * n, k, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(dv.rcur, sv.rcur, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.next, sv.next, sizeof(int) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.lc, sv.lc, sizeof(int) * n, k, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(dv.kin, sv.kin, sizeof(int) * n, k, S->stream));
-    HIPCHECK(S, hipMemcpyAsync(dv.phin, sv.phin, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.vid, sv.vid, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dc.rcur, sc.rcur, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dc.kin, sc.kin, sizeof(int) * n, k, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(dc.phin, sc.phin, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.fuel, sv.fuel, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.co, sv.co, sizeof(float) * n, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(dv.ty, sv.ty, n, k, S->stream));
@@ -360,14 +383,16 @@ int copy_state(sim_t* S, const Veh& dv, int* dq, Counters* dctr, int* dhold, con
 int take_checkpoint(sim_t* S, int p) {
     if (S->nckpt == S->ckpt_pool.size()) {
         sim_t::Ckpt ck;
-        if (!alloc_veh(S, ck.v, S->cap) || !dalloc(S, ck.qstate, 2 * (size_t)S->tr.nq) || !dalloc(S, ck.ctr, 1) ||
+        if (!alloc_veh(S, ck.v, S->cap) || !alloc_cold(S, ck.c, S->cap) || !dalloc(S, ck.qstate, 2 * (size_t)S->tr.nq) ||
+            !dalloc(S, ck.ctr, 1) ||
             !dalloc(S, ck.holder, S->nn))
             return fail(S, SIM_ENOMEM, "checkpoint allocation failed");
         S->ckpt_pool.push_back(ck);
     }
     sim_t::Ckpt& ck = S->ckpt_pool[S->nckpt++];
     ck.t = S->host_t;
-    return copy_state(S, ck.v, ck.qstate, ck.ctr, ck.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
+    return copy_state(S, ck.v, ck.c, ck.qstate, ck.ctr, ck.holder, S->buf[p], cold_of(S->tr), S->qstate, S->ctr,
+                      S->s.holder);
 }
 
 Tape slice(sim_t* S, int k) {
@@ -398,7 +423,7 @@ void replay_window(sim_t* S, const ReplayCon<R>& con, int K, R* cx, R* cv, R* nx
     const dim3 g(S->adj_grid), b(kBlock);
     const sim_t::Ckpt& ck = S->ckpt_pool[0];
     hipLaunchKernelGGL(k_replay_init<R>, g, b, 0, S->stream, slice(S, 0), cx, cv, phin, (long long)S->cap);
-    hipLaunchKernelGGL(k_replay_phin<R>, g, b, 0, S->stream, ck.v, ck.ctr, phin);
+    hipLaunchKernelGGL(k_replay_phin<R>, g, b, 0, S->stream, ck.v, ck.c.phin, ck.ctr, phin);
     hipLaunchKernelGGL(k_zero_f64, g, b, 0, S->stream, S->d_rF, (long long)S->ne);
     for (int k = 0; k < K; ++k) {
         if (k + 1 < K) hipLaunchKernelGGL(k_replay_seed<R>, g, b, 0, S->stream, slice(S, k + 1), nx, nv);
@@ -461,7 +486,7 @@ int alloc_adjoint(sim_t* S) {
     AdjState& a = S->adj;
     S->adj_grid = S->grid;
     const size_t nthreads = (size_t)S->adj_grid * kBlock;
-    bool ok = alloc_veh(S, S->rbuf[0], cap) && alloc_veh(S, S->rbuf[1], cap) &&
+    bool ok = alloc_veh(S, S->rbuf[0], cap) && alloc_veh(S, S->rbuf[1], cap) && alloc_cold(S, S->rcold, cap) &&
               dalloc(S, S->rqstate, 2 * (size_t)S->tr.nq) && dalloc(S, S->rctr, 1) && dalloc(S, t.x, n) && dalloc(S, t.v, n) &&
               dalloc(S, t.vid, n) && dalloc(S, t.edge, n) && dalloc(S, t.lead, n) && dalloc(S, t.clead, n) &&
               dalloc(S, t.next, n) && dalloc(S, t.mode, n) && dalloc(S, t.flags, n) && dalloc(S, t.cflags, n) &&
@@ -822,11 +847,9 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
               dalloc(S, d_qtype, (size_t)nq) && dalloc(S, S->qstate, 2 * (size_t)nq);
     for (int b = 0; b < 2 && ok; ++b) {
         Veh& V = S->buf[b];
-        ok = dalloc(S, V.key, cap) && dalloc(S, V.x, cap) && dalloc(S, V.v, cap) && dalloc(S, V.edge, cap) &&
-             dalloc(S, V.rcur, cap) && dalloc(S, V.next, cap) && dalloc(S, V.lc, cap) &&
-             dalloc(S, V.kin, cap) && dalloc(S, V.phin, cap) && dalloc(S, V.vid, cap) &&
-             dalloc(S, V.fuel, cap) && dalloc(S, V.co, cap) && dalloc(S, V.ty, cap);
+        ok = alloc_veh(S, V, cap);
     }
+    ok = ok && dalloc(S, S->tr.rcur, cap) && dalloc(S, S->tr.kin, cap) && dalloc(S, S->tr.phin, cap);
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
     // claim segment q takes the claims of one eighth of k_decide's tiles (at
     // most one per vehicle; sized for the largest tile) and the departures of
@@ -871,14 +894,24 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     HIPCHECK(S, hipMemsetAsync(s.tile_status, 0, sizeof(unsigned long long) * ntiles, S->stream));
     const int p = (int)(S->host_t & 1);
     const int np = (int)pkey.size();
+    {  // trip state by vehicle id: the placed vehicles', the rest set at departure
+        std::vector<int> crcur(cap, 0), ckin(cap, 0);
+        std::vector<float> cphin(cap, 1.0f);
+        for (int i = 0; i < np; ++i) {
+            crcur[pvid[i]] = prcur[i];
+            ckin[pvid[i]] = pkin[i];
+            cphin[pvid[i]] = pphin[i];
+        }
+        if ((rc = h2d(S, S->tr.rcur, crcur.data(), cap)) || (rc = h2d(S, S->tr.kin, ckin.data(), cap)) ||
+            (rc = h2d(S, S->tr.phin, cphin.data(), cap)))
+            return rc;
+    }
     if (np) {
         Veh& V = S->buf[p];
         if ((rc = h2d(S, V.key, pkey.data(), np)) || (rc = h2d(S, V.x, px.data(), np)) ||
             (rc = h2d(S, V.v, pv.data(), np)) || (rc = h2d(S, V.edge, pedge.data(), np)) ||
-            (rc = h2d(S, V.rcur, prcur.data(), np)) || (rc = h2d(S, V.next, pnext.data(), np)) ||
-            (rc = h2d(S, V.lc, plc.data(), np)) || (rc = h2d(S, V.kin, pkin.data(), np)) ||
-            (rc = h2d(S, V.phin, pphin.data(), np)) || (rc = h2d(S, V.vid, pvid.data(), np)) ||
-            (rc = h2d(S, V.ty, pty.data(), np)))
+            (rc = h2d(S, V.next, pnext.data(), np)) || (rc = h2d(S, V.lc, plc.data(), np)) ||
+            (rc = h2d(S, V.vid, pvid.data(), np)) || (rc = h2d(S, V.ty, pty.data(), np)))
             return rc;
     }
     Counters c0{};
@@ -1000,6 +1033,9 @@ Trips recompute_trips(sim_t* S) {
     Trips rtr = S->tr;
     rtr.qhead = S->rqstate;
     rtr.qtail = S->rqstate + S->tr.nq;
+    rtr.rcur = S->rcold.rcur;
+    rtr.kin = S->rcold.kin;
+    rtr.phin = S->rcold.phin;
     return rtr;
 }
 
@@ -1009,7 +1045,8 @@ int recompute_segment(sim_t* S, size_t c, const Scratch& rs, const Trips& rtr, i
     const long long t_end = (c + 1 < S->nckpt) ? S->ckpt_pool[c + 1].t : S->host_t;
     const int K = (int)(t_end - ck.t);
     int rc;
-    if ((rc = copy_state(S, S->rbuf[0], S->rqstate, S->rctr, S->d_rholder, ck.v, ck.qstate, ck.ctr, ck.holder)))
+    if ((rc = copy_state(S, S->rbuf[0], S->rcold, S->rqstate, S->rctr, S->d_rholder, ck.v, ck.c, ck.qstate, ck.ctr,
+                         ck.holder)))
         return rc;
     if ((rc = reindex(S, S->rbuf[0], rs, S->rctr))) return rc;
     for (int k = 0; k < K; ++k)
@@ -1194,26 +1231,33 @@ int sim_read_vehicles(sim_t* S, int32_t cap, int32_t* n_out, int32_t* vid, int32
     if (c.n > cap) return fail(S, SIM_EINVAL, "capacity too small");
     const int n = c.n;
     const Veh& V = S->buf[S->host_t & 1];
-    std::vector<int> hvid(n), hedge(n), hkey(n), hrcur(n);
+    std::vector<int> hvid(n), hedge(n), hkey(n);
+    // the trip state is kept by vehicle id: whole arrays, read only if asked for
+    std::vector<int> crcur(cursor ? S->cap : 0), ckin(kin ? S->cap : 0);
+    std::vector<float> cphin(phin ? S->cap : 0);
     if (n) {
         HIPCHECK(S, hipMemcpyAsync(hvid.data(), V.vid, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
         HIPCHECK(S, hipMemcpyAsync(hedge.data(), V.edge, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
         HIPCHECK(S, hipMemcpyAsync(hkey.data(), V.key, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
-        HIPCHECK(S, hipMemcpyAsync(hrcur.data(), V.rcur, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
+        const size_t cb = sizeof(int) * (size_t)S->cap;
+        if (cursor) HIPCHECK(S, hipMemcpyAsync(crcur.data(), S->tr.rcur, cb, hipMemcpyDeviceToHost, S->stream));
+        if (kin) HIPCHECK(S, hipMemcpyAsync(ckin.data(), S->tr.kin, cb, hipMemcpyDeviceToHost, S->stream));
+        if (phin) HIPCHECK(S, hipMemcpyAsync(cphin.data(), S->tr.phin, cb, hipMemcpyDeviceToHost, S->stream));
         if (lc) HIPCHECK(S, hipMemcpyAsync(lc, V.lc, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
-        if (kin) HIPCHECK(S, hipMemcpyAsync(kin, V.kin, sizeof(int) * n, hipMemcpyDeviceToHost, S->stream));
         if (x) HIPCHECK(S, hipMemcpyAsync(x, V.x, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         if (v) HIPCHECK(S, hipMemcpyAsync(v, V.v, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
-        if (phin) HIPCHECK(S, hipMemcpyAsync(phin, V.phin, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         if (fuel) HIPCHECK(S, hipMemcpyAsync(fuel, V.fuel, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         if (co) HIPCHECK(S, hipMemcpyAsync(co, V.co, sizeof(float) * n, hipMemcpyDeviceToHost, S->stream));
         HIPCHECK(S, hipStreamSynchronize(S->stream));
     }
     for (int i = 0; i < n; ++i) {
-        if (vid) vid[i] = hvid[i];
+        const int id = hvid[i];
+        if (vid) vid[i] = id;
         if (edge) edge[i] = hedge[i];
         if (lane) lane[i] = hkey[i] - S->lane_base[hedge[i]];
-        if (cursor) cursor[i] = hrcur[i] - S->h_rbeg[hvid[i]];
+        if (cursor) cursor[i] = crcur[id] - S->h_rbeg[id];
+        if (kin) kin[i] = ckin[id];
+        if (phin) phin[i] = cphin[id];
     }
     return SIM_OK;
 }
@@ -1233,7 +1277,7 @@ int sim_read_trips(sim_t* S, int32_t* depart_actual, int32_t* arrive_step) {
 // state image: a header, then the sections below, each 256-byte aligned
 // ---------------------------------------------------------------------------
 namespace {
-constexpr unsigned long long kStateMagic = 0x3154415453534D54ull;  // "TMSSTAT1"
+constexpr unsigned long long kStateMagic = 0x3254415453534D54ull;  // "TMSSTAT2"
 struct StateHdr {
     unsigned long long magic;
     long long step, cap, nq, nn, ne, ntrips, bytes;
@@ -1261,9 +1305,10 @@ StateLayout state_layout(const sim_t* S) {
     L.total = o;
     return L;
 }
-// the 13 vehicle arrays of a buffer, in image order
-void veh_fields(const Veh& V, void* f[13]) {
-    void* a[13] = {V.key, V.x, V.v, V.edge, V.rcur, V.next, V.lc, V.kin, V.phin, V.vid, V.fuel, V.co, V.ty};
+// the 13 vehicle arrays, in image order: the sorted arrays of a buffer and
+// (route cursor, entry step, entry fraction) the trip state by vehicle id
+void veh_fields(const Veh& V, const Trips& T, void* f[13]) {
+    void* a[13] = {V.key, V.x, V.v, V.edge, T.rcur, V.next, V.lc, T.kin, T.phin, V.vid, V.fuel, V.co, V.ty};
     for (int i = 0; i < 13; ++i) f[i] = a[i];
 }
 }  // namespace
@@ -1285,7 +1330,7 @@ int sim_get_state(sim_t* S, sim_state_view* out, void* image) {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
         const size_t n = (size_t)S->cap;
         void* f[13];
-        veh_fields(V, f);
+        veh_fields(V, S->tr, f);
         for (int i = 0; i < 13; ++i) HIPCHECK(S, hipMemcpyAsync(img + L.veh[i], f[i], i < 12 ? 4 * n : n, k, S->stream));
         if (S->tr.nq) HIPCHECK(S, hipMemcpyAsync(img + L.q, S->qstate, sizeof(int) * 2 * (size_t)S->tr.nq, k, S->stream));
         HIPCHECK(S, hipMemcpyAsync(img + L.ctr, S->ctr, sizeof(Counters), k, S->stream));
@@ -1330,7 +1375,7 @@ int sim_set_state(sim_t* S, const void* image, size_t bytes) {
     const size_t n = (size_t)S->cap;
     const int p = (int)(h.step & 1);
     void* f[13];
-    veh_fields(S->buf[p], f);
+    veh_fields(S->buf[p], S->tr, f);
     for (int i = 0; i < 13; ++i) HIPCHECK(S, hipMemcpyAsync(f[i], img + L.veh[i], i < 12 ? 4 * n : n, k, S->stream));
     if (S->tr.nq) HIPCHECK(S, hipMemcpyAsync(S->qstate, img + L.q, sizeof(int) * 2 * (size_t)S->tr.nq, k, S->stream));
     HIPCHECK(S, hipMemcpyAsync(S->ctr, img + L.ctr, sizeof(Counters), k, S->stream));
@@ -1728,7 +1773,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     const int p = (int)(S->host_t & 1);
     unsigned long long* st_save = nullptr;
     int* trip_save = nullptr;
-    if (!alloc_veh(S, save.v, S->cap) || !dalloc(S, save.qstate, 2 * (size_t)S->tr.nq) || !dalloc(S, save.ctr, 1) ||
+    if (!alloc_veh(S, save.v, S->cap) || !alloc_cold(S, save.c, S->cap) || !dalloc(S, save.qstate, 2 * (size_t)S->tr.nq) ||
+        !dalloc(S, save.ctr, 1) ||
         !dalloc(S, st_save, 3 * (size_t)S->ne) || !dalloc(S, trip_save, 4 * (size_t)S->cap) ||
         !dalloc(S, save.holder, S->nn)) {
         release_from(S, mark);
@@ -1744,7 +1790,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     // put the saved state back (after every trial, and at the end)
     auto restore_state = [&]() -> int {
         S->host_t = t_save;
-        int r = copy_state(S, S->buf[p], S->qstate, S->ctr, S->s.holder, save.v, save.qstate, save.ctr, save.holder);
+        int r = copy_state(S, S->buf[p], cold_of(S->tr), S->qstate, S->ctr, S->s.holder, save.v, save.c, save.qstate,
+                           save.ctr, save.holder);
         if (r) return r;
         return reindex(S, S->buf[p], S->s, S->ctr);
     };
@@ -1788,7 +1835,8 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     TUNE_CHECK(hipMemcpyAsync(trip_save + S->cap, S->tr.arrive_step, tb, hipMemcpyDeviceToDevice, S->stream));
     TUNE_CHECK(hipMemcpyAsync(trip_save + 2 * (size_t)S->cap, S->tr.fuel_total, tb, hipMemcpyDeviceToDevice, S->stream));
     TUNE_CHECK(hipMemcpyAsync(trip_save + 3 * (size_t)S->cap, S->tr.co_total, tb, hipMemcpyDeviceToDevice, S->stream));
-    int rc = copy_state(S, save.v, save.qstate, save.ctr, save.holder, S->buf[p], S->qstate, S->ctr, S->s.holder);
+    int rc = copy_state(S, save.v, save.c, save.qstate, save.ctr, save.holder, S->buf[p], cold_of(S->tr), S->qstate,
+                        S->ctr, S->s.holder);
     if (rc) return finish(rc);
     TUNE_CHECK(hipMemcpyAsync(st_save, S->s.st_cnt, eb, hipMemcpyDeviceToDevice, S->stream));
     TUNE_CHECK(hipMemcpyAsync(st_save + S->ne, S->s.st_steps, eb, hipMemcpyDeviceToDevice, S->stream));
