@@ -255,8 +255,8 @@ def adjoint_speedup(seed=1812, log_prefix="[adjoint]"):
     classes, (v0_scale, T, a, b)) on the differentiation workload, three ways:
       * adjoint: one taped forward (checkpoint every 60 steps) + sim_grad;
       * the per-parameter loop at equal accuracy: central differences
-        (h = 1e-3) of the frozen-event replay, 32 replays of the recorded
-        window plus the forward that records it;
+        (h = 1e-8, in double) of the frozen-event replay, 32 replays of the
+        recorded window plus the forward that records it;
       * the plain per-scenario loop: central differences over 32 plain GPU
         runs (the events move with the parameters).
     Accuracy of each against the FP64 CPU adjoint of the FP32 oracle's tape

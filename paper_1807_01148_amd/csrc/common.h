@@ -221,6 +221,7 @@ struct Scratch {
     // movers (winning claims), in kSeg segments of cl_seg entries: the winners
     // of claim segment q go to mover segment q
     int* mvcnt;  // segment counters, kSegStride ints apart
+    int* tcnt;   // per segment, k_decide's next tile (kSegStride ints apart; cleared by k_resolve)
     int* mv_claim;
     int* mv_p;
     int* mv_slot;

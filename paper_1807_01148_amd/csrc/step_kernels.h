@@ -466,13 +466,21 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
     // and lane records of neighbouring vehicles are shared in that XCD's L2;
     // q is also the segment of every claim they append
     const int vb = bid - qblocks;
-    const int per = (nblk - qblocks) / kSeg;
     const int q = vb & (kSeg - 1);
     const int nch = (N + kTile - 1) / kTile;
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
     int clamps = 0, arrivals = 0, listed = 0, claims = 0;
     if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
-    for (int c = (int)(((long long)nch * q) / kSeg) + vb / kSeg; c < c_end; c += per) {
+    // the tiles of the eighth are taken in order from a counter of its own, so
+    // that a block that meets fast tiles takes more of them
+    __shared__ int s_c;
+    const int c_beg = (int)(((long long)nch * q) / kSeg);
+    for (;;) {
+        __syncthreads();  // s_c is read
+        if (threadIdx.x == 0) s_c = c_beg + atomicAdd(s.tcnt + q * kSegStride, 1);
+        __syncthreads();
+        const int c = s_c;
+        if (c >= c_end) break;
         const int b0 = c * kTile;
         // the tile and its two neighbours into LDS; the rest of the own
         // entries into registers
@@ -559,6 +567,7 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
     const int nb = nblk / kSeg;
     const unsigned ep = *s.epoch;
     const unsigned long long tag = epoch_tag(ep);
+    if (bid == 0 && threadIdx.x < kSeg) s.tcnt[threadIdx.x * kSegStride] = 0;  // k_decide is done with them
     if (bid == 0 && threadIdx.x == 0) {
         ctr->scan_tile = 0;
         ctr->epoch_next = ep + 1u;

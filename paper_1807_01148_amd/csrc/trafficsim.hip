@@ -857,7 +857,7 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     const size_t vseg = ((size_t)(cap + kMaxTile - 1) / kMaxTile + kSeg - 1) / kSeg * kMaxTile;
     s.cl_seg = (int)(vseg + ((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
     const size_t ncl = (size_t)kSeg * s.cl_seg;
-    ok = ok && dalloc(S, s.ccnt, (size_t)2 * kSeg * kSegStride) &&
+    ok = ok && dalloc(S, s.ccnt, (size_t)3 * kSeg * kSegStride) &&
          dalloc(S, s.sstat, (size_t)kSeg * kStatStride) &&
          dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
          dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && dalloc(S, s.cl_vid, ncl) &&
@@ -881,7 +881,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
     HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
     s.mvcnt = s.ccnt + kSeg * kSegStride;
-    HIPCHECK(S, hipMemsetAsync(s.ccnt, 0, sizeof(int) * 2 * kSeg * kSegStride, S->stream));
+    s.tcnt = s.ccnt + 2 * kSeg * kSegStride;
+    HIPCHECK(S, hipMemsetAsync(s.ccnt, 0, sizeof(int) * 3 * kSeg * kSegStride, S->stream));
     HIPCHECK(S, hipMemsetAsync(s.sstat, 0, sizeof(unsigned long long) * kSeg * kStatStride, S->stream));
     if (nq) HIPCHECK(S, hipMemsetAsync(S->qstate, 0, sizeof(int) * 2 * (size_t)nq, S->stream));
     HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));
