@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "vehicle-updates/sec at 1 GPU + % HBM roofline; adjoint & ensemble vs plain"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of k_decide: x and v read and written once per
-# vehicle-update (16 B), plus one 64-byte record per crossing claim
+# vehicle-update (16 B), plus one 64-byte record per claim
 B_PER_VEH = 16.0
 B_PER_EVENT = 64.0
 
@@ -661,9 +661,9 @@ def main():
     if samples:
         dom = max(avg, key=avg.get)
         per_launch_units = upd / args.steps
-        # k_decide advances the vehicles; its events are their crossing claims
-        # (the lane-change claims are k_change's)
-        per_launch_claims = claims_cross / args.steps
+        # k_decide advances the vehicles and issues every claim of the step
+        # (crossings, lane changes, departures)
+        per_launch_claims = claims / args.steps
         alg_bytes = B_PER_VEH * per_launch_units + B_PER_EVENT * per_launch_claims
         achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9
         tb = sum(traffic[dom]) if traffic and dom in traffic else None

@@ -191,38 +191,13 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     return true;
 }
 
-// Run of lane kt in the sorted arrays, from the tile when the tile decides it
-// (the slots before and after the lane's slots in the window are known to
-// hold other lanes or the array's ends): in [lo, hi] (tile slots) with
-// *empty when the lane has no vehicle.  Returns false when the run may reach
-// beyond the window.
-template <class TileT>
-__device__ __forceinline__ bool tile_run(const TileT& T, int kt, int& lo, int& hi) {
-    constexpr int NS = TileT::kSlots;
-    int a = 0, b = NS;  // first slot with key >= kt
-    while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (T.key[mid] < kt) a = mid + 1;
-        else b = mid;
-    }
-    int c = a, d = NS;  // first slot with key > kt
-    while (c < d) {
-        const int mid = (c + d) >> 1;
-        if (T.key[mid] <= kt) c = mid + 1;
-        else d = mid;
-    }
-    lo = a;
-    hi = c - 1;
-    return a > 0 && c < NS;
-}
-
 // Lane-change evaluation of a vehicle (Sec. 6.3.2): candidate lanes (the
 // mandatory one when the vehicle is outside its turn band near the link
 // end, else the neighbours inside the band), gap acceptance, the safety
 // criterion for the new follower, the incentive criterion; the best candidate
-// claims its cells in the target lane.  The follower, and the leader and lag
-// in a target lane whose run the tile holds, come from LDS; other runs from
-// the lane index and the sorted arrays.
+// claims its cells in the target lane.  The follower comes from LDS; a
+// target lane's run from the lane index (one record read), and its leader and
+// lag from LDS when the tile holds the run, else from the sorted arrays.
 template <class TileT>
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
                                const TileT& T, int t_slot, int b0, unsigned ep, unsigned long long tag, int seg,
@@ -283,8 +258,12 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         int jl = -1;
         float xl = 0.0f, vl = 0.0f, xFt = 0.0f, vFt = 0.0f;
         int tyl = 0, tyFt = 0;
-        int ra, rb;
-        if (tile_run(T, kt, ra, rb)) {
+        // the run from the lane index; searched in LDS when the tile holds it
+        int tlo, thi;
+        const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
+        const int w0 = b0 - 1;  // the entry in slot 0
+        if (occ && tlo >= w0 && thi <= w0 + TileT::kSlots - 1) {
+            const int ra = tlo - w0, rb = thi - w0;
             int a = ra, c = rb + 1;  // first slot in the run with x > own x
             while (a < c) {
                 const int mid = (a + c) >> 1;
@@ -294,12 +273,10 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             hasLead = a <= rb;
             hasFt = a - 1 >= ra;
             const int sl = hasLead ? a : t_slot, sf = hasFt ? a - 1 : t_slot;
-            jl = b0 - 1 + a;
+            jl = w0 + a;
             xl = T.x[sl]; vl = T.v[sl]; tyl = T.ty[sl];
             xFt = T.x[sf]; vFt = T.v[sf]; tyFt = T.ty[sf];
         } else {
-            int tlo, thi;
-            const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
             const int j = occ ? ub_x(in.x, tlo, thi + 1, x) : -1;
             hasLead = occ && j <= thi;
             hasFt = occ && j - 1 >= tlo;
