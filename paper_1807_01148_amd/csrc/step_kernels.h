@@ -57,6 +57,54 @@ struct Own {
     Lead L;
 };
 
+// The claims of a tile's vehicles (crossings and lane changes, at most one per
+// vehicle), gathered in LDS while the tile is decided and issued together
+// after it: the chain of a claim (its link's claim record, the cell atomics,
+// the list slot) is waited for once per tile instead of once for every pass
+// of a wave that holds a claiming vehicle.
+template <int NT>
+struct ClaimStage {
+    int n;
+    int i[NT];      // entry of the claiming vehicle
+    int vid[NT];
+    int tedge[NT];  // target link
+    int lb[NT];     // its first global lane
+    int pk[NT];     // target lane | kind << 8 | type << 16
+    float X[NT], v[NT], f[NT];
+};
+
+template <class StageT>
+__device__ __forceinline__ void stage_claim(StageT& CS, int i, int vid, int tedge, int lb, int tlane, int kind,
+                                            int ty, float X, float v, float f) {
+    const int m = atomicAdd(&CS.n, 1);
+    CS.i[m] = i;
+    CS.vid[m] = vid;
+    CS.tedge[m] = tedge;
+    CS.lb[m] = lb;
+    CS.pk[m] = tlane | (kind << 8) | (ty << 16);
+    CS.X[m] = X;
+    CS.v[m] = v;
+    CS.f[m] = f;
+}
+
+// issues the staged claims of a tile (after a barrier that follows the last
+// stage_claim): their cells, then their slots in segment seg of the list
+template <int BS, class StageT>
+__device__ __forceinline__ void issue_claims(const Params& P, const Net& net, const Scratch& s, StageT& CS, int seg,
+                                             unsigned long long tag) {
+    const int M = CS.n;
+    for (int m = threadIdx.x; m < M; m += BS) {
+        const int te = CS.tedge[m];
+        const int pk = CS.pk[m];
+        const float X = CS.X[m];
+        const ClaimRec C = net.cr[te];
+        int lo, hi;
+        claim_cells(P, C.ncell, pk >> 16, X, lo, hi);
+        push_claim(s, C, CS.lb[m], seg, tag, CS.vid[m], (pk >> 8) & 0xFF, CS.i[m], te, pk & 0xFF, X, CS.v[m],
+                   CS.f[m], lo, hi);
+    }
+}
+
 // Own leader: the next entry if it is in the same lane (ka, xa, va, tya), else
 // the stop line if the movement at the link end is held, else the rearmost
 // vehicle of the mapped lane of the next link of the route (E2), if any.
@@ -89,10 +137,10 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
 // The step decision of entry i (tile slot t + 1): leader, IDM, move, crossing
 // claim or arrival.  Returns true when the vehicle is to be evaluated for a
 // lane change, with what that needs in o.
-template <class TileT>
+template <class TileT, class StageT>
 __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in, const Scratch& s,
-                               const Tape& tp, const TileT& T, int t_slot, int N, int t, unsigned ep,
-                               unsigned long long tag, int i, int seg, int e, int nx, int vid, int lcs, int& clamps,
+                               const Tape& tp, const TileT& T, StageT& CS, int t_slot, int N, int t, unsigned ep,
+                               unsigned long long tag, int i, int e, int nx, int vid, int lcs, int& clamps,
                                int& arrivals, Own& o) {
     // the own entry and the one after it from the tile; the records of the
     // own link and type, and for the front vehicle of a lane the next link's,
@@ -167,13 +215,10 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         int nl2 = E2.lanes;
         int tl = l < nl2 - 1 ? l : nl2 - 1;
         float X = xs - len;
-        int lo, hi;
-        const ClaimRec C2 = net.cr[nx];
-        claim_cells(P, C2.ncell, ty, X, lo, hi);
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
-        push_claim(s, C2, E2.lane_base, seg, tag, vid, kCross, i, nx, tl, X, vn, f, lo, hi);
+        stage_claim(CS, i, vid, nx, E2.lane_base, tl, kCross, ty, X, vn, f);
         return false;
     }
     s.xs[i] = xs;
@@ -198,10 +243,9 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // claims its cells in the target lane.  The follower comes from LDS; a
 // target lane's run from the lane index (one record read), and its leader and
 // lag from LDS when the tile holds the run, else from the sorted arrays.
-template <class TileT>
+template <class TileT, class StageT>
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
-                               const TileT& T, int t_slot, int b0, unsigned ep, unsigned long long tag, int seg,
-                               const Own& o) {
+                               const TileT& T, StageT& CS, int t_slot, int b0, unsigned ep, const Own& o) {
     const int i = o.i, k = o.k, e = o.e, nx = o.nx, ty = o.ty, vid = o.vid, l = o.l;
     const float x = o.x, v = o.v, lme = o.lme, ac = o.ac;
     const bool held = o.held;
@@ -361,10 +405,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             tp.cflags[i] = (unsigned short)best_fl;
             tp.clead[i] = best_lead;
         }
-        int lo, hi;
-        const ClaimRec C = net.cr[e];
-        claim_cells(P, C.ncell, ty, best_X, lo, hi);
-        push_claim(s, C, lb, seg, tag, vid, kChange, i, e, best, best_X, best_v, 0.0f, lo, hi);
+        stage_claim(CS, i, vid, e, lb, best, kChange, ty, best_X, best_v, 0.0f);
         return true;
     }
     return false;
@@ -438,6 +479,7 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
         return;
     }
     __shared__ Tile<kTile + 2> T;
+    __shared__ ClaimStage<kTile> CS;
     // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
     // the q-th eighth of the sorted entries, tiles in order, so that the link
     // and lane records of neighbouring vehicles are shared in that XCD's L2;
@@ -497,6 +539,7 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
             T.x[kTile + 1] = has ? in.x[j] : 0.0f;
             T.v[kTile + 1] = has ? in.v[j] : 0.0f;
             T.ty[kTile + 1] = has ? (int)in.ty[j] : 0;
+            CS.n = 0;
         }
         __syncthreads();
 #pragma unroll
@@ -505,14 +548,16 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
             const int ts = r * BS + threadIdx.x + 1;
             if (i < N) {
                 Own o;
-                if (decide_vehicle(P, net, tr, in, s, tp, T, ts, N, t, ep, tag, i, q, e[r], nx[r], vid[r], lcs[r],
+                if (decide_vehicle(P, net, tr, in, s, tp, T, CS, ts, N, t, ep, tag, i, e[r], nx[r], vid[r], lcs[r],
                                    clamps, arrivals, o)) {
                     listed += 1;
-                    claims += change_vehicle(P, net, in, s, tp, T, ts, b0, ep, tag, q, o) ? 1 : 0;
+                    claims += change_vehicle(P, net, in, s, tp, T, CS, ts, b0, ep, o) ? 1 : 0;
                 }
             }
         }
-        __syncthreads();  // the tile is overwritten next
+        __syncthreads();  // every claim of the tile is staged
+        issue_claims<BS>(P, net, s, CS, q, tag);
+        __syncthreads();  // the tile and the staged claims are overwritten next
     }
     if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
