@@ -385,9 +385,11 @@ B_PER_RELAX = 20.0
 
 def bench_reroute(args):
     """Iterative decaying re-routing (Sec. 6.3.1) on the workload: four
-    iterations of (plan routes on the GPU, simulate the whole horizon,
-    measured link times become the weights), re-planning all, all, half and a
-    quarter of the trips.  Reports the route search rate (relaxed links per
+    iterations of (plan routes on the GPU, hand them to the simulation on
+    the device, simulate the whole horizon, measured link times become the
+    weights), re-planning all, all, half and a quarter of the trips; the
+    hand-off through the host (routes read out, a new simulation loaded) is
+    timed once beside it.  Reports the route search rate (relaxed links per
     second) of the full plan, per-iteration times and the mean trip time;
     the CPU baseline is the oracle's Dijkstra on a sample of origins."""
     import numpy as np
@@ -403,7 +405,9 @@ def bench_reroute(args):
     masks = S.reroute_masks(1813, n)
     rt = Router(scen["net"])
     rt.set_trips(d["src_nodes"], d["trip_src"], d["trip_dst"])
+    sim = P.Sim(scen)  # loaded once; every iteration replaces its routes on the device
     its = []
+    host_handoff = None
     for k in range(4):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -411,9 +415,19 @@ def bench_reroute(args):
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
         relax, nsrc = rt.last_work()
-        ptr, edges = rt.routes()
+        if k == 0:
+            # for comparison, once: the routes read out and a new simulation loaded with them
+            t0 = time.perf_counter()
+            ptr, edges = rt.routes()
+            t_read = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            other = P.Sim(with_routes(scen, ptr, edges))
+            torch.cuda.synchronize()
+            host_handoff = {"read_routes_s": t_read, "load_s": time.perf_counter() - t0}
+            other.close()
+            del ptr, edges, other
         t0 = time.perf_counter()
-        sim = P.Sim(with_routes(scen, ptr, edges))
+        sim.reload_routes(*rt.route_views())
         torch.cuda.synchronize()
         t_load = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -432,8 +446,7 @@ def bench_reroute(args):
                                          scen["params"]["dt"]) if done.any() else None,
                     "vehicle_updates": c["vehicle_updates"]})
         log("[reroute] iteration %d: %s" % (k, its[-1]))
-        sim.close()
-        del ptr, edges
+    sim.close()
     # trees/s: shortest-path trees (one per origin zone) of the full plan per second
     rate = its[0]["origins"] / its[0]["plan_s"]
     # CPU baseline: the oracle's Dijkstra from a sample of origins, scaled
@@ -454,7 +467,8 @@ def bench_reroute(args):
            "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "trees/s", "cores": 1, "kind": "oracle",
                             "sample": "binary-heap Dijkstra (int64) from %d origins of the workload, each "
                                       "relaxing every link once" % len(sample), "host": host_cpu()},
-           "iterations": its}
+           "iterations": its, "handoff": "device (sim_reload_routes; load_s of each iteration)",
+           "host_handoff_once": host_handoff}
     print(json.dumps(out), flush=True)
 
 

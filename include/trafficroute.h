@@ -77,6 +77,15 @@ int rt_plan(rt_t* rt, const uint8_t* select, int64_t* total_route_edges);
  * with trip_route[i] = i.  Either pointer may be NULL.  Errors: SIM_ESTATE. */
 int rt_read_routes(rt_t* rt, int64_t* route_ptr, int32_t* route_edges);
 
+/* The current routes where they are, on the DEVICE: *route_ptr int64
+ * [num_trips + 1] and *route_edges int32 [*total_route_edges], laid out as
+ * rt_read_routes writes them.  Owned by the router; valid until the next
+ * rt_plan or rt_destroy.  sim_reload_routes takes them as they are, so the
+ * routes never leave the device.  Any output may be NULL.
+ * Errors: SIM_ESTATE (no routes planned). */
+int rt_route_views(rt_t* rt, const int64_t** route_ptr, const int32_t** route_edges,
+                   int64_t* total_route_edges);
+
 /* Shortest-path tree from one node under the current weights: dist HOST
  * int64 [num_nodes] (INT64_MAX where unreachable) and pred HOST int32
  * [num_nodes] (last edge of the route to each node; -1 at the source and at

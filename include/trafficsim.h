@@ -125,6 +125,27 @@ int sim_load_demand(sim_t* sim, int32_t num_trips, const int32_t* depart_step,
                     const int32_t* route_edges, const float* init_x, const float* init_v,
                     const int32_t* init_lane);
 
+/* New routes for the same trips, handed over on the DEVICE, and the demand
+ * started again from its first step (Sec. 6.3.1: each iteration of the
+ * decaying re-routing simulates the whole horizon again with the re-planned
+ * routes).  route_ptr: DEVICE int64 [num_trips + 1], route_ptr[0] = 0,
+ * strictly increasing; route i = route_edges[route_ptr[i] .. route_ptr[i+1])
+ * (DEVICE int32 [total_route_edges]) is the route of trip i in the order of
+ * the sim_load_demand call (the table rt_route_views exposes).  Both arrays
+ * are copied; the caller keeps them.  Every route is checked on the device
+ * (non-empty, edge ids in range, consecutive edges meeting at a node) before
+ * anything changes.  The trips keep their departure steps and types; their
+ * departure queues (first link, type) are rebuilt for the new first links;
+ * the state goes back to the step the demand was loaded at: no vehicle on the
+ * road, empty queues, zero link statistics and samples, no trip outcomes.
+ * Launch shape, control and sampler settings stay.  Synchronises.
+ * Errors: SIM_ESTATE (no demand; a demand that placed vehicles on the road; a
+ * batch of scenarios; inside a differentiation window), SIM_EINVAL (null or
+ * negative arrays, route_ptr[num_trips] != total_route_edges), SIM_EROUTE (a
+ * bad route: nothing was changed), SIM_ENOMEM, SIM_EHIP. */
+int sim_reload_routes(sim_t* sim, const int64_t* route_ptr, const int32_t* route_edges,
+                      int64_t total_route_edges);
+
 /* Advance num_steps synchronous steps (Sec. 6.3.2: lane change, car following,
  * position/speed/travel-time update per vehicle per dt).  Asynchronous: only
  * enqueues kernels.  Errors: SIM_ESTATE (no demand), SIM_EINVAL, SIM_EHIP. */

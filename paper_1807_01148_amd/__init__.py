@@ -26,7 +26,7 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
             "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror", "sim_replay",
-            "sim_set_decide_shape", "sim_get_decide_shape", "sim_step_persistent")
+            "sim_set_decide_shape", "sim_get_decide_shape", "sim_step_persistent", "sim_reload_routes")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -89,6 +89,8 @@ def library(path: str = LIB_PATH):
         lib.sim_step.restype = ctypes.c_int
         lib.sim_step_persistent.argtypes = [P, i32]
         lib.sim_step_persistent.restype = ctypes.c_int
+        lib.sim_reload_routes.argtypes = [P, P, P, ctypes.c_int64]
+        lib.sim_reload_routes.restype = ctypes.c_int
         lib.sim_stats.argtypes = [P, ctypes.POINTER(SimStats), P, P, P]
         lib.sim_stats.restype = ctypes.c_int
         lib.sim_read_vehicles.argtypes = [P, i32, ctypes.POINTER(i32), P, P, P, P, P, P, P, P, P, P, P]
@@ -319,6 +321,27 @@ class Sim:
         another one with the same network, parameters, types and demand)."""
         self.stream.synchronize()
         self._check(self.lib.sim_set_state(self.h, ctypes.c_void_p(img.data_ptr()), img.numel()))
+
+    def reload_routes(self, route_ptr, route_edges, total=None):
+        """sim_reload_routes: new routes for the same trips from DEVICE memory
+        (torch tensors on this GPU, int64 [num_trips + 1] and int32, or raw
+        device addresses with `total`), and the demand started again from
+        its first step."""
+        if hasattr(route_ptr, "data_ptr"):
+            import torch
+            if route_ptr.dtype != torch.int64 or route_edges.dtype != torch.int32 or not route_ptr.is_cuda \
+                    or not route_edges.is_cuda or route_ptr.numel() != self.num_trips + 1:
+                raise ValueError("route_ptr: int64 [num_trips + 1] and route_edges: int32, both on the GPU")
+            route_ptr, route_edges = route_ptr.contiguous(), route_edges.contiguous()
+            total = route_edges.numel()
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            pa, ea = route_ptr.data_ptr(), route_edges.data_ptr()
+        else:
+            if total is None:
+                raise ValueError("raw device addresses need the total number of route edges")
+            pa, ea = int(route_ptr), int(route_edges)
+        self._check(self.lib.sim_reload_routes(self.h, ctypes.c_void_p(pa), ctypes.c_void_p(ea or None),
+                                               int(total)))
 
     def trips(self) -> dict:
         da = np.zeros(self.num_trips, np.int32)

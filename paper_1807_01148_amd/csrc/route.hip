@@ -857,6 +857,15 @@ int rt_read_routes(rt_t* R, int64_t* route_ptr, int32_t* route_edges) {
     return SIM_OK;
 }
 
+int rt_route_views(rt_t* R, const int64_t** route_ptr, const int32_t** route_edges, int64_t* total_route_edges) {
+    if (!R) return SIM_EINVAL;
+    if (!R->have_routes) return rfail(R, SIM_ESTATE, "no routes planned");
+    if (route_ptr) *route_ptr = reinterpret_cast<const int64_t*>(R->d_ptr);
+    if (route_edges) *route_edges = R->d_edges;
+    if (total_route_edges) *total_route_edges = R->total;
+    return SIM_OK;
+}
+
 int rt_tree(rt_t* R, int32_t src_node, int64_t* dist, int32_t* pred) {
     if (!R || src_node < 0 || src_node >= R->nn) return SIM_EINVAL;
     int rc = check_weight_sum(R, R->d_u64 + 1);

@@ -45,6 +45,9 @@
 #include <string>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
 #include "trafficsim.h"
 
 #include "common.h"
@@ -121,6 +124,22 @@ struct sim_t {
     bool loaded = false;
     int cap = 0;
     int ntrips = 0;
+    // what a route reload needs of the demand: its first step, whether it
+    // placed vehicles, per vehicle id the trip index and departure step, the
+    // capacities of the route table and of the departure queues
+    long long t_load = 0;
+    bool placed = false;
+    int* d_ord = nullptr;
+    int* d_dep = nullptr;
+    long long re_cap = 0;
+    int nq_cap = 0;
+    // route reload scratch (allocated at the first reload)
+    int* d_tail = nullptr;
+    unsigned* d_rkey = nullptr;  // [2 x cap] queue keys, then sorted
+    int* d_rval = nullptr;       // [2 x cap] vehicle ids, then queue flags and indices
+    int* d_rerr = nullptr;       // [2] first bad route, queue count
+    void* d_rtmp = nullptr;
+    size_t rtmp_bytes = 0;
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
     int grid_small = 1;  // k_scan's persistent blocks
@@ -212,6 +231,21 @@ template <class T>
 bool dalloc(sim_t* S, T*& out, size_t n) {
     out = static_cast<T*>(raw_alloc(S, sizeof(T) * (n ? n : 1)));
     return out != nullptr;
+}
+
+// frees one allocation of the handle (after the stream has drained)
+template <class T>
+void dfree(sim_t* S, T*& p) {
+    if (!p) return;
+    void* raw = const_cast<void*>(static_cast<const void*>(p));
+    auto it = std::find(S->allocs.begin(), S->allocs.end(), raw);
+    if (it != S->allocs.end()) {
+        (void)hipStreamSynchronize(S->stream);
+        if (S->free_fn) S->free_fn(S->ctx, raw);
+        else (void)hipFree(raw);
+        S->allocs.erase(it);
+    }
+    p = nullptr;
 }
 
 void release_all(sim_t* S) {
@@ -499,6 +533,128 @@ int alloc_adjoint(sim_t* S) {
     a.ncls = S->ncls;
     S->adj_k = S->tape_every;
     S->adj_ready = true;
+    return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// route reload (Sec. 6.3.1: each iteration simulates the horizon again with
+// the re-planned routes, handed over on the device)
+// ---------------------------------------------------------------------------
+
+// the lowest trip whose route is empty, out of the table, has an edge out of
+// range or two consecutive edges that do not meet
+__global__ void k_route_check(const int64_t* __restrict__ ptr, const int* __restrict__ edges, long long total,
+                              int ntrips, int ne, const int* __restrict__ head, const int* __restrict__ tail,
+                              int* first_bad) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < ntrips; i += gridDim.x * kBlock) {
+        const long long a = ptr[i], b = ptr[i + 1];
+        bool ok = (i > 0 || a == 0) && 0 <= a && a < b && b <= total;
+        for (long long k = a; ok && k < b; ++k) {
+            const int e = edges[k];
+            ok = 0 <= e && e < ne;
+            if (ok && k + 1 < b) {
+                const int e2 = edges[k + 1];
+                ok = 0 <= e2 && e2 < ne && head[e] == tail[e2];
+            }
+        }
+        if (!ok) atomicMin(first_bad, i);
+    }
+}
+
+// per vehicle id: its route's bounds and its departure queue's key
+// (first link x 4 + type), with the vehicle ids to sort by it
+__global__ void k_route_trips(const int64_t* __restrict__ ptr, const int* __restrict__ edges,
+                              const int* __restrict__ ord, const unsigned char* __restrict__ vtype, int n, int* rbeg,
+                              int* rend, unsigned* key, int* vid) {
+    for (int v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+        const int i = ord[v];
+        const long long a = ptr[i];
+        rbeg[v] = (int)a;
+        rend[v] = (int)ptr[i + 1];
+        key[v] = 4u * (unsigned)edges[a] + vtype[v];
+        vid[v] = v;
+    }
+}
+
+__global__ void k_queue_flags(const unsigned* __restrict__ key, int n, int* flag) {
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < n; m += gridDim.x * kBlock)
+        flag[m] = (m == 0 || key[m] != key[m - 1]) ? 1 : 0;
+}
+
+__global__ void k_queue_count(const int* __restrict__ flag, const int* __restrict__ qidx, int n, int* nq) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nq = n > 0 ? qidx[n - 1] + flag[n - 1] : 0;
+}
+
+// the queues from the trips sorted by key (stable: by vehicle id within a
+// queue): first member, link and type of each, and every member's departure
+__global__ void k_queue_build(const unsigned* __restrict__ key, const int* __restrict__ qvid,
+                              const int* __restrict__ flag, const int* __restrict__ qidx, const int* __restrict__ dep,
+                              int n, int* qoff, int* qedge, unsigned char* qtype, int* qdep) {
+    for (int m = blockIdx.x * kBlock + threadIdx.x; m < n; m += gridDim.x * kBlock) {
+        qdep[m] = dep[qvid[m]];
+        if (flag[m]) {
+            const int q = qidx[m];
+            qoff[q] = m;
+            qedge[q] = (int)(key[m] >> 2);
+            qtype[q] = (unsigned char)(key[m] & 3u);
+        }
+        if (m == n - 1) qoff[qidx[m] + flag[m]] = n;
+    }
+}
+
+__global__ void k_fill_i32(int* p, long long n, int v) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// the claim list's segments for nq departure queues: segment q takes the
+// claims of one eighth of k_decide's tiles (at most one per vehicle; sized for
+// the largest tile) and the departures of queue chunks q, q + kSeg, ...
+int claim_segment(int cap, int nq) {
+    const size_t vseg = ((size_t)(cap + kMaxTile - 1) / kMaxTile + kSeg - 1) / kSeg * kMaxTile;
+    return (int)(vseg + ((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
+}
+
+bool alloc_claims(sim_t* S, int nq) {
+    Scratch& s = S->s;
+    s.cl_seg = claim_segment(S->cap, nq);
+    const size_t ncl = (size_t)kSeg * s.cl_seg;
+    return dalloc(S, s.cl_vid, ncl) && dalloc(S, s.cl_key, ncl) && dalloc(S, s.cl_lo, ncl) &&
+           dalloc(S, s.cl_hi, ncl) && dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) &&
+           dalloc(S, s.cl_tedge, ncl) && dalloc(S, s.cl_cell, ncl) && dalloc(S, s.cl_X, ncl) &&
+           dalloc(S, s.cl_v, ncl) && dalloc(S, s.cl_f, ncl) && dalloc(S, s.mv_claim, ncl) &&
+           dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) && dalloc(S, s.mv_g, ncl);
+}
+
+void free_claims(sim_t* S) {
+    Scratch& s = S->s;
+    dfree(S, s.cl_vid); dfree(S, s.cl_key); dfree(S, s.cl_lo); dfree(S, s.cl_hi); dfree(S, s.cl_src);
+    dfree(S, s.cl_kind); dfree(S, s.cl_tedge); dfree(S, s.cl_cell); dfree(S, s.cl_X); dfree(S, s.cl_v);
+    dfree(S, s.cl_f); dfree(S, s.mv_claim); dfree(S, s.mv_p); dfree(S, s.mv_slot); dfree(S, s.mv_g);
+}
+
+// room for nq departure queues: the queue arrays and the claim segments
+int grow_queues(sim_t* S, int nq) {
+    if (nq <= S->nq_cap) return SIM_OK;
+    const int cap_q = nq + nq / 4;
+    dfree(S, S->tr.qoff);
+    dfree(S, S->tr.qedge);
+    dfree(S, S->tr.qtype);
+    dfree(S, S->qstate);
+    free_claims(S);
+    int *qoff = nullptr, *qedge = nullptr;
+    unsigned char* qtype = nullptr;
+    if (!dalloc(S, qoff, (size_t)cap_q + 1) || !dalloc(S, qedge, (size_t)cap_q) || !dalloc(S, qtype, (size_t)cap_q) ||
+        !dalloc(S, S->qstate, 2 * (size_t)cap_q) || !alloc_claims(S, cap_q))
+        return fail(S, SIM_ENOMEM, "route reload: queue allocation failed");
+    for (auto& ck : S->ckpt_pool) {  // checkpoints kept from an earlier window copy the queues too
+        dfree(S, ck.qstate);
+        if (!dalloc(S, ck.qstate, 2 * (size_t)cap_q)) return fail(S, SIM_ENOMEM, "route reload: queue allocation failed");
+    }
+    S->tr.qoff = qoff;
+    S->tr.qedge = qedge;
+    S->tr.qtype = qtype;
+    S->nq_cap = cap_q;
     return SIM_OK;
 }
 
@@ -842,7 +998,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
               dalloc(S, d_rel, rel_len + 1) &&
               dalloc(S, S->tr.depart_actual, cap) && dalloc(S, S->tr.arrive_step, cap) &&
               dalloc(S, S->tr.fuel_total, cap) && dalloc(S, S->tr.co_total, cap) &&
-              dalloc(S, S->d_vtype, cap) && dalloc(S, d_qoff, (size_t)nq + 1) &&
+              dalloc(S, S->d_vtype, cap) && dalloc(S, S->d_ord, cap) && dalloc(S, S->d_dep, cap) &&
+              dalloc(S, d_qoff, (size_t)nq + 1) &&
               dalloc(S, d_qvid, qmem.size()) && dalloc(S, d_qdep, qmem.size()) && dalloc(S, d_qedge, (size_t)nq) &&
               dalloc(S, d_qtype, (size_t)nq) && dalloc(S, S->qstate, 2 * (size_t)nq);
     for (int b = 0; b < 2 && ok; ++b) {
@@ -851,22 +1008,11 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     }
     ok = ok && dalloc(S, S->tr.rcur, cap) && dalloc(S, S->tr.kin, cap) && dalloc(S, S->tr.phin, cap);
     const size_t ntiles = (size_t)(cap + 1 + kScanTile - 1) / kScanTile + 1;
-    // claim segment q takes the claims of one eighth of k_decide's tiles (at
-    // most one per vehicle; sized for the largest tile) and the departures of
-    // queue chunks q, q + kSeg, ...
-    const size_t vseg = ((size_t)(cap + kMaxTile - 1) / kMaxTile + kSeg - 1) / kSeg * kMaxTile;
-    s.cl_seg = (int)(vseg + ((size_t)(nq + kBlock - 1) / kBlock + kSeg - 1) / kSeg * kBlock);
-    const size_t ncl = (size_t)kSeg * s.cl_seg;
     ok = ok && dalloc(S, s.ccnt, (size_t)3 * kSeg * kSegStride) &&
          dalloc(S, s.sstat, (size_t)kSeg * kStatStride) &&
          dalloc(S, s.xs, cap) && dalloc(S, s.vs, cap) && dalloc(S, s.stay, cap + 1) &&
-         dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && dalloc(S, s.cl_vid, ncl) &&
-         dalloc(S, s.cl_key, ncl) && dalloc(S, s.cl_lo, ncl) && dalloc(S, s.cl_hi, ncl) &&
-         dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) && dalloc(S, s.cl_tedge, ncl) && dalloc(S, s.cl_cell, ncl) &&
-         dalloc(S, s.cl_X, ncl) && dalloc(S, s.cl_v, ncl) && dalloc(S, s.cl_f, ncl) &&
-         dalloc(S, s.mv_claim, ncl) && dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) &&
-         dalloc(S, s.mv_g, ncl) && dalloc(S, s.grp_key, cap) && dalloc(S, s.grp_X, cap) &&
-         dalloc(S, s.tile_status, ntiles);
+         dalloc(S, s.mcnt, cap + 1) && dalloc(S, s.cscan, cap + 1) && alloc_claims(S, nq) &&
+         dalloc(S, s.grp_key, cap) && dalloc(S, s.grp_X, cap) && dalloc(S, s.tile_status, ntiles);
     if (!ok) return fail(S, SIM_ENOMEM, "device allocation failed in sim_load_demand");
     int rc;
     std::vector<int> minus1(cap, -1);
@@ -875,7 +1021,8 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
         (rc = h2d(S, S->d_vtype, vtype.data(), ntrips)) || (rc = h2d(S, d_qoff, qoff.data(), qoff.size())) ||
         (rc = h2d(S, d_qvid, qmem.data(), qmem.size())) || (rc = h2d(S, d_qdep, qdep.data(), qdep.size())) ||
         (rc = h2d(S, d_qedge, qedge.data(), qedge.size())) || (rc = h2d(S, d_qtype, qtype.data(), qtype.size())) ||
-        (rc = h2d(S, S->tr.arrive_step, minus1.data(), cap)))
+        (rc = h2d(S, S->tr.arrive_step, minus1.data(), cap)) || (rc = h2d(S, S->d_ord, ord.data(), ntrips)) ||
+        (rc = h2d(S, S->d_dep, dep.data(), ntrips)))
         return rc;
     std::vector<int> da(cap, init_x ? t0 : -1);
     if ((rc = h2d(S, S->tr.depart_actual, da.data(), cap))) return rc;
@@ -936,6 +1083,10 @@ int sim_load_demand(sim_t* S, int32_t ntrips, const int32_t* depart_step, const 
     S->tr.qhead = S->qstate;
     S->tr.qtail = S->qstate + nq;
     S->h_rbeg = rbeg;
+    S->t_load = t0;
+    S->placed = init_x != nullptr;
+    S->re_cap = nre;
+    S->nq_cap = nq;
     S->grid = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)cap + kBlock - 1) / kBlock));
     S->grid_small = std::max(1, S->grid / 4);
     S->grid_q = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)nq + kBlock - 1) / kBlock));
@@ -1637,6 +1788,144 @@ int sim_load_demand_batch(sim_t* S, int32_t n, const int32_t* num_trips, const i
     }
     return sim_load_demand(S, (int32_t)dep.size(), dep.data(), trt.data(), route_off, rp.data(), re.data(), nullptr,
                            nullptr, nullptr);
+}
+
+int sim_reload_routes(sim_t* S, const int64_t* route_ptr, const int32_t* route_edges, int64_t total_route_edges) {
+    if (!S) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    if (S->placed) return fail(S, SIM_ESTATE, "the demand placed vehicles on the road: no route reload");
+    if (!S->batch_edge_off.empty()) return fail(S, SIM_ESTATE, "no route reload on a batch of scenarios");
+    if (S->tape_on || S->adj_ready) return fail(S, SIM_ESTATE, "no route reload inside a differentiation window");
+    if (!route_ptr || total_route_edges < 0 || (total_route_edges > 0 && !route_edges))
+        return fail(S, SIM_EINVAL, "null or negative route arrays");
+    if (total_route_edges > (long long)INT32_MAX - 2) return fail(S, SIM_EROUTE, "route_edges too long");
+    const int n = S->ntrips;
+    const long long total = total_route_edges;
+    long long last = -1;
+    HIPCHECK(S, hipMemcpyAsync(&last, route_ptr + n, sizeof(long long), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    if (last != total) return fail(S, SIM_EINVAL, "route_ptr[num_trips] differs from total_route_edges");
+    if (!S->d_tail) {
+        if (!dalloc(S, S->d_tail, (size_t)S->ne) || !dalloc(S, S->d_rkey, 2 * (size_t)S->cap) ||
+            !dalloc(S, S->d_rval, 2 * (size_t)S->cap) || !dalloc(S, S->d_rerr, 2))
+            return fail(S, SIM_ENOMEM, "route reload: scratch allocation failed");
+        int rc = h2d(S, S->d_tail, S->tail.data(), (size_t)S->ne);
+        if (rc) return rc;
+    }
+    const dim3 gn((unsigned)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)n + kBlock - 1) / kBlock)));
+    const dim3 b(kBlock);
+    // every route checked before anything changes
+    const int none = INT32_MAX;
+    int bad = INT32_MAX;
+    HIPCHECK(S, hipMemcpyAsync(S->d_rerr, &none, sizeof(int), hipMemcpyHostToDevice, S->stream));
+    if (n > 0)
+        hipLaunchKernelGGL(k_route_check, gn, b, 0, S->stream, route_ptr, route_edges, total, n, S->ne, S->net.head,
+                           S->d_tail, S->d_rerr);
+    HIPCHECK(S, hipGetLastError());
+    HIPCHECK(S, hipMemcpyAsync(&bad, S->d_rerr, sizeof(int), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    if (bad != INT32_MAX)
+        return fail(S, SIM_EROUTE, "route of trip " + std::to_string(bad) + " is empty, out of range or not contiguous");
+
+    // the route table, copied in
+    drop_graphs(S);
+    if (total > S->re_cap) {
+        dfree(S, S->tr.route_edges);
+        int* re = nullptr;
+        if (!dalloc(S, re, (size_t)total)) return fail(S, SIM_ENOMEM, "route reload: route table allocation failed");
+        S->tr.route_edges = re;
+        S->re_cap = total;
+    }
+    int* re = const_cast<int*>(S->tr.route_edges);
+    if (total > 0)
+        HIPCHECK(S, hipMemcpyAsync(re, route_edges, sizeof(int) * (size_t)total, hipMemcpyDeviceToDevice, S->stream));
+    // per vehicle id its route, and the departure queues: trips by (first
+    // link, type), each queue by vehicle id (a stable sort of the ids by key)
+    int* rbeg = const_cast<int*>(S->tr.rbeg);
+    int* rend = const_cast<int*>(S->tr.rend);
+    int* qvid = const_cast<int*>(S->tr.qvid);
+    unsigned* key = S->d_rkey;
+    unsigned* skey = S->d_rkey + S->cap;
+    int* flag = S->d_rval;
+    int* qidx = S->d_rval + S->cap;
+    int nq = 0;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_route_trips, gn, b, 0, S->stream, route_ptr, re, S->d_ord, S->d_vtype, n, rbeg, rend,
+                           key, S->d_rval);
+        HIPCHECK(S, hipGetLastError());
+        unsigned bits = 1;
+        while (bits < 32 && (1ull << bits) < 4ull * (unsigned long long)S->ne) ++bits;
+        size_t b_sort = 0, b_scan = 0;
+        HIPCHECK(S, rocprim::radix_sort_pairs(nullptr, b_sort, key, skey, S->d_rval, qvid, (size_t)n, 0, bits,
+                                              S->stream));
+        HIPCHECK(S, rocprim::exclusive_scan(nullptr, b_scan, flag, qidx, 0, (size_t)n, rocprim::plus<int>(),
+                                            S->stream));
+        const size_t need = std::max(b_sort, b_scan);
+        if (need > S->rtmp_bytes) {
+            dfree(S, S->d_rtmp);
+            void* tmp = raw_alloc(S, need);
+            if (!tmp) return fail(S, SIM_ENOMEM, "route reload: sort scratch allocation failed");
+            S->d_rtmp = tmp;
+            S->rtmp_bytes = need;
+        }
+        size_t bytes = S->rtmp_bytes;
+        HIPCHECK(S, rocprim::radix_sort_pairs(S->d_rtmp, bytes, key, skey, S->d_rval, qvid, (size_t)n, 0, bits,
+                                              S->stream));
+        hipLaunchKernelGGL(k_queue_flags, gn, b, 0, S->stream, skey, n, flag);
+        bytes = S->rtmp_bytes;
+        HIPCHECK(S, rocprim::exclusive_scan(S->d_rtmp, bytes, flag, qidx, 0, (size_t)n, rocprim::plus<int>(),
+                                            S->stream));
+        hipLaunchKernelGGL(k_queue_count, dim3(1), dim3(64), 0, S->stream, flag, qidx, n, S->d_rerr + 1);
+        HIPCHECK(S, hipGetLastError());
+        HIPCHECK(S, hipMemcpyAsync(&nq, S->d_rerr + 1, sizeof(int), hipMemcpyDeviceToHost, S->stream));
+        HIPCHECK(S, hipStreamSynchronize(S->stream));
+        int rc = grow_queues(S, nq);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_queue_build, gn, b, 0, S->stream, skey, qvid, flag, qidx, S->d_dep, n,
+                           const_cast<int*>(S->tr.qoff), const_cast<int*>(S->tr.qedge),
+                           const_cast<unsigned char*>(S->tr.qtype), const_cast<int*>(S->tr.qdep));
+        HIPCHECK(S, hipGetLastError());
+    }
+    S->tr.nq = nq;
+    S->tr.qhead = S->qstate;
+    S->tr.qtail = S->qstate + nq;
+    S->grid_q = (int)std::min<long long>(kMaxGrid, std::max<long long>(1, ((long long)nq + kBlock - 1) / kBlock));
+
+    // the dynamic state back to the demand's first step: no vehicle on the
+    // road, empty queues, statistics and trip outcomes
+    Scratch& s = S->s;
+    const size_t cap = (size_t)S->cap, ne = (size_t)S->ne;
+    const dim3 gc((unsigned)std::min<size_t>(kMaxGrid, (cap + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_fill_i32, gc, b, 0, S->stream, S->tr.depart_actual, (long long)cap, -1);
+    hipLaunchKernelGGL(k_fill_i32, gc, b, 0, S->stream, S->tr.arrive_step, (long long)cap, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::max(1, std::min(kMaxGrid, (S->nn + kBlock - 1) / kBlock))), b, 0,
+                       S->stream, s.holder, (long long)S->nn, -1);
+    HIPCHECK(S, hipGetLastError());
+    HIPCHECK(S, hipMemsetAsync(S->tr.fuel_total, 0, sizeof(float) * cap, S->stream));
+    HIPCHECK(S, hipMemsetAsync(S->tr.co_total, 0, sizeof(float) * cap, S->stream));
+    if (nq) HIPCHECK(S, hipMemsetAsync(S->qstate, 0, sizeof(int) * 2 * (size_t)nq, S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.st_cnt, 0, sizeof(unsigned long long) * ne, S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.st_steps, 0, sizeof(unsigned long long) * ne, S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.st_us, 0, sizeof(unsigned long long) * ne, S->stream));
+    if (s.samp_every > 0) {
+        const size_t ns = (size_t)s.samp_max * ne;
+        HIPCHECK(S, hipMemsetAsync(s.samp_cnt, 0, sizeof(unsigned long long) * ns, S->stream));
+        HIPCHECK(S, hipMemsetAsync(s.samp_spd, 0, sizeof(unsigned long long) * ns, S->stream));
+    }
+    HIPCHECK(S, hipMemsetAsync(s.stay, 0, cap + 1, S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.mcnt, 0, sizeof(int) * (cap + 1), S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.ccnt, 0, sizeof(int) * 3 * kSeg * kSegStride, S->stream));
+    HIPCHECK(S, hipMemsetAsync(s.sstat, 0, sizeof(unsigned long long) * kSeg * kStatStride, S->stream));
+    Counters c0{};
+    c0.t = (int)S->t_load;
+    HIPCHECK(S, hipMemcpyAsync(S->ctr, &c0, sizeof(Counters), hipMemcpyHostToDevice, S->stream));
+    S->host_t = S->t_load;
+    int rc = reindex(S, S->buf[S->host_t & 1], S->s, S->ctr);
+    if (rc) return rc;
+    if (n > 0) HIPCHECK(S, hipMemcpyAsync(S->h_rbeg.data(), rbeg, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost,
+                                          S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
 }
 
 int sim_set_launch(sim_t* S, int32_t grid, int32_t grid_small) {

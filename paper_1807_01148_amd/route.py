@@ -6,8 +6,8 @@ link weights and the current routes on the GPU.  ``reroute(scen, masks)``
 runs the loop of Sec. 6.3.1: plan every route on the initial estimates,
 simulate, replace the estimates by the measured link times, plan again for
 the trips selected by ``masks[k]`` (all, all, half, a quarter), simulate
-again.  Routing, weights and simulation run in the library's kernels; the
-loop only moves routes from the router into a new simulation.
+again.  Routing, weights and simulation run in the library's kernels, and
+the routes pass from the router to the simulation on the device.
 """
 from __future__ import annotations
 
@@ -41,6 +41,8 @@ def _bind(lib):
     lib.rt_plan.restype = ctypes.c_int
     lib.rt_read_routes.argtypes = [P, P, P]
     lib.rt_read_routes.restype = ctypes.c_int
+    lib.rt_route_views.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
+    lib.rt_route_views.restype = ctypes.c_int
     lib.rt_tree.argtypes = [P, i32, P, P]
     lib.rt_tree.restype = ctypes.c_int
     lib.rt_tree_static.argtypes = [P, i32, P, P]
@@ -144,6 +146,14 @@ class Router:
         self._check(self.lib.rt_read_routes(self.h, _p(ptr), _p(edges)))
         return ptr, edges[:self.total]
 
+    def route_views(self):
+        """rt_route_views: DEVICE addresses of the current route table
+        (route_ptr int64 [num_trips + 1], route_edges int32) and its length;
+        valid until the next plan."""
+        pa, ea, tot = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64(0)
+        self._check(self.lib.rt_route_views(self.h, ctypes.byref(pa), ctypes.byref(ea), ctypes.byref(tot)))
+        return int(pa.value or 0), int(ea.value or 0), int(tot.value)
+
     def tree(self, src_node: int):
         dist = np.empty(self.num_nodes, np.int64)
         pred = np.empty(self.num_nodes, np.int32)
@@ -188,18 +198,31 @@ def with_routes(scen, route_ptr, route_edges):
     return out
 
 
-def reroute(scen, masks, iterations: int = 4, device: int = 0, on_iteration=None):
+def reroute(scen, masks, iterations: int = 4, device: int = 0, on_iteration=None, handoff: str = "device"):
     """The loop of Sec. 6.3.1 on the GPU.  Returns one dict per iteration
-    with the weights used, the routes, the link statistics and counters."""
+    with the weights used, the link statistics and counters, and with
+    handoff="host" the routes.  handoff="device": one simulation, its routes
+    replaced on the device from the router's table each iteration (the demand
+    starts again from its first step); "host": the routes are read out and a
+    new simulation is loaded with them."""
+    if handoff not in ("device", "host"):
+        raise ValueError("handoff is 'device' or 'host'")
     d = scen["demand"]
     rt = Router(scen["net"], device)
     rt.set_trips(d["src_nodes"], d["trip_src"], d["trip_dst"])
     out = []
+    sim = None
     for k in range(iterations):
         w = rt.weights()
         rt.plan(None if k == 0 else masks[k])
-        ptr, edges = rt.routes()
-        sim = Sim(with_routes(scen, ptr, edges), device)
+        ptr = edges = None
+        if handoff == "device":
+            if sim is None:
+                sim = Sim(scen, device)
+            sim.reload_routes(*rt.route_views())
+        else:
+            ptr, edges = rt.routes()
+            sim = Sim(with_routes(scen, ptr, edges), device)
         sim.step(scen["steps"])
         st = sim.edge_stats_device()
         rt.weights_from_stats(st["count"], st["tt_us"])
@@ -208,6 +231,9 @@ def reroute(scen, masks, iterations: int = 4, device: int = 0, on_iteration=None
         if on_iteration:
             on_iteration(k, res, rt, sim)
         out.append(res)
+        if handoff == "host":
+            sim.close()
+    if sim is not None and handoff == "device":
         sim.close()
     rt.close()
     return out

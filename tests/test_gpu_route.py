@@ -9,7 +9,12 @@ rule (lowest tight edge into every node) makes every route unique:
   * planned routes equal the oracle's for full and partial plans, for any
     number of origins searched at once;
   * the whole loop (plan, simulate, measured weights, partial re-plans) equals
-    the oracle's loop on the 10x10 grid, iteration by iteration;
+    the oracle's loop on the 10x10 grid, iteration by iteration, with the
+    routes handed to the simulation on the device (sim_reload_routes) and
+    through the host;
+  * a route reload equals a new simulation loaded with the same routes, also
+    when the new first links need more departure queues than there were;
+    a bad route is refused and changes nothing;
   * error codes for unreachable destinations and bad calls.
 """
 import numpy as np
@@ -98,11 +103,19 @@ def test_full_and_partial_plans_equal_the_oracle(batch):
     assert nsrc == np.unique(d["trip_src"][mask]).size and relax >= nsrc
 
 
-def test_reroute_loop_equals_the_oracle_loop():
+def keep_routes(k, res, rt, sim):
+    """reroute callback: the router's routes of the iteration, read for the
+    comparison only (the loop itself hands them over as it was told)."""
+    if res["route_ptr"] is None:
+        res["route_ptr"], res["route_edges"] = rt.routes()
+
+
+@pytest.mark.parametrize("handoff", ["device", "host"])
+def test_reroute_loop_equals_the_oracle_loop(handoff):
     from paper_1807_01148_amd.route import reroute
     scen = S.small_grid(n_trips=2000, steps=3600)
     masks = S.reroute_masks(5, 2000)
-    g = reroute(scen, masks)
+    g = reroute(scen, masks, on_iteration=keep_routes, handoff=handoff)
     o = R.reroute(scen, masks)
     for k, (a, b) in enumerate(zip(g, o)):
         assert np.array_equal(a["weights"], b["weights"]), k
@@ -117,10 +130,109 @@ def test_diamond_loop_equals_the_oracle_loop():
     from paper_1807_01148_amd.route import reroute
     scen = diamond()
     masks = S.reroute_masks(1, 300)
-    g, o = reroute(scen, masks), R.reroute(scen, masks)
+    g, o = reroute(scen, masks, on_iteration=keep_routes), R.reroute(scen, masks)
     for a, b in zip(g, o):
         assert np.array_equal(a["route_edges"], b["route_edges"])
         assert np.array_equal(a["weights"], b["weights"])
+
+
+def same_run(a, b):
+    assert a.counters() == b.counters()
+    for key, v in b.edge_stats().items():
+        assert np.array_equal(a.edge_stats()[key], v), key
+    for key, v in b.trips().items():
+        assert np.array_equal(a.trips()[key], v), key
+    for key, v in b.vehicles().items():
+        assert np.array_equal(a.vehicles()[key], v), key
+    for key, v in b.emissions().items():
+        assert np.array_equal(a.emissions()[key], v), key
+
+
+def device_routes(ptr, edges):
+    import torch
+    return (torch.from_numpy(np.asarray(ptr, np.int64)).cuda(), torch.from_numpy(np.asarray(edges, np.int32)).cuda())
+
+
+@pytest.mark.parametrize("one_route", [False, True])
+def test_route_reload_equals_a_new_simulation(one_route):
+    """A simulation part-way through its run takes the router's routes on the
+    device and starts again; it then runs exactly as a new simulation loaded
+    with those routes through the host.  With one_route, the first load gives
+    every trip the same route (one departure queue per type), so the reload
+    must make room for many more queues."""
+    import paper_1807_01148_amd as P
+    from paper_1807_01148_amd.route import with_routes
+    scen = S.small_grid(n_trips=2000, steps=3600)
+    net, d = scen["net"], scen["demand"]
+    rng = np.random.default_rng(5)
+    first = scen
+    if one_route:
+        r0 = d["route_edges"][d["route_ptr"][d["trip_route"][0]]:d["route_ptr"][d["trip_route"][0] + 1]]
+        n = d["depart_step"].size
+        first = with_routes(scen, np.arange(n + 1, dtype=np.int64) * r0.size, np.tile(r0, n))
+    a = P.Sim(first)
+    a.step(700)
+    rt = router(net)
+    rt.set_weights(rng.integers(5000, 20000, net["col_idx"].size).astype(np.int64))
+    rt.set_trips(d["src_nodes"], d["trip_src"], d["trip_dst"])
+    rt.plan()
+    a.reload_routes(*rt.route_views())
+    ptr, edges = rt.routes()
+    b = P.Sim(with_routes(scen, ptr, edges))
+    same_run(a, b)
+    for steps in (1, 899, 2700):
+        a.step(steps)
+        b.step(steps)
+        same_run(a, b)
+    # a second reload from tensors, with other routes
+    rt.set_weights(rng.integers(5000, 20000, net["col_idx"].size).astype(np.int64))
+    rt.plan()
+    ptr2, edges2 = rt.routes()
+    a.reload_routes(*device_routes(ptr2, edges2))
+    c = P.Sim(with_routes(scen, ptr2, edges2))
+    a.step(3600)
+    c.step(3600)
+    same_run(a, c)
+
+
+def test_route_reload_refuses_a_bad_route_and_changes_nothing():
+    import paper_1807_01148_amd as P
+    scen = S.small_grid(n_trips=2000, steps=3600)
+    d = scen["demand"]
+    a, b = P.Sim(scen), P.Sim(scen)
+    a.step(500)
+    b.step(500)
+    rp = d["route_ptr"][d["trip_route"]]
+    ptr = np.concatenate([[0], np.cumsum(d["route_ptr"][d["trip_route"] + 1] - rp)]).astype(np.int64)
+    edges = np.concatenate([d["route_edges"][s:e] for s, e in zip(rp, d["route_ptr"][d["trip_route"] + 1])])
+    long_route = int(np.argmax(np.diff(ptr)))
+    assert ptr[long_route + 1] - ptr[long_route] >= 3
+    bad = edges.copy()
+    bad[ptr[long_route] + 1] = bad[ptr[long_route] + 2]  # two edges that do not meet
+    with pytest.raises(P.SimError) as e:
+        a.reload_routes(*device_routes(ptr, bad))
+    assert e.value.code == P.SIM_EROUTE and "trip %d" % long_route in str(e.value)
+    bad = edges.copy()
+    bad[0] = scen["net"]["col_idx"].size  # an edge id out of range
+    with pytest.raises(P.SimError) as e:
+        a.reload_routes(*device_routes(ptr, bad))
+    assert e.value.code == P.SIM_EROUTE
+    pt, et = device_routes(ptr, edges)
+    with pytest.raises(P.SimError) as e:  # a table length that route_ptr does not end at
+        a.reload_routes(pt.data_ptr(), et.data_ptr(), total=et.numel() - 1)
+    assert e.value.code == P.SIM_EINVAL
+    with pytest.raises(ValueError):  # one trip short
+        a.reload_routes(*device_routes(ptr[:-1], edges))
+    same_run(a, b)
+    a.step(700)
+    b.step(700)
+    same_run(a, b)
+    # the same routes, reloaded: the run from the first step again
+    a.reload_routes(*device_routes(ptr, edges))
+    c = P.Sim(scen)
+    a.step(1200)
+    c.step(1200)
+    same_run(a, c)
 
 
 def test_metro_trees_from_sampled_origins():
