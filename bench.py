@@ -524,6 +524,8 @@ def main():
                     help="skip the adjoint and ensemble speed-ups that follow the plain-step measurement")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--chunk", type=int, default=60, help="steps per captured HIP graph")
+    ap.add_argument("--launch", default="",
+                    help="launch shape GRID,SMALL_GRID,DECIDE_BLOCK,DECIDE_PER_THREAD instead of the tuned one")
     ap.add_argument("--tune-at", type=int, default=0,
                     help="simulate to this step, autotune the launch shape there, store it in the cache, exit")
     ap.add_argument("--mode", default="plain", choices=["plain", "ensemble", "adjoint", "reroute", "copycal"],
@@ -579,14 +581,19 @@ def main():
         print(json.dumps(res), flush=True)
         return
     shape = "default"
-    try:
-        with open(cache) as f:
-            hit = json.load(f).get("%s|%s" % (E.device_key(0), args.workload))
-        if hit:
-            E.apply_shape(sim, hit)
-            shape = "autotuned"
-    except (OSError, ValueError):
-        pass
+    if args.launch:
+        g, gs, db, dr = (int(v) for v in args.launch.split(","))
+        E.apply_shape(sim, {"grid": g, "grid_small": gs, "decide_block": db, "decide_per_thread": dr})
+        shape = "given"
+    else:
+        try:
+            with open(cache) as f:
+                hit = json.load(f).get("%s|%s" % (E.device_key(0), args.workload))
+            if hit:
+                E.apply_shape(sim, hit)
+                shape = "autotuned"
+        except (OSError, ValueError):
+            pass
     launch = E.get_launch(sim) + E.get_decide_shape(sim)
     log("[bench] launch shape %s: grid %d, small grid %d, decide blocks of %d x %d entries"
         % (shape, launch[0], launch[1], launch[2], launch[3]))
