@@ -380,8 +380,9 @@ int sim_step_graph(sim_t* sim, int32_t num_steps, int32_t chunk);
 int sim_step_persistent(sim_t* sim, int32_t num_steps);
 
 /* Time `steps_per_trial` steps for each candidate launch shape, all from the
- * current state (every candidate twice): grid counts and the scan's share of
- * them, then every decide shape with the best grid, half and twice it.  Then
+ * current state (every candidate twice): grid counts with the scan's blocks a
+ * share of them (1/2, 1/4, 1/8) or 128 or 256, then every decide shape with
+ * the best grid, half and twice it.  Then
  * restore that state (vehicles, counters, statistics, per-trip outcomes, the
  * sampler setting) and keep the fastest shape (read the decide shape with
  * sim_get_decide_shape).  Outputs the grids and the time per step (ms).  The

@@ -10,7 +10,7 @@ namespace tsim {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
-constexpr int kScanItems = 16;
+constexpr int kScanItems = 32;
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kLcNone = -(1 << 30);
 constexpr int kMaxGrid = 2048;

@@ -715,11 +715,19 @@ __device__ __forceinline__ void scan_body(const Scratch& s, Counters* ctr) {
         unsigned stays = 0;  // bit q: entry base + q stays
         int tsum = 0;
         if (base + kScanItems <= total) {
-            // a whole run of 16: four 16-byte loads of the counts and one of the
-            // stay flags (stay[N] is 0)
+            // a whole run: 16-byte loads of the counts and of the stay flags
+            // (stay[N] is 0)
+            static_assert(kScanItems % 16 == 0 && kScanItems <= 32, "a run is whole 16-byte words of flags");
             const int4* m4 = reinterpret_cast<const int4*>(s.mcnt + base);
-            const uint4 st = *reinterpret_cast<const uint4*>(s.stay + base);
-            const unsigned sw[4] = {st.x, st.y, st.z, st.w};
+            unsigned sw[kScanItems / 4];
+#pragma unroll
+            for (int u = 0; u < kScanItems / 16; ++u) {
+                const uint4 st = reinterpret_cast<const uint4*>(s.stay + base)[u];
+                sw[4 * u] = st.x;
+                sw[4 * u + 1] = st.y;
+                sw[4 * u + 2] = st.z;
+                sw[4 * u + 3] = st.w;
+            }
 #pragma unroll
             for (int h = 0; h < kScanItems / 4; ++h) {
                 const int4 m = m4[h];

@@ -2165,12 +2165,17 @@ int sim_autotune(sim_t* S, int32_t steps_per_trial, int32_t* best_grid, int32_t*
     // shape's time is the faster of its trials
     const int g0 = S->grid;
     const int gcand[] = {g0 / 4, g0 / 2, g0 * 3 / 4, g0, g0 * 3 / 2, g0 * 2};
-    const int scand[] = {2, 4, 8};
     for (int pass = 0; pass < 2; ++pass)
         for (int gc : gcand) {
             if (gc < 1) continue;
-            for (int sd : scand) {
-                const int gs = std::max(1, gc / sd);
+            // the scan's blocks: a share of the grid, or a fixed few (its
+            // tiles are taken from a counter, and fewer blocks contend less)
+            int scand[5] = {gc / 2, gc / 4, gc / 8, 128, 256};
+            for (int c = 0; c < 5; ++c) {
+                const int gs = std::max(1, std::min(gc, scand[c]));
+                bool seen = false;
+                for (int c2 = 0; c2 < c; ++c2) seen |= std::max(1, std::min(gc, scand[c2])) == gs;
+                if (seen) continue;
                 float ms = 0.0f;
                 if ((rc = trial(gc, gs, bd, &ms))) return finish(rc);
                 if (ms < best) {
