@@ -42,10 +42,16 @@ def build(force: bool = False):
     return outs
 
 
+def _path(key, default):
+    """The library to load: a sanitizer build named by ORACLE_LIB_<KEY> (the
+    sanitizer test's child process), else the one build() writes."""
+    return os.environ.get("ORACLE_LIB_" + key, os.path.join(_HERE, default))
+
+
 def _adjlib():
     if "adj" not in _LIBS:
         build()
-        lib = ctypes.CDLL(os.path.join(_HERE, "libadjoint.so"))
+        lib = ctypes.CDLL(_path("ADJ", "libadjoint.so"))
         P = ctypes.c_void_p
         lib.adj_eval.argtypes = [ctypes.c_int64] + [P] * 8 + [ctypes.c_int32, ctypes.c_int32, P, P, P,
                                                             ctypes.c_int32] + [P] * 9 + [ctypes.c_int32] * 2 + [P] * 2
@@ -57,7 +63,7 @@ def _adjlib():
 def _lib(prec):
     if prec not in _LIBS:
         build()
-        lib = ctypes.CDLL(os.path.join(_HERE, "liboracle_%s.so" % prec))
+        lib = ctypes.CDLL(_path(prec.upper(), "liboracle_%s.so" % prec))
         P = ctypes.c_void_p
         i32 = ctypes.c_int32
         lib.or_create.argtypes = [i32, i32, P, P, P, P, P, P, i32, P, P, i32, P]

@@ -37,7 +37,7 @@ def _lib():
     global _LIB
     if _LIB is None:
         build()
-        lib = ctypes.CDLL(os.path.join(_HERE, "liboracle_route.so"))
+        lib = ctypes.CDLL(os.environ.get("ORACLE_LIB_ROUTE", os.path.join(_HERE, "liboracle_route.so")))
         P, i32 = ctypes.c_void_p, ctypes.c_int32
         lib.or_sssp.argtypes = [i32, i32, P, P, P, i32, P, P]
         lib.or_sssp.restype = ctypes.c_int
