@@ -632,6 +632,11 @@ def main():
     if args.warmup > 0:
         E.step_graph(sim, args.warmup, args.chunk)
         sim.load_state(img)
+    if args.chunk > 0 and args.steps >= args.chunk:
+        # the window replays graphs of `chunk` steps: capture them here, untimed
+        # (two chunks, for both step parities), then start again from the window
+        E.step_graph(sim, 2 * args.chunk, args.chunk)
+        sim.load_state(img)
     torch.cuda.synchronize()
     c0 = sim.counters()
     log("[bench] at step %d: en_route %d waiting %d" % (c0["step"], c0["en_route"], c0["waiting"]))
