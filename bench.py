@@ -632,10 +632,12 @@ def main():
     if args.warmup > 0:
         E.step_graph(sim, args.warmup, args.chunk)
         sim.load_state(img)
-    if args.chunk > 0 and args.steps >= args.chunk:
-        # the window replays graphs of `chunk` steps: capture them here, untimed
-        # (two chunks, for both step parities), then start again from the window
-        E.step_graph(sim, 2 * args.chunk, args.chunk)
+    # the window replays graphs of `wchunk` steps (a shorter window is one
+    # graph): capture them here, untimed (two chunks, for both step parities),
+    # then start again from the window
+    wchunk = max(1, min(args.chunk, args.steps))
+    if wchunk >= 2:
+        E.step_graph(sim, 2 * wchunk, wchunk)
         sim.load_state(img)
     torch.cuda.synchronize()
     c0 = sim.counters()
@@ -649,7 +651,7 @@ def main():
     done = 0
     while done < args.steps:
         n = min(chunk, args.steps - done)
-        E.step_graph(sim, n, args.chunk)
+        E.step_graph(sim, n, wchunk)
         done += n
         if done < args.steps:
             log("[bench] enqueued %d / %d steps" % (done, args.steps))
@@ -735,7 +737,7 @@ def main():
         "kernel_replay_identical": replay_same,
         "run_to_window": approach,
         "launch": {"grid": launch[0], "grid_small": launch[1], "decide_block": launch[2],
-                   "decide_per_thread": launch[3], "shape": shape, "graph_chunk": args.chunk},
+                   "decide_per_thread": launch[3], "shape": shape, "graph_chunk": wchunk},
     }
     sim.close()
     del sim

@@ -57,51 +57,51 @@ struct Own {
     Lead L;
 };
 
-// The claims of a tile's vehicles (crossings and lane changes, at most one per
-// vehicle), gathered in LDS while the tile is decided and issued together
-// after it: the chain of a claim (its link's claim record, the cell atomics,
-// the list slot) is waited for once per tile instead of once for every pass
-// of a wave that holds a claiming vehicle.
+// The claims of a block's vehicles (crossings and lane changes, at most one per
+// vehicle), gathered in LDS while its tiles are decided and issued together
+// when the stage is more than half full and after the block's last tile: the
+// chain of a claim (its link's claim record, the cell atomics, the list slot)
+// is waited for once every few tiles instead of once for every pass of a wave
+// that holds a claiming vehicle.  NT is twice the tile, so a tile's claims
+// always fit.
 template <int NT>
 struct ClaimStage {
     int n;
     int i[NT];      // entry of the claiming vehicle
-    int vid[NT];
     int tedge[NT];  // target link
-    int lb[NT];     // its first global lane
     int pk[NT];     // target lane | kind << 8 | type << 16
     float X[NT], v[NT], f[NT];
 };
 
 template <class StageT>
-__device__ __forceinline__ void stage_claim(StageT& CS, int i, int vid, int tedge, int lb, int tlane, int kind,
-                                            int ty, float X, float v, float f) {
+__device__ __forceinline__ void stage_claim(StageT& CS, int i, int tedge, int tlane, int kind, int ty, float X, float v,
+                                            float f) {
     const int m = atomicAdd(&CS.n, 1);
     CS.i[m] = i;
-    CS.vid[m] = vid;
     CS.tedge[m] = tedge;
-    CS.lb[m] = lb;
     CS.pk[m] = tlane | (kind << 8) | (ty << 16);
     CS.X[m] = X;
     CS.v[m] = v;
     CS.f[m] = f;
 }
 
-// issues the staged claims of a tile (after a barrier that follows the last
-// stage_claim): their cells, then their slots in segment seg of the list
+// issues the staged claims (after a barrier that follows the last
+// stage_claim): their cells, then their slots in segment seg of the list; the
+// claimant's id and the target link's first lane are read here
 template <int BS, class StageT>
-__device__ __forceinline__ void issue_claims(const Params& P, const Net& net, const Scratch& s, StageT& CS, int seg,
-                                             unsigned long long tag) {
+__device__ __forceinline__ void issue_claims(const Params& P, const Net& net, const Veh& in, const Scratch& s,
+                                             StageT& CS, int seg, unsigned long long tag) {
     const int M = CS.n;
     for (int m = threadIdx.x; m < M; m += BS) {
         const int te = CS.tedge[m];
         const int pk = CS.pk[m];
         const float X = CS.X[m];
+        const int i = CS.i[m];
         const ClaimRec C = net.cr[te];
+        const int lb = net.lane_base[te], vid = in.vid[i];
         int lo, hi;
         claim_cells(P, C.ncell, pk >> 16, X, lo, hi);
-        push_claim(s, C, CS.lb[m], seg, tag, CS.vid[m], (pk >> 8) & 0xFF, CS.i[m], te, pk & 0xFF, X, CS.v[m],
-                   CS.f[m], lo, hi);
+        push_claim(s, C, lb, seg, tag, vid, (pk >> 8) & 0xFF, i, te, pk & 0xFF, X, CS.v[m], CS.f[m], lo, hi);
     }
 }
 
@@ -218,7 +218,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         s.xs[i] = len;  // outcome if the claim is lost: wait at the link end
         s.vs[i] = 0.0f;
         s.stay[i] = 1;
-        stage_claim(CS, i, vid, nx, E2.lane_base, tl, kCross, ty, X, vn, f);
+        stage_claim(CS, i, nx, tl, kCross, ty, X, vn, f);
         return false;
     }
     s.xs[i] = xs;
@@ -405,7 +405,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
             tp.cflags[i] = (unsigned short)best_fl;
             tp.clead[i] = best_lead;
         }
-        stage_claim(CS, i, vid, e, lb, best, kChange, ty, best_X, best_v, 0.0f);
+        stage_claim(CS, i, e, best, kChange, ty, best_X, best_v, 0.0f);
         return true;
     }
     return false;
@@ -479,7 +479,7 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
         return;
     }
     __shared__ Tile<kTile + 2> T;
-    __shared__ ClaimStage<kTile> CS;
+    __shared__ ClaimStage<2 * kTile> CS;
     // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
     // the q-th eighth of the sorted entries, tiles in order, so that the link
     // and lane records of neighbouring vehicles are shared in that XCD's L2;
@@ -494,6 +494,7 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
     // that a block that meets fast tiles takes more of them
     __shared__ int s_c;
     const int c_beg = (int)(((long long)nch * q) / kSeg);
+    if (threadIdx.x == 0) CS.n = 0;
     for (;;) {
         __syncthreads();  // s_c is read
         if (threadIdx.x == 0) s_c = c_beg + atomicAdd(s.tcnt + q * kSegStride, 1);
@@ -539,7 +540,6 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
             T.x[kTile + 1] = has ? in.x[j] : 0.0f;
             T.v[kTile + 1] = has ? in.v[j] : 0.0f;
             T.ty[kTile + 1] = has ? (int)in.ty[j] : 0;
-            CS.n = 0;
         }
         __syncthreads();
 #pragma unroll
@@ -556,9 +556,13 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
             }
         }
         __syncthreads();  // every claim of the tile is staged
-        issue_claims<BS>(P, net, s, CS, q, tag);
-        __syncthreads();  // the tile and the staged claims are overwritten next
+        if (CS.n > kTile) {  // room for the next tile's claims: issue what is staged
+            issue_claims<BS>(P, net, in, s, CS, q, tag);
+            __syncthreads();
+            if (threadIdx.x == 0) CS.n = 0;
+        }
     }
+    if (CS.n > 0) issue_claims<BS>(P, net, in, s, CS, q, tag);
     if (vb == 0 && threadIdx.x == 0) s.stay[N] = 0;
     unsigned long long cw = wave_sum_u64((unsigned long long)clamps);
     unsigned long long aw = wave_sum_u64((unsigned long long)arrivals);
