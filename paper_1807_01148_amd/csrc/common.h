@@ -223,6 +223,10 @@ struct Scratch {
     int* mvcnt;  // segment counters, kSegStride ints apart
     int* tcnt;   // per segment, k_decide's next tile (kSegStride ints apart; cleared by k_resolve)
     int* mv_claim;
+    int* mv_src;  // the claim's source entry (departures: -2 - queue) and vehicle id
+    int* mv_vid;
+    int* mv_rc;   // crossings and departures: the route cursor and next link after the move
+    int* mv_nx;
     int* mv_p;
     int* mv_slot;
     int* mv_g;

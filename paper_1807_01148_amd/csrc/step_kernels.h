@@ -617,6 +617,10 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
         const int sx = src >= 0 ? src : 0;
         const int se = in.edge[sx], skin = tr.kin[vid];
         const float sphin = tr.phin[vid];
+        // a crossing's or departure's place in its route after the move
+        const int rc = kind == kCross ? tr.rcur[vid] + 1 : tr.rbeg[vid];
+        const int rend = tr.rend[vid];
+        const int nn = (kind != kChange && rc + 1 < rend) ? tr.route_edges[rc + 1] : -1;
         // ownership of every claimed cell (all read at once: no early exit)
         const unsigned long long* cell = s.cells + cb;
         const unsigned long long mine = tag | (unsigned)vid;
@@ -630,6 +634,10 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
             if (src >= 0) s.stay[src] = 0;
             const int m = seg * s.cl_seg + wave_slot(s.mvcnt + seg * kSegStride);
             s.mv_claim[m] = ci;
+            s.mv_src[m] = src;
+            s.mv_vid[m] = vid;
+            s.mv_rc[m] = rc;
+            s.mv_nx[m] = nn;
             // its gap in the sorted order: inside its lane's run if the lane is
             // occupied, else before the first entry of a later lane
             const int p = occ ? lb_x(in.x, lo, hi + 1, cX) : lb_key(in.key, kb0, kb1, key);
@@ -900,27 +908,24 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
     const int nb = nblk / kSeg;
     for (int jm = (bid / kSeg) * kBlock + threadIdx.x; jm < M; jm += nb * kBlock) {
         const int m = seg * s.cl_seg + jm;
+        // reads in two rounds, each issued before any branch: the mover's
+        // record (written by k_resolve); its claim, gap, source vehicle and type
         const int ci = s.mv_claim[m];
         const int p = s.mv_p[m];
         const int g = s.mv_g[m];
-        // reads in three dependent rounds, each issued before any branch: the
-        // claim and its gap; the source vehicle's fields and the trip's; the
-        // route's next link
+        const int src = s.mv_src[m], vid = s.mv_vid[m], rc = s.mv_rc[m], nn = s.mv_nx[m];
         const int cp = s.cscan[p];
-        const int b = (cp ^ (cp >> 31)) - g;
         const int key = s.cl_key[ci];
         const float X = s.cl_X[ci];
         const int kind = s.cl_kind[ci];
-        const int src = s.cl_src[ci];
-        const int vid = s.cl_vid[ci];
         const float cv = s.cl_v[ci];
         const int cedge = s.cl_tedge[ci];
         const float cf = s.cl_f[ci];
         const int sx = src >= 0 ? src : 0;
         const float sfu = in.fuel[sx], sco = in.co[sx], sv = in.v[sx];
         const int snext = in.next[sx], slc = in.lc[sx];
-        const int srcur = tr.rcur[vid];
-        const int vty = tr.vtype[vid], rend = tr.rend[vid], rbeg = tr.rbeg[vid];
+        const int vty = tr.vtype[vid];
+        const int b = (cp ^ (cp >> 31)) - g;
         int r = 0;
         if (g > 1) {
             for (int q = 0; q < g; ++q) {
@@ -949,8 +954,7 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
             out.next[j] = snext;
             out.lc[j] = t;
         } else {  // a crossing enters the next link of its route, a departure the first
-            const int rc = kind == kCross ? srcur + 1 : rbeg;
-            out.next[j] = (rc + 1 < rend) ? tr.route_edges[rc + 1] : -1;
+            out.next[j] = nn;
             out.lc[j] = kind == kCross ? slc : lc_none;
             tr.rcur[vid] = rc;
             tr.kin[vid] = t + 1;

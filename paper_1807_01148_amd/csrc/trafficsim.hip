@@ -623,7 +623,8 @@ bool alloc_claims(sim_t* S, int nq) {
            dalloc(S, s.cl_hi, ncl) && dalloc(S, s.cl_src, ncl) && dalloc(S, s.cl_kind, ncl) &&
            dalloc(S, s.cl_tedge, ncl) && dalloc(S, s.cl_cell, ncl) && dalloc(S, s.cl_X, ncl) &&
            dalloc(S, s.cl_v, ncl) && dalloc(S, s.cl_f, ncl) && dalloc(S, s.mv_claim, ncl) &&
-           dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) && dalloc(S, s.mv_g, ncl);
+           dalloc(S, s.mv_p, ncl) && dalloc(S, s.mv_slot, ncl) && dalloc(S, s.mv_g, ncl) &&
+           dalloc(S, s.mv_src, ncl) && dalloc(S, s.mv_vid, ncl) && dalloc(S, s.mv_rc, ncl) && dalloc(S, s.mv_nx, ncl);
 }
 
 void free_claims(sim_t* S) {
@@ -631,6 +632,7 @@ void free_claims(sim_t* S) {
     dfree(S, s.cl_vid); dfree(S, s.cl_key); dfree(S, s.cl_lo); dfree(S, s.cl_hi); dfree(S, s.cl_src);
     dfree(S, s.cl_kind); dfree(S, s.cl_tedge); dfree(S, s.cl_cell); dfree(S, s.cl_X); dfree(S, s.cl_v);
     dfree(S, s.cl_f); dfree(S, s.mv_claim); dfree(S, s.mv_p); dfree(S, s.mv_slot); dfree(S, s.mv_g);
+    dfree(S, s.mv_src); dfree(S, s.mv_vid); dfree(S, s.mv_rc); dfree(S, s.mv_nx);
 }
 
 // room for nq departure queues: the queue arrays and the claim segments
