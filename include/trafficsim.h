@@ -280,11 +280,48 @@ int sim_get_state(sim_t* sim, sim_state_view* out, void* image);
 /* Replace the dynamic state by an image (DEVICE, `bytes` bytes) written by
  * sim_get_state of this handle or of another one created with the same
  * network, parameters, vehicle types and demand; the simulation continues from
- * the image's step exactly as the one that wrote it would.  Synchronises.
- * Errors: SIM_EINVAL (null, wrong size or an image of a different
- * simulation), SIM_ESTATE (no demand, or inside a differentiation window),
- * SIM_EHIP. */
+ * the image's step exactly as the one that wrote it would.  The image is
+ * validated first, on the device, against every class of sim_check_state; an
+ * image that fails is refused with nothing copied (sim_last_error names the
+ * first failing class, its count and its lowest entry).  Synchronises.
+ * Errors: SIM_EINVAL (null, wrong size, an image of a different simulation,
+ * or one that fails validation), SIM_ESTATE (no demand, or inside a
+ * differentiation window), SIM_ENOMEM, SIM_EHIP. */
 int sim_set_state(sim_t* sim, const void* image, size_t bytes);
+
+/* Classes of violations that sim_check_state counts: what the step kernels
+ * assume of a state, since they index link, lane, route, trip and queue
+ * arrays with its values and take the vehicles of a lane as consecutive
+ * entries ordered by position (Sec. 6.3.3, the per-lane order of vehicles). */
+enum sim_check_class {
+    SIM_CHECK_COUNT = 0, /* vehicle count outside [0, capacity], or a negative step */
+    SIM_CHECK_KEY,       /* lane key outside [0, total lanes) */
+    SIM_CHECK_EDGE,      /* link out of range, or the lane key not one of its lanes */
+    SIM_CHECK_ORDER,     /* entries not ordered by (lane key, position) */
+    SIM_CHECK_POSITION,  /* position not finite, or negative */
+    SIM_CHECK_SPEED,     /* speed not finite, or negative */
+    SIM_CHECK_VID,       /* vehicle id outside [0, trips) */
+    SIM_CHECK_DUPLICATE, /* a vehicle id on the road twice */
+    SIM_CHECK_TYPE,      /* vehicle type out of range, or not its trip's type */
+    SIM_CHECK_ROUTE,     /* route cursor outside the trip's route, or the route's link there not the vehicle's */
+    SIM_CHECK_NEXT,      /* next link not the route's next one (-1 after the last) */
+    SIM_CHECK_VALUE,     /* link-entry fraction outside [0, 1], or fuel or CO not finite */
+    SIM_CHECK_ARRIVED,   /* a vehicle on the road whose trip already has an arrival step */
+    SIM_CHECK_QUEUE,     /* a departure queue's head past its tail, or its tail past its trips */
+    SIM_CHECK_HOLDER,    /* a stop node's holder neither -1 nor a vehicle id */
+    SIM_CHECK_CLASSES
+};
+
+/* Check the current state against every class above (one device pass over
+ * the vehicles on the road, the departure queues and the stop nodes; each
+ * index is tested before it is used).
+ *   counts [SIM_CHECK_CLASSES]  HOST int64 out: violations per class (all 0: valid)
+ *   first  [SIM_CHECK_CLASSES]  HOST int32 out, may be NULL: lowest offending
+ *                               entry (sorted position, queue or node) per
+ *                               class, INT32_MAX where there is none
+ * A state the step itself produced passes.  Synchronises.  Errors: SIM_EINVAL
+ * (null counts), SIM_ESTATE (no demand), SIM_ENOMEM, SIM_EHIP. */
+int sim_check_state(sim_t* sim, int64_t* counts, int32_t* first);
 
 /* Start a differentiation window at the current step: subsequent sim_step
  * calls save a full-state checkpoint every `checkpoint_every` steps (device

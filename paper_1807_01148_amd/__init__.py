@@ -26,7 +26,11 @@ EXPORTED = ("sim_create", "sim_load_demand", "sim_step", "sim_stats", "sim_read_
             "sim_load_demand_batch", "sim_set_launch", "sim_get_launch", "sim_step_graph", "sim_autotune",
             "sim_set_vehicle_types", "sim_set_control", "sim_state_bytes", "sim_get_state", "sim_set_state",
             "sim_set_stream", "sim_destroy", "sim_last_error", "sim_strerror", "sim_replay",
-            "sim_set_decide_shape", "sim_get_decide_shape", "sim_step_persistent", "sim_reload_routes")
+            "sim_set_decide_shape", "sim_get_decide_shape", "sim_step_persistent", "sim_reload_routes",
+            "sim_check_state")
+# the classes of sim_check_state, in the order of enum sim_check_class
+CHECK_CLASSES = ("count", "key", "edge", "order", "position", "speed", "vid", "duplicate", "type", "route", "next",
+                 "value", "arrived", "queue", "holder")
 KERNELS = ("k_decide", "k_resolve", "k_scan", "k_scatter", "k_place", "k_lanes")
 
 
@@ -125,6 +129,8 @@ def library(path: str = LIB_PATH):
         lib.sim_get_state.restype = ctypes.c_int
         lib.sim_set_state.argtypes = [P, P, ctypes.c_size_t]
         lib.sim_set_state.restype = ctypes.c_int
+        lib.sim_check_state.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+        lib.sim_check_state.restype = ctypes.c_int
         lib.sim_set_stream.argtypes = [P, P]
         lib.sim_set_stream.restype = ctypes.c_int
         lib.sim_destroy.argtypes = [P]
@@ -321,6 +327,17 @@ class Sim:
         another one with the same network, parameters, types and demand)."""
         self.stream.synchronize()
         self._check(self.lib.sim_set_state(self.h, ctypes.c_void_p(img.data_ptr()), img.numel()))
+
+    def check_state(self):
+        """sim_check_state: violations per class of the current state (all 0
+        for a valid one) and the lowest offending entry of each class (None
+        where there is none)."""
+        n = len(CHECK_CLASSES)
+        counts = (ctypes.c_int64 * n)()
+        first = (ctypes.c_int32 * n)()
+        self._check(self.lib.sim_check_state(self.h, counts, first))
+        return ({c: int(counts[k]) for k, c in enumerate(CHECK_CLASSES)},
+                {c: (None if first[k] == 2**31 - 1 else int(first[k])) for k, c in enumerate(CHECK_CLASSES)})
 
     def reload_routes(self, route_ptr, route_edges, total=None):
         """sim_reload_routes: new routes for the same trips from DEVICE memory

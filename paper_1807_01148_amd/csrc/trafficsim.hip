@@ -53,6 +53,7 @@
 #include "common.h"
 #include "step_kernels.h"
 #include "adjoint_kernels.h"
+#include "check_kernels.h"
 
 using namespace tsim;
 
@@ -140,6 +141,11 @@ struct sim_t {
     int* d_rerr = nullptr;       // [2] first bad route, queue count
     void* d_rtmp = nullptr;
     size_t rtmp_bytes = 0;
+    // state check (allocated at the first check): a bit per vehicle id, the
+    // count and the lowest offending entry per class
+    unsigned* d_chk_seen = nullptr;
+    unsigned long long* d_chk_fail = nullptr;
+    int* d_chk_first = nullptr;
     long long host_t = 0;  // steps enqueued so far (selects the buffer parity)
     int grid = 1;
     int grid_small = 1;  // k_scan's persistent blocks
@@ -1465,6 +1471,44 @@ void veh_fields(const Veh& V, const Trips& T, void* f[13]) {
     void* a[13] = {V.key, V.x, V.v, V.edge, T.rcur, V.next, V.lc, T.kin, T.phin, V.vid, V.fuel, V.co, V.ty};
     for (int i = 0; i < 13; ++i) f[i] = a[i];
 }
+
+const char* const kCheckNames[kChkClasses] = {
+    "vehicle count or step", "lane key", "link of the lane key", "order by (lane, position)", "position", "speed",
+    "vehicle id", "duplicate vehicle id", "vehicle type", "route cursor", "next link", "entry fraction, fuel or CO",
+    "arrived vehicle on the road", "departure queue", "stop-node holder"};
+static_assert(kChkClasses == SIM_CHECK_CLASSES, "the check classes are the public ones");
+
+// One pass of k_check_state over a state (c.n vehicles at step t); counts and
+// first receive, per class, the violations and the lowest offending entry.
+// A count or step out of range is reported without reading any array.
+int check_state(sim_t* S, const CheckIn& c, int t, unsigned long long* counts, int* first) {
+    for (int k = 0; k < kChkClasses; ++k) {
+        counts[k] = 0;
+        first[k] = INT32_MAX;
+    }
+    if (c.n < 0 || c.n > S->cap || t < 0) {
+        counts[kChkCount] = 1;
+        first[kChkCount] = 0;
+        return SIM_OK;
+    }
+    const size_t words = ((size_t)S->cap + 31) / 32;
+    if (!S->d_chk_seen && !(dalloc(S, S->d_chk_seen, words) && dalloc(S, S->d_chk_fail, (size_t)kChkClasses) &&
+                            dalloc(S, S->d_chk_first, (size_t)kChkClasses)))
+        return fail(S, SIM_ENOMEM, "state check: device allocation failed");
+    HIPCHECK(S, hipMemsetAsync(S->d_chk_seen, 0, sizeof(unsigned) * words, S->stream));
+    HIPCHECK(S, hipMemsetAsync(S->d_chk_fail, 0, sizeof(unsigned long long) * kChkClasses, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(S->d_chk_first, first, sizeof(int) * kChkClasses, hipMemcpyHostToDevice, S->stream));
+    const long long items = std::max<long long>({(long long)c.n, (long long)S->tr.nq, (long long)S->nn, 1ll});
+    const dim3 g((unsigned)std::min<long long>(kMaxGrid, (items + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_check_state, g, dim3(kBlock), 0, S->stream, c, S->net, S->tr, S->nlanes, S->P.nt,
+                       S->ntrips, S->nn, S->d_chk_seen, S->d_chk_fail, S->d_chk_first);
+    HIPCHECK(S, hipGetLastError());
+    HIPCHECK(S, hipMemcpyAsync(counts, S->d_chk_fail, sizeof(unsigned long long) * kChkClasses,
+                               hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipMemcpyAsync(first, S->d_chk_first, sizeof(int) * kChkClasses, hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
 }  // namespace
 
 int sim_state_bytes(sim_t* S, size_t* bytes) {
@@ -1525,6 +1569,37 @@ int sim_set_state(sim_t* S, const void* image, size_t bytes) {
         h.ntrips != S->ntrips || h.bytes != (long long)L.total || h.step < 0)
         return fail(S, SIM_EINVAL, "not a state image of this simulation");
     const char* img = static_cast<const char*>(image);
+    {  // the image's contents, checked in place before any of it is copied in
+        Counters hc{};
+        HIPCHECK(S, hipMemcpyAsync(&hc, img + L.ctr, sizeof(Counters), hipMemcpyDeviceToHost, S->stream));
+        HIPCHECK(S, hipStreamSynchronize(S->stream));
+        auto at = [&](int f) { return img + L.veh[f]; };
+        CheckIn c;
+        c.key = reinterpret_cast<const int*>(at(0));
+        c.x = reinterpret_cast<const float*>(at(1));
+        c.v = reinterpret_cast<const float*>(at(2));
+        c.edge = reinterpret_cast<const int*>(at(3));
+        c.rcur = reinterpret_cast<const int*>(at(4));
+        c.next = reinterpret_cast<const int*>(at(5));
+        c.phin = reinterpret_cast<const float*>(at(8));
+        c.vid = reinterpret_cast<const int*>(at(9));
+        c.fuel = reinterpret_cast<const float*>(at(10));
+        c.co = reinterpret_cast<const float*>(at(11));
+        c.ty = reinterpret_cast<const unsigned char*>(at(12));
+        c.arrive = reinterpret_cast<const int*>(img + L.trip[1]);
+        c.qstate = reinterpret_cast<const int*>(img + L.q);
+        c.holder = reinterpret_cast<const int*>(img + L.hold);
+        c.n = hc.n;
+        unsigned long long cnt[kChkClasses];
+        int first[kChkClasses];
+        const int rc = check_state(S, c, hc.t, cnt, first);
+        if (rc) return rc;
+        for (int k = 0; k < kChkClasses; ++k)
+            if (cnt[k])
+                return fail(S, SIM_EINVAL, std::string("state image fails validation: ") + kCheckNames[k] + " (" +
+                                               std::to_string(cnt[k]) + " cases, first at " +
+                                               std::to_string(first[k]) + ")");
+    }
     const hipMemcpyKind k = hipMemcpyDeviceToDevice;
     const size_t n = (size_t)S->cap;
     const int p = (int)(h.step & 1);
@@ -1543,6 +1618,40 @@ int sim_set_state(sim_t* S, const void* image, size_t bytes) {
     int rc = reindex(S, S->buf[p], S->s, S->ctr);
     if (rc) return rc;
     HIPCHECK(S, hipStreamSynchronize(S->stream));
+    return SIM_OK;
+}
+
+int sim_check_state(sim_t* S, int64_t* counts, int32_t* first) {
+    if (!S || !counts) return SIM_EINVAL;
+    if (!S->loaded) return fail(S, SIM_ESTATE, "no demand loaded");
+    const Veh& V = S->buf[S->host_t & 1];
+    Counters hc{};
+    HIPCHECK(S, hipMemcpyAsync(&hc, S->ctr, sizeof(Counters), hipMemcpyDeviceToHost, S->stream));
+    HIPCHECK(S, hipStreamSynchronize(S->stream));
+    CheckIn c;
+    c.key = V.key;
+    c.x = V.x;
+    c.v = V.v;
+    c.edge = V.edge;
+    c.next = V.next;
+    c.vid = V.vid;
+    c.fuel = V.fuel;
+    c.co = V.co;
+    c.ty = V.ty;
+    c.rcur = S->tr.rcur;
+    c.phin = S->tr.phin;
+    c.arrive = S->tr.arrive_step;
+    c.qstate = S->qstate;
+    c.holder = S->s.holder;
+    c.n = hc.n;
+    unsigned long long cnt[kChkClasses];
+    int fst[kChkClasses];
+    const int rc = check_state(S, c, hc.t, cnt, fst);
+    if (rc) return rc;
+    for (int k = 0; k < kChkClasses; ++k) {
+        counts[k] = (int64_t)cnt[k];
+        if (first) first[k] = fst[k];
+    }
     return SIM_OK;
 }
 

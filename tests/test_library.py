@@ -54,3 +54,13 @@ def test_strerror_codes():
     assert lib.sim_strerror(0) == b"ok"
     assert lib.sim_strerror(P.SIM_EROUTE) == b"invalid route"
     assert lib.sim_strerror(12345) == b"unknown error"
+
+
+def test_check_classes_match_the_header():
+    import paper_1807_01148_amd as P
+    text = open(os.path.join(INCLUDE, "trafficsim.h")).read()
+    body = re.search(r"enum sim_check_class \{(.*?)\};", text, flags=re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"SIM_CHECK_([A-Z]+)", body)
+    assert names[-1] == "CLASSES"
+    assert tuple(n.lower() for n in names[:-1]) == P.CHECK_CLASSES
