@@ -29,16 +29,21 @@ __device__ __forceinline__ int lb_x(const float* __restrict__ x, int lo, int hi,
 // k_decide
 // ---------------------------------------------------------------------------
 // A block takes the sorted entries in tiles (of its threads times the entries
-// per thread).  The tile and one entry on either side sit in LDS, slot s
-// holding entry b0 - 1 + s: the vehicle
+// per thread).  The tile and H entries on either side sit in LDS, slot s
+// holding entry b0 - H + s: the vehicle
 // ahead of an entry in its lane, the one behind it, and the run of a
 // neighbouring lane (the lanes of a link are consecutive keys, so their runs
-// are usually in the same tile) are then LDS reads.  A slot before the first
-// entry holds key -1 and a slot past the last entry key INT_MAX, so the keys
-// stay sorted over the whole window.
-template <int NS>
+// are next to the entry's own) are then LDS reads.  The H entries beyond each
+// end keep the runs that cross the tile's ends in LDS too: without them the
+// waves at both ends of every tile would search such runs in global memory,
+// and the block, which waits for its slowest wave, with them.  A slot before
+// the first entry holds key -1 and a slot past the last entry key INT_MAX, so
+// the keys stay sorted over the whole window.
+constexpr int kTileHalo = 32;
+template <int NS, int H>
 struct Tile {
     static constexpr int kSlots = NS;
+    static constexpr int kHalo = H;
     int key[NS];
     float x[NS];
     float v[NS];
@@ -134,7 +139,7 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
     return L;
 }
 
-// The step decision of entry i (tile slot t + 1): leader, IDM, move, crossing
+// The step decision of entry i (tile slot t_slot): leader, IDM, move, crossing
 // claim or arrival.  Returns true when the vehicle is to be evaluated for a
 // lane change, with what that needs in o.
 template <class TileT, class StageT>
@@ -305,7 +310,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         // the run from the lane index; searched in LDS when the tile holds it
         int tlo, thi;
         const bool occ = lane_range(s.lanes, kt, ep, tlo, thi);
-        const int w0 = b0 - 1;  // the entry in slot 0
+        const int w0 = b0 - TileT::kHalo;  // the entry in slot 0
         if (occ && tlo >= w0 && thi <= w0 + TileT::kSlots - 1) {
             const int ra = tlo - w0, rb = thi - w0;
             int a = ra, c = rb + 1;  // first slot in the run with x > own x
@@ -478,7 +483,8 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
         }
         return;
     }
-    __shared__ Tile<kTile + 2> T;
+    static_assert(BS >= 2 * kTileHalo, "one thread per halo entry");
+    __shared__ Tile<kTile + 2 * kTileHalo, kTileHalo> T;
     __shared__ ClaimStage<2 * kTile> CS;
     // XCD-aware mapping: the vehicle blocks (a multiple of kSeg) of XCD q take
     // the q-th eighth of the sorted entries, tiles in order, so that the link
@@ -502,13 +508,13 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
         const int c = s_c;
         if (c >= c_end) break;
         const int b0 = c * kTile;
-        // the tile and its two neighbours into LDS; the rest of the own
-        // entries into registers
+        // the tile and the entries on either side into LDS; the rest of the
+        // own entries into registers
         int e[R], nx[R], vid[R], lcs[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = b0 + r * BS + threadIdx.x;
-            const int ts = r * BS + threadIdx.x + 1;
+            const int ts = r * BS + threadIdx.x + kTileHalo;
             e[r] = 0; nx[r] = -1; vid[r] = 0; lcs[r] = 0;
             if (i < N) {
                 T.key[ts] = in.key[i];
@@ -526,26 +532,22 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
                 T.ty[ts] = 0;
             }
         }
-        if (threadIdx.x == 0) {
-            const bool has = b0 > 0;
-            T.key[0] = has ? in.key[b0 - 1] : -1;
-            T.x[0] = has ? in.x[b0 - 1] : 0.0f;
-            T.v[0] = has ? in.v[b0 - 1] : 0.0f;
-            T.ty[0] = has ? (int)in.ty[b0 - 1] : 0;
-        }
-        if (threadIdx.x == BS - 1) {
-            const int j = b0 + kTile;
-            const bool has = j < N;
-            T.key[kTile + 1] = has ? in.key[j] : kKeyPast;
-            T.x[kTile + 1] = has ? in.x[j] : 0.0f;
-            T.v[kTile + 1] = has ? in.v[j] : 0.0f;
-            T.ty[kTile + 1] = has ? (int)in.ty[j] : 0;
+        if (threadIdx.x < 2 * kTileHalo) {  // slots [0, H) before the tile, [H + kTile, 2 H + kTile) after it
+            const int h = threadIdx.x;
+            const bool before = h < kTileHalo;
+            const int j = before ? b0 - kTileHalo + h : b0 + kTile + (h - kTileHalo);
+            const int ts = before ? h : kTile + h;
+            const bool has = j >= 0 && j < N;
+            T.key[ts] = has ? in.key[j] : (before ? -1 : kKeyPast);
+            T.x[ts] = has ? in.x[j] : 0.0f;
+            T.v[ts] = has ? in.v[j] : 0.0f;
+            T.ty[ts] = has ? (int)in.ty[j] : 0;
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = b0 + r * BS + threadIdx.x;
-            const int ts = r * BS + threadIdx.x + 1;
+            const int ts = r * BS + threadIdx.x + kTileHalo;
             if (i < N) {
                 Own o;
                 if (decide_vehicle(P, net, tr, in, s, tp, T, CS, ts, N, t, ep, tag, i, e[r], nx[r], vid[r], lcs[r],
