@@ -460,11 +460,18 @@ __device__ __forceinline__ unsigned long long epoch_tag(unsigned epoch) {
 
 // a per-type constant, picked from registers (the table lives in the kernel
 // arguments; indexing it with a per-lane type would be a memory read)
+// A per-type constant of the parameters (uniform over the launch), chosen by
+// selects between the four values held in scalar registers.  The empty asm
+// hides that the values are the array's elements: otherwise the compiler
+// folds the selects into one vector load at a type-dependent address in the
+// kernel arguments, a memory round trip after the type is known.
 __device__ __forceinline__ float by_type(const float (&a)[4], int ty) {
-    float r = a[0];
-    r = ty == 1 ? a[1] : r;
-    r = ty == 2 ? a[2] : r;
-    r = ty == 3 ? a[3] : r;
+    float a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+    asm("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3));
+    float r = a0;
+    r = ty == 1 ? a1 : r;
+    r = ty == 2 ? a2 : r;
+    r = ty == 3 ? a3 : r;
     return r;
 }
 
