@@ -587,6 +587,8 @@ __global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh 
 // ---------------------------------------------------------------------------
 // k_resolve
 // ---------------------------------------------------------------------------
+constexpr int kCellBatch = 8;
+
 __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                              const Scratch& s, const Tape& tp, Counters* ctr, int bid, int nblk) {
     const int t = ctr->t;
@@ -619,32 +621,60 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
         const int sx = src >= 0 ? src : 0;
         const int se = in.edge[sx], skin = tr.kin[vid];
         const float sphin = tr.phin[vid];
-        // a crossing's or departure's place in its route after the move
-        const int rc = kind == kCross ? tr.rcur[vid] + 1 : tr.rbeg[vid];
-        const int rend = tr.rend[vid];
-        const int nn = (kind != kChange && rc + 1 < rend) ? tr.route_edges[rc + 1] : -1;
-        // ownership of every claimed cell (all read at once: no early exit)
+        const int rcu = tr.rcur[vid], rbg = tr.rbeg[vid], rend = tr.rend[vid];
+        // ownership of every claimed cell, kCellBatch cells at a time with all
+        // the loads of a batch issued before any is compared (a car's claim
+        // covers 8 cells: one round trip, not one per cell).  The first batch
+        // is read unconditionally, with the reads beyond the last cell (or of
+        // a claim that covers none) kept on a valid cell of the lane and not
+        // counted, so that its reads go out with the others above
         const unsigned long long* cell = s.cells + cb;
         const unsigned long long mine = tag | (unsigned)vid;
         bool win = true;
-        for (int c = clo; c <= chi; ++c) win &= cell[c] == mine;
+        int c0 = clo;
+        do {
+            unsigned long long w[kCellBatch];
+#pragma unroll
+            for (int q = 0; q < kCellBatch; ++q) {
+                const int c = c0 + q <= chi ? c0 + q : chi;
+                w[q] = cell[c > 0 ? c : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < kCellBatch; ++q) win &= c0 + q > chi || w[q] == mine;
+            c0 += kCellBatch;
+        } while (c0 <= chi);
+        // a crossing's or departure's place in its route after the move (both
+        // cursors read with the rest; the kind picks one), and the route's
+        // link after it, read for every kind at an index kept inside the route
+        // and kept for a crossing or a departure that has one
+        const int rc = kind == kCross ? rcu + 1 : rbg;
+        int rn = tr.route_edges[rc + 1 < rend ? rc + 1 : rend - 1];
+        // the claim's gap in the sorted order: inside its lane's run if the
+        // lane is occupied, else before the first entry of a later lane; found
+        // for every claim, won or lost, so that the search overlaps the read
+        // above.  The empty asm after it keeps that read in its place: the
+        // compiler would otherwise move it, and the route end's read with it,
+        // into a branch of their own
+        const int p = occ ? lb_x(in.x, lo, hi + 1, cX) : lb_key(in.key, kb0, kb1, key);
+        asm("" : "+v"(rn));
+        const int nn = (kind != kChange && rc + 1 < rend) ? rn : -1;
         if (tp.on && src >= 0) {
             if (kind == kCross) tp.mode[src] = win ? kModeCross : kModeYield;
             else tp.mode[src] = win ? kModeChange : kModeStay;
         }
         if (win) {
             if (src >= 0) s.stay[src] = 0;
+            // its place in its gap and its slot in the list of movers, whose
+            // two atomics are waited for together
+            const int slot = atomicAdd(&s.mcnt[p], 1);
             const int m = seg * s.cl_seg + wave_slot(s.mvcnt + seg * kSegStride);
             s.mv_claim[m] = ci;
             s.mv_src[m] = src;
             s.mv_vid[m] = vid;
             s.mv_rc[m] = rc;
             s.mv_nx[m] = nn;
-            // its gap in the sorted order: inside its lane's run if the lane is
-            // occupied, else before the first entry of a later lane
-            const int p = occ ? lb_x(in.x, lo, hi + 1, cX) : lb_key(in.key, kb0, kb1, key);
             s.mv_p[m] = p;
-            s.mv_slot[m] = atomicAdd(&s.mcnt[p], 1);
+            s.mv_slot[m] = slot;
             if (kind == kCross) {
                 record_exit(P, s, se, skin, sphin, cf, t);
                 if (net.ctrl) {  // reaching the next link frees a stop node
@@ -654,7 +684,7 @@ __device__ __forceinline__ void resolve_body(const Params& P, const Net& net, co
             }
             if (kind == kInsert) {
                 tr.depart_actual[vid] = t + 1;
-                tr.qhead[-2 - src] += 1;  // the queue's head has left (one winner per queue)
+                atomicAdd(tr.qhead + (-2 - src), 1);  // the queue's head has left (one winner per queue)
                 departed += 1;
             }
         } else {
@@ -929,10 +959,19 @@ __device__ __forceinline__ void place_body(const Params& P, const Trips& tr, con
         const int vty = tr.vtype[vid];
         const int b = (cp ^ (cp >> 31)) - g;
         int r = 0;
-        if (g > 1) {
-            for (int q = 0; q < g; ++q) {
-                int kq = s.grp_key[b + q];
-                if (kq < key || (kq == key && s.grp_X[b + q] < X)) ++r;
+        if (g > 1) {  // four members of the gap at a time, their reads issued together
+            for (int q0 = 0; q0 < g; q0 += 4) {
+                int kq[4];
+                float xq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int at = b + (q0 + q < g ? q0 + q : g - 1);
+                    kq[q] = s.grp_key[at];
+                    xq[q] = s.grp_X[at];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q0 + q < g && (kq[q] < key || (kq[q] == key && xq[q] < X))) ++r;
             }
         }
         const int j = b + r;
@@ -990,11 +1029,20 @@ __device__ __forceinline__ void lanes_body(const Params& P, const Net& net, cons
         for (int b = bid * kBlock + threadIdx.x; b <= s.nlblk; b += nblk * kBlock)
             s.lblk[b] = lb_key(buf.key, 0, N, b << kLaneBlkLog);
     for (int j = bid * kBlock + threadIdx.x; j <= N; j += nblk * kBlock) {
+        // the entry and its neighbours' lanes, its type, position and speed,
+        // all read at once first (at indices kept inside the arrays, whose
+        // values are not used where the index was moved)
+        const int jc = j < N ? j : (N > 0 ? N - 1 : 0);
+        const int k = buf.key[jc];
+        const int kp = buf.key[j > 0 ? j - 1 : 0];
+        const int kn = buf.key[j + 1 < N ? j + 1 : jc];
+        const int tyj = buf.ty[jc];
+        const float xj = buf.x[jc], vj = buf.v[jc];
         // lane blocks from the one after entry j-1's to entry j's begin at j;
         // a long run of them (empty lanes) is written by the whole wave, so no
         // single thread serialises it
-        const int b0 = sparse ? 1 : (j == 0 ? 0 : (buf.key[j - 1] >> kLaneBlkLog) + 1);
-        const int b1 = sparse ? 0 : (j == N ? s.nlblk : (buf.key[j] >> kLaneBlkLog));
+        const int b0 = sparse ? 1 : (j == 0 ? 0 : (kp >> kLaneBlkLog) + 1);
+        const int b1 = sparse ? 0 : (j == N ? s.nlblk : (k >> kLaneBlkLog));
         const bool longrun = b1 - b0 >= kWave / 2;
         if (!longrun)
             for (int b = b0; b <= b1; ++b) s.lblk[b] = j;
@@ -1011,12 +1059,6 @@ __device__ __forceinline__ void lanes_body(const Params& P, const Net& net, cons
             }
         }
         if (j == N) continue;
-        // the entry and its neighbours' lanes, read before any branch
-        const int k = buf.key[j];
-        const int kp = buf.key[j > 0 ? j - 1 : j];
-        const int kn = buf.key[j + 1 < N ? j + 1 : j];
-        const int tyj = buf.ty[j];
-        const float xj = buf.x[j], vj = buf.v[j];
         if (net.ctrl) {  // waiting at the line of a free stop node: ask to be admitted next step
             const int e = buf.edge[j];
             const int h = net.head[e];
