@@ -142,7 +142,7 @@ __device__ __forceinline__ Lead own_leader(const Params& P, const Scratch& s, un
 // The step decision of entry i (tile slot t_slot): leader, IDM, move, crossing
 // claim or arrival.  Returns true when the vehicle is to be evaluated for a
 // lane change, with what that needs in o.
-template <class TileT, class StageT>
+template <bool kFull, class TileT, class StageT>
 __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr, const Veh& in, const Scratch& s,
                                const Tape& tp, const TileT& T, StageT& CS, int t_slot, int N, int t, unsigned ep,
                                unsigned long long tag, int i, int e, int nx, int vid, int lcs, int& clamps,
@@ -169,7 +169,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     const int nlanes = D.lanes_m & 0xFFFF;
     const int l = k - lb;
 
-    const bool held = movement_held(P, net, s, e, nx, vid, t, tag);
+    const bool held = kFull && movement_held(P, net, s, e, nx, vid, t, tag);
     Lead L = own_leader(P, s, ep, i, N, k, x, len, l, held, nx, E2, ka, xa, va, tya);
     int own_fl = lead_flags(L);
     const float ac = idm_acc_fl(P, A, Tg, kab, iv, v, L, own_fl);
@@ -178,7 +178,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     clamps += clamp_to_leader_fl(L, dx, vn, own_fl);
     const float xs = x + dx;
     // utilization / speed sample of the state at t (Sec. 6.4)
-    if (s.samp_every > 0 && t % s.samp_every == 0) {
+    if (kFull && s.samp_every > 0 && t % s.samp_every == 0) {
         const int g = (t / s.samp_every) / s.samp_group;
         if (g < s.samp_max) {
             const size_t so = (size_t)g * (size_t)net.ne + (size_t)e;
@@ -186,7 +186,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
             atomicAdd(s.samp_spd + so, (unsigned long long)(long long)rintf(v * 1e6f));
         }
     }
-    if (tp.on) {
+    if (kFull && tp.on) {
         tp.x[i] = x;
         tp.v[i] = v;
         tp.vid[i] = vid;
@@ -202,7 +202,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
         float fq = (len - x) / dx;
         if (!(fq < 1.0f)) own_fl |= kFFOne;
         float f = dx > 0.0f ? fmn(fq, 1.0f) : 0.0f;
-        if (tp.on) {
+        if (kFull && tp.on) {
             tp.flags[i] = (unsigned short)own_fl;
             tp.mode[i] = nx < 0 ? kModeArrive : kModeCross;
         }
@@ -229,7 +229,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
     s.xs[i] = xs;
     s.vs[i] = vn;
     s.stay[i] = 1;
-    if (tp.on) tp.flags[i] = (unsigned short)own_fl;
+    if (kFull && tp.on) tp.flags[i] = (unsigned short)own_fl;
 
     // lane change (Sec. 6.3.2): a vehicle past the cool-down on a multi-lane
     // link that is not on its entry cells
@@ -248,7 +248,7 @@ __device__ bool decide_vehicle(const Params& P, const Net& net, const Trips& tr,
 // claims its cells in the target lane.  The follower comes from LDS; a
 // target lane's run from the lane index (one record read), and its leader and
 // lag from LDS when the tile holds the run, else from the sorted arrays.
-template <class TileT, class StageT>
+template <bool kFull, class TileT, class StageT>
 __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, const Scratch& s, const Tape& tp,
                                const TileT& T, StageT& CS, int t_slot, int b0, unsigned ep, const Own& o) {
     const int i = o.i, k = o.k, e = o.e, nx = o.nx, ty = o.ty, vid = o.vid, l = o.l;
@@ -405,7 +405,7 @@ __device__ bool change_vehicle(const Params& P, const Net& net, const Veh& in, c
         }
     }
     if (best >= 0) {
-        if (tp.on) {
+        if (kFull && tp.on) {
             tp.mode[i] = kModeChange;
             tp.cflags[i] = (unsigned short)best_fl;
             tp.clead[i] = best_lead;
@@ -460,8 +460,12 @@ __device__ void decide_queue(const Params& P, const Net& net, const Trips& tr, c
 // entries, R per thread: the step decision of every vehicle of a tile, then,
 // for the vehicles it lists, the lane-change evaluation in the same thread.
 // The two parts share nothing but the claim list.  (BS, R) is a launch shape
-// the autotuner picks; results do not depend on it.
-template <int BS, int R>
+// the autotuner picks; results do not depend on it.  With kFull false the
+// event tape, the utilization sampler and intersection control are compiled
+// out, for launches where none of them is on (the host picks): their code
+// and the arguments it keeps in registers cost the plain step spills and
+// instructions.
+template <int BS, int R, bool kFull>
 __device__ __forceinline__ void decide_body(const Params& P, const Net& net, const Trips& tr, const Veh& in,
                                             const Scratch& s, const Tape& tp, Counters* ctr, int qblocks, int bid,
                                             int nblk) {
@@ -495,7 +499,7 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
     const int nch = (N + kTile - 1) / kTile;
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
     int clamps = 0, arrivals = 0, listed = 0, claims = 0;
-    if (tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
+    if (kFull && tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
     // the tiles of the eighth are taken in order from a counter of its own, so
     // that a block that meets fast tiles takes more of them
     __shared__ int s_c;
@@ -550,10 +554,10 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
             const int ts = r * BS + threadIdx.x + kTileHalo;
             if (i < N) {
                 Own o;
-                if (decide_vehicle(P, net, tr, in, s, tp, T, CS, ts, N, t, ep, tag, i, e[r], nx[r], vid[r], lcs[r],
+                if (decide_vehicle<kFull>(P, net, tr, in, s, tp, T, CS, ts, N, t, ep, tag, i, e[r], nx[r], vid[r], lcs[r],
                                    clamps, arrivals, o)) {
                     listed += 1;
-                    claims += change_vehicle(P, net, in, s, tp, T, CS, ts, b0, ep, o) ? 1 : 0;
+                    claims += change_vehicle<kFull>(P, net, in, s, tp, T, CS, ts, b0, ep, o) ? 1 : 0;
                 }
             }
         }
@@ -578,10 +582,10 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
     }
 }
 
-template <int BS, int R>
+template <int BS, int R, bool kFull>
 __global__ __launch_bounds__(BS) void k_decide(Params P, Net net, Trips tr, Veh in, Scratch s, Tape tp,
                                                Counters* ctr, int qblocks) {
-    decide_body<BS, R>(P, net, tr, in, s, tp, ctr, qblocks, (int)blockIdx.x, (int)gridDim.x);
+    decide_body<BS, R, kFull>(P, net, tr, in, s, tp, ctr, qblocks, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,7 +1178,7 @@ __global__ __launch_bounds__(kBlock) void k_steps(Params P, Net net, Trips tr, V
         const bool odd = ((parity + k) & 1) != 0;
         const Veh& in = odd ? b1 : b0;
         const Veh& out = odd ? b0 : b1;
-        for (int vb = blockIdx.x; vb < qb + g8; vb += nb) decide_body<kBlock, R>(P, net, tr, in, s, off, ctr, qb, vb, qb + g8);
+        for (int vb = blockIdx.x; vb < qb + g8; vb += nb) decide_body<kBlock, R, true>(P, net, tr, in, s, off, ctr, qb, vb, qb + g8);
         if (grid_sync(gs, nb, spin_limit)) return;
         for (int vb = blockIdx.x; vb < g8; vb += nb) resolve_body(P, net, tr, in, s, off, ctr, vb, g8);
         if (grid_sync(gs, nb, spin_limit)) return;

@@ -359,14 +359,22 @@ int launch_step(sim_t* S, const Veh& in, const Veh& out, const Trips& tr, const 
     // departure queues first, in a multiple of kSeg blocks, then the vehicles
     const int qb = tr.nq > 0 ? (S->grid_q + kSeg - 1) / kSeg * kSeg : 0;
     const dim3 gd(qb + g8.x);
-    switch (S->dshape) {
-        case 1: STEP_LAUNCH_B(0, (k_decide<256, 2>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
-        case 2: STEP_LAUNCH_B(0, (k_decide<128, 1>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
-        case 3: STEP_LAUNCH_B(0, (k_decide<128, 2>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
-        case 4: STEP_LAUNCH_B(0, (k_decide<512, 1>), gd, dim3(512), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
-        case 5: STEP_LAUNCH_B(0, (k_decide<256, 4>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
-        default: STEP_LAUNCH_B(0, (k_decide<256, 1>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break;
+    // the decide kernel with the tape, sampler and control code only when one
+    // of them is on
+#define DECIDE_SHAPES(F)                                                                                          \
+    switch (S->dshape) {                                                                                          \
+        case 1: STEP_LAUNCH_B(0, (k_decide<256, 2, F>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
+        case 2: STEP_LAUNCH_B(0, (k_decide<128, 1, F>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
+        case 3: STEP_LAUNCH_B(0, (k_decide<128, 2, F>), gd, dim3(128), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
+        case 4: STEP_LAUNCH_B(0, (k_decide<512, 1, F>), gd, dim3(512), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
+        case 5: STEP_LAUNCH_B(0, (k_decide<256, 4, F>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
+        default: STEP_LAUNCH_B(0, (k_decide<256, 1, F>), gd, dim3(256), S->P, S->net, tr, in, sc, tp, ctr, qb); break; \
     }
+    if (tp.on || sc.samp_every > 0 || S->net.ctrl)
+        DECIDE_SHAPES(true)
+    else
+        DECIDE_SHAPES(false)
+#undef DECIDE_SHAPES
     STEP_LAUNCH(1, k_resolve, g8, S->P, S->net, tr, in, sc, tp, ctr);
     STEP_LAUNCH(2, k_scan, gs, sc, ctr);
     STEP_LAUNCH(3, k_scatter, g8, S->P, in, out, sc, tp, ctr);
