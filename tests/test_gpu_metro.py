@@ -32,11 +32,12 @@ def metro():
 
 
 def cached_shape():
-    import torch
+    """The launch shape the benchmark takes from the tuned-shape cache."""
+    from paper_1807_01148_amd import ensemble as E
     with open(os.path.join(ROOT, "paper_1807_01148_amd", "autotune_cache.json")) as f:
         db = json.load(f)
-    hit = db.get("%s|metro" % torch.cuda.get_device_name(0))
-    return (hit["grid"], hit["grid_small"]) if hit else (1536, 192)
+    hit = db.get("%s|metro" % E.device_key(0))
+    return hit or {"grid": 1536, "grid_small": 192, "decide_block": 256, "decide_per_thread": 1}
 
 
 def test_benchmark_configuration_equals_plain_steps_at_full_size(metro):
@@ -44,7 +45,7 @@ def test_benchmark_configuration_equals_plain_steps_at_full_size(metro):
     from paper_1807_01148_amd import ensemble as E
     steps = 7200
     bench = P.Sim(metro)
-    E.set_launch(bench, *cached_shape())
+    E.apply_shape(bench, cached_shape())
     E.step_graph(bench, steps, 60)
     vb, cb, eb, tb = bench.vehicles(), bench.counters(), bench.edge_stats(), bench.trips()
     bench.close()
