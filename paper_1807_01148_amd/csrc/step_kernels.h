@@ -500,14 +500,18 @@ __device__ __forceinline__ void decide_body(const Params& P, const Net& net, con
     const int c_end = (int)(((long long)nch * (q + 1)) / kSeg);
     int clamps = 0, arrivals = 0, listed = 0, claims = 0;
     if (kFull && tp.on && vb == 0 && threadIdx.x == 0) *tp.n = N;
-    // the tiles of the eighth are taken in order from a counter of its own, so
-    // that a block that meets fast tiles takes more of them
+    // a block's first tile of the eighth is the one its index names (no
+    // atomic: a block without one leaves at once); the tiles after the first
+    // of every block are taken in order from a counter of the eighth, so that
+    // a block that meets fast tiles takes more of them
     __shared__ int s_c;
     const int c_beg = (int)(((long long)nch * q) / kSeg);
+    const int nbs = (nblk - qblocks) / kSeg;  // vehicle blocks of the eighth
     if (threadIdx.x == 0) CS.n = 0;
-    for (;;) {
+    for (int it = 0;; ++it) {
         __syncthreads();  // s_c is read
-        if (threadIdx.x == 0) s_c = c_beg + atomicAdd(s.tcnt + q * kSegStride, 1);
+        if (threadIdx.x == 0)
+            s_c = c_beg + (it == 0 ? vb / kSeg : nbs + atomicAdd(s.tcnt + q * kSegStride, 1));
         __syncthreads();
         const int c = s_c;
         if (c >= c_end) break;
